@@ -1,0 +1,208 @@
+/*
+ * qbvm.h - C interface of the MI355X (gfx950) PinT quasi-boundary value solver.
+ *
+ * Method: J. Liu, "Fast parallel-in-time quasi-boundary value methods for
+ * backward heat conduction problems" (arXiv 2107.06381).  Given the noisy final
+ * state g_delta of the heat equation z_t = Lap z on Omega=(0,L)^d (d = 1, 2, 3,
+ * homogeneous Dirichlet data, Section 1), the library solves the regularised
+ * all-at-once system of Section 3:
+ *
+ *   PinT-QBVM  (Section 3.1, QBVM_PQ): omega = -1/alpha,   f0 = g_delta/(tau alpha)
+ *   PinT-MQBVM (Section 3.2, QBVM_PM): omega = -tau/alpha, f0 = g_delta/alpha
+ *     (1/tau) y^0 - Lap_h y^0 - (omega/tau) y^N = f0
+ *     (1/tau) y^t - Lap_h y^t - (1/tau) y^{t-1} = 0,  t = 1..N
+ *
+ * with the (2d+1)-point Dirichlet Laplacian Lap_h on m interior points per
+ * dimension (h = L/(m+1)), backward Euler with tau = T/n, N = n and
+ * N_t = n+1 time levels.  The solve follows the diagonalisation of Section 3.3
+ * (eq. "3step"): omega-power scaling and a DFT along time (Step a), N_t
+ * independent complex-shifted spatial solves (Step b), and the inverse DFT with
+ * the inverse scaling (Step c).
+ *
+ * Conventions shared by every call:
+ *  - All solve data are IEEE double.  Grid functions are stored in C order with
+ *    x_1 fastest: index (x_d, ..., x_1); full solutions are y[t][x_d]..[x_1],
+ *    t = 0..n, i.e. (n+1) * m^d doubles.
+ *  - Pointers documented as DEVICE point to memory on the GPU the plan was made
+ *    on; HOST pointers are ordinary CPU memory.  The caller owns every buffer it
+ *    passes; the library owns only what a plan allocates.
+ *  - Return value 0 (QBVM_OK) on success, a negative QBVM_E* code otherwise.  No
+ *    C++ exception crosses this interface.  After QBVM_EHIP the HIP error text is
+ *    available from qbvm_last_error().
+ *  - A plan is bound to one HIP stream and is not thread safe.  Solves are
+ *    enqueued asynchronously on that stream unless stated otherwise.
+ *  - Input and output buffers must not alias.
+ */
+#ifndef QBVM_H
+#define QBVM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QBVM_OK            0
+#define QBVM_EINVAL       -1  /* invalid argument (sizes, alpha <= 0, NaN, null) */
+#define QBVM_ENOMEM       -2  /* device or host allocation failed */
+#define QBVM_EHIP         -3  /* a HIP runtime call failed */
+#define QBVM_ENOROOT      -4  /* discrepancy principle has no root in the bracket */
+#define QBVM_EUNSUPPORTED -5  /* size outside what the kernels support */
+#define QBVM_ENOMODEL     -6  /* learned alpha requested but no model was set */
+
+/* Regularisation variant: PinT-QBVM (Section 3.1) or PinT-MQBVM (Section 3.2). */
+#define QBVM_PQ 0
+#define QBVM_PM 1
+
+/* What qbvm_solve writes to y. */
+#define QBVM_OUT_ALL 0 /* every level: (n+1) * m^d doubles, y[t][x_d]..[x_1]  */
+#define QBVM_OUT_Y0  1 /* the reconstruction y^0 only: m^d doubles (Section 5) */
+#define QBVM_OUT_YN  2 /* the final level y^N only: m^d doubles              */
+
+/* Size limits of this build. */
+#define QBVM_MAX_NT      4096  /* n + 1 */
+#define QBVM_MAX_M_1D    4095
+#define QBVM_MAX_M_2D    2047
+#define QBVM_MAX_M_3D    511
+
+/* Number of floats in a learned-alpha model blob (see qbvm_set_alpha_model). */
+#define QBVM_MLP_PARAMS   6401
+#define QBVM_MODEL_FLOATS 6469
+#define QBVM_NFEAT        33
+
+typedef struct qbvm_plan_s* qbvm_plan_t;
+
+/* Discretisation (Section 2): d in {1,2,3}; m >= 1 interior points per
+ * dimension; n >= 1 backward-Euler steps; domain length L > 0; final time T > 0. */
+typedef struct {
+  int d;
+  int m;
+  int n;
+  double L;
+  double T;
+} qbvm_grid;
+
+/* Options of qbvm_choose_alpha (an addition; the paper fixes alpha a priori). */
+typedef struct {
+  double tau_dp;    /* discrepancy factor: seek D(alpha) = tau_dp * delta (e.g. 1.1) */
+  double log10_lo;  /* bisection bracket on log10(alpha), e.g. -20 */
+  double log10_hi;  /* e.g. 0 */
+  int steps;        /* bisection halvings, e.g. 30 */
+  int use_learned;  /* 1: try the plan's network first, bisection on a window miss */
+  double win_lo;    /* accept the predicted alpha if win_lo <= D/delta <= win_hi */
+  double win_hi;
+} qbvm_alpha_opts;
+
+typedef struct {
+  double discrepancy;    /* D(alpha_out) in the h^{d/2}-weighted 2-norm */
+  double alpha_learned;  /* network prediction (0 if not used) */
+  int iterations;        /* discrepancy evaluations performed */
+  int used_fallback;     /* 1 if the prediction missed the window and bisection ran */
+  int bracket_hit;       /* 1 if the root lies outside the bracket (end returned) */
+} qbvm_alpha_info;
+
+/* ---------------------------------------------------------------- plans ---- */
+
+/* Create a plan for one grid, bound to hip_stream (a hipStream_t; NULL = the
+ * default stream) on the current HIP device.  Builds the FFT factorisations
+ * along time (length n+1) and for the sine transforms (length 2(m+1)), uploads
+ * twiddle, Rader/Bluestein and eigenvalue tables, and allocates the workspace.
+ * *out receives the plan; on error *out is NULL. */
+int qbvm_plan(qbvm_plan_t* out, const qbvm_grid* grid, void* hip_stream);
+
+/* Release a plan and its device memory (waits for its stream).  NULL is a no-op. */
+void qbvm_plan_destroy(qbvm_plan_t p);
+
+/* Re-bind a plan to another stream. */
+int qbvm_plan_set_stream(qbvm_plan_t p, void* hip_stream);
+
+/* Device bytes held by the plan (tables + workspace). */
+long long qbvm_plan_workspace_bytes(qbvm_plan_t p);
+
+/* -------------------------------------------------------------- solving ---- */
+
+/* Solve one PinT system (Sections 3.1-3.3).  g_delta: DEVICE, m^d doubles.
+ * y: DEVICE, (n+1) * m^d doubles for QBVM_OUT_ALL, m^d for QBVM_OUT_Y0/YN.
+ * alpha > 0; variant QBVM_PQ or QBVM_PM.  Asynchronous on the plan's stream. */
+int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta,
+               double* y, int output);
+
+/* Solve `count` independent instances of possibly different grids in one
+ * batched launch sequence (an addition; not in the paper).  All arrays of
+ * length `count` are HOST arrays; g_deltas[i] and ys[i] are DEVICE pointers
+ * with the sizes qbvm_solve documents for grids[i] and outputs[i].  Plans,
+ * descriptor tables and a captured HIP graph are cached by the set of grids;
+ * the call is asynchronous on hip_stream (the descriptor upload is ordered on it). */
+int qbvm_solve_batched(int count, const qbvm_grid* grids, const double* alphas,
+                       const int* variants, const double* const* g_deltas,
+                       double* const* ys, const int* outputs, void* hip_stream);
+
+/* Free every cached batched plan and graph. */
+void qbvm_batched_cache_clear(void);
+
+/* ---------------------------------------------- regularisation parameter ---- */
+
+/* D(alpha) = ||y^N(alpha) - g_delta||_h, ||v||_h = h^{d/2} ||v||_2 (the discrete
+ * L2 norm of Section 5), with y^N computed by Step (c) at the last level only.
+ * g_delta: DEVICE.  *D_out: HOST.  Synchronous. */
+int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_delta,
+                     double* D_out);
+
+/* Choose alpha by the discrepancy principle D(alpha) = tau_dp * delta (an
+ * addition; the paper uses alpha = delta or tau*delta a priori, Section 5).
+ * With opts->use_learned the plan's network predicts log10 alpha from the sine
+ * spectrum of g_delta and delta; the prediction is accepted if
+ * win_lo <= D/delta <= win_hi, otherwise the device-side bisection on log10 alpha
+ * runs and its result is returned.  g_delta: DEVICE; delta > 0 (weighted norm).
+ * alpha_out, info: HOST (info may be NULL).  Synchronous.  Returns QBVM_ENOROOT
+ * (with *alpha_out = the nearer bracket end and info->bracket_hit = 1) when the
+ * root is outside the bracket. */
+int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double delta,
+                      const qbvm_alpha_opts* opts, double* alpha_out, qbvm_alpha_info* info);
+
+/* Batched bisection for `count` instances on the plan's grid (label generation).
+ * g_deltas: DEVICE, count * m^d doubles; deltas: DEVICE, count doubles;
+ * alphas_out: DEVICE, count doubles; hits_out: DEVICE, count ints (may be NULL).
+ * Asynchronous on the plan's stream. */
+int qbvm_bisect_batched(qbvm_plan_t p, int variant, int count, const double* g_deltas,
+                        const double* deltas, const qbvm_alpha_opts* opts,
+                        double* alphas_out, int* hits_out);
+
+/* Learned-alpha input features for `count` instances on the plan's grid:
+ * 32 bins of log10(h^d * sum of squared orthonormal-DST coefficients) over
+ * rho = |k|_2 in [sqrt(d), m sqrt(d)], then log10(delta).  g_deltas: DEVICE,
+ * count * m^d; deltas: DEVICE, count; feats: DEVICE, count * 33 floats (FP32 of
+ * the FP64 values).  Asynchronous on the plan's stream. */
+int qbvm_features(qbvm_plan_t p, int count, const double* g_deltas, const double* deltas,
+                  float* feats);
+
+/* Attach a learned-alpha model to the plan (copied to the device).  model: HOST,
+ * QBVM_MODEL_FLOATS floats = network parameters (QBVM_MLP_PARAMS, layout of
+ * qbvm_mlp_forward) | feature mean[33] | feature std[33] | label mean | label std.
+ * The network maps standardised features to the standardised label log10 alpha. */
+int qbvm_set_alpha_model(qbvm_plan_t p, const float* model);
+
+/* ------------------------------------------------------- network (FP32) ---- */
+/* 33 -> 64 -> 64 -> 1 perceptron, GELU (erf form) after both hidden layers.
+ * Parameter layout (QBVM_MLP_PARAMS floats): W1[64][33] | b1[64] | W2[64][64] |
+ * b2[64] | W3[64] | b3.  All pointers DEVICE; asynchronous on hip_stream. */
+
+/* out[b] = net(X[b, :]) for b < B.  X: B x 33 row-major. */
+int qbvm_mlp_forward(const float* params, int B, const float* X, float* out, void* hip_stream);
+
+/* Mean-squared-error loss over the batch and its gradient (backpropagation).
+ * grad: QBVM_MLP_PARAMS floats (overwritten); loss: 1 float (overwritten). */
+int qbvm_mlp_loss_grad(const float* params, int B, const float* X, const float* y,
+                       float* grad, float* loss, void* hip_stream);
+
+/* One Adam step (bias-corrected, step >= 1) on n parameters. */
+int qbvm_adam_step(float* params, const float* grad, float* m, float* v, int n, int step,
+                   float lr, float beta1, float beta2, float eps, void* hip_stream);
+
+/* ------------------------------------------------------------- errors ---- */
+const char* qbvm_strerror(int code);
+const char* qbvm_last_error(void);
+int qbvm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QBVM_H */

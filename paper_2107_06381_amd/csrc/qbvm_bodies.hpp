@@ -1,0 +1,253 @@
+// Kernel bodies of the solve path, written against the HIP device model
+// (threadIdx, blockDim, __syncthreads, LDS pointer passed in).  Included by the
+// gfx950 kernels and, with a thin shim, by the CPU build used in the tests.
+#pragma once
+
+#include "qbvm_fft_dev.hpp"
+
+namespace qbvm {
+
+// ------------------------------------------------------------------ helpers
+// omega and f0 scale from alpha (Sections 3.1, 3.2)
+__device__ __forceinline__ SolveScalars scalars_from_alpha(double alpha, int variant, double tau) {
+  SolveScalars s;
+  if (variant == 0) {
+    s.logabsw = -log(alpha);          // |omega| = 1/alpha
+    s.f0s = 1.0 / (tau * alpha);
+  } else {
+    s.logabsw = log(tau) - log(alpha);  // |omega| = tau/alpha
+    s.f0s = 1.0 / alpha;
+  }
+  return s;
+}
+
+// d_j / tau with d_j = 1 - omega^{1/N_t} theta^j = 1 - |omega|^{1/N_t} exp(i pi (2j+1)/N_t)
+__device__ __forceinline__ c64 shift_over_tau(int j, int Nt, double croot, double inv_tau) {
+  double sn, cs;
+  sincospi((double)(2 * j + 1) / (double)Nt, &sn, &cs);
+  return {(1.0 - croot * cs) * inv_tau, -croot * sn * inv_tau};
+}
+
+// scale * gamma_l^{-1} = scale * |omega|^{-l/N_t} exp(-i pi l/N_t)
+__device__ __forceinline__ c64 inv_gamma(int l, int Nt, double logabsw, double scale) {
+  double sn, cs;
+  sincospi((double)l / (double)Nt, &sn, &cs);
+  const double g = exp(-(double)l * logabsw / (double)Nt) * scale;
+  return {g * cs, -g * sn};
+}
+
+// eigenvalue of -Lap_h for flattened mode index k (x_1 fastest)
+__device__ __forceinline__ double mode_mu(long long k, int d, int m, const double* __restrict__ mu1d) {
+  double mu = 0.0;
+  for (int i = 0; i < d; ++i) {
+    const long long q = k / m;
+    mu += mu1d[k - q * m];
+    k = q;
+  }
+  return mu;
+}
+
+// ================================================================ k_dst ====
+// Orthonormal DST-I along the `len` axis of [outer][len][inner]: X_i = sqrt(2/(m+1)) *
+// sum_k x_k sin(pi i k/(m+1)).  Two real lines a, b are packed as a + i b into one
+// length-2(m+1) DFT of their odd extensions v = [0, x, 0, -reverse(x)]:
+// DFT(v_a + i v_b)_i = -2i S_a(i) + 2 S_b(i).
+template <bool WIDE>
+__device__ __forceinline__ void dst_body(const DstArgs& a, long long wg, c64* lds) {
+  const int S = a.S, m = a.len, nc = a.fft.nc, N = a.fft.n;
+  const int nl = 2 * S;
+  c64* buf = lds;
+  c64* side = lds + (size_t)S * nc;
+  const bool contig = (a.inner == 1);
+  long long o = 0, i0 = 0;
+  if (contig) {
+    i0 = wg * nl;  // first line (outer index)
+  } else {
+    o = wg / a.tiles_per_outer;
+    i0 = (wg - o * a.tiles_per_outer) * nl;
+  }
+  for (int e = threadIdx.x; e < S * nc; e += blockDim.x) buf[e] = {0.0, 0.0};
+  __syncthreads();
+  double* bp = reinterpret_cast<double*>(buf);
+  const int tot = nl * m;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    int q, k;
+    double x = 0.0;
+    if (contig) {
+      q = e / m;
+      k = e - q * m;
+      const long long line = i0 + q;
+      if (line < a.outer) x = a.in[line * m + k];
+    } else {
+      k = e / nl;
+      q = e - k * nl;
+      const long long i = i0 + q;
+      if (i < a.inner) x = a.in[(o * m + k) * a.inner + i];
+    }
+    const int s = q >> 1, comp = q & 1;
+    const int p1 = fft_in_pos(a.fft, k + 1), p2 = fft_in_pos(a.fft, N - 1 - k);
+    bp[2 * ((size_t)p1 * S + s) + comp] = x;
+    bp[2 * ((size_t)p2 * S + s) + comp] = -x;
+  }
+  __syncthreads();
+  if (a.fft.kind == kBluestein) fft_bluestein_prep(buf, S, a.fft);
+  fft_run<WIDE>(buf, S, a.fft, side);
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    int q, k;
+    long long dst;
+    bool ok;
+    if (contig) {
+      q = e / m;
+      k = e - q * m;
+      const long long line = i0 + q;
+      ok = line < a.outer;
+      dst = line * m + k;
+    } else {
+      k = e / nl;
+      q = e - k * nl;
+      const long long i = i0 + q;
+      ok = i < a.inner;
+      dst = (o * m + k) * a.inner + i;
+    }
+    const int s = q >> 1, comp = q & 1;
+    const c64 V = fft_out(buf, S, a.fft, s, k + 1, side);
+    const double val = comp == 0 ? -V.im : V.re;
+    if (ok) a.out[dst] = val * a.scale;
+  }
+}
+
+
+// =============================================================== k_time ====
+template <bool WIDE>
+__device__ __forceinline__ void time_body(const TimeArgs& a, long long wg, c64* lds) {
+  const int S = a.S, Nt = a.Nt, nc = a.fft.nc;
+  c64* buf = lds;
+  c64* side = buf + (size_t)S * nc;
+  c64* dt = side + 2 * S;
+  c64* gi = dt + Nt;
+  double* mus = reinterpret_cast<double*>(gi + a.lev_count);
+  double* gh = mus + 2 * S;
+
+  SolveScalars sc = a.sc;
+  if (a.alpha_dev) sc = scalars_from_alpha(*a.alpha_dev, a.variant, a.tau);
+  const double croot = exp(sc.logabsw / (double)Nt);
+  const double inv_tau = 1.0 / a.tau;
+  const double gscale = sc.f0s / (double)Nt;
+  for (int j = threadIdx.x; j < Nt; j += blockDim.x) dt[j] = shift_over_tau(j, Nt, croot, inv_tau);
+  for (int li = threadIdx.x; li < a.lev_count; li += blockDim.x)
+    gi[li] = inv_gamma(a.lev_first + li, Nt, sc.logabsw, gscale);
+  const long long k0 = wg * 2LL * S;
+  for (int q = threadIdx.x; q < 2 * S; q += blockDim.x) {
+    const long long k = k0 + q;
+    if (k < a.nmodes) {
+      mus[q] = mode_mu(k, a.d, a.m, a.mu1d);
+      gh[q] = a.ghat[k];
+    } else {
+      mus[q] = 0.0;
+      gh[q] = 0.0;
+    }
+  }
+  __syncthreads();
+  // Steps (a)+(b): u_j = g_a/(d_j/tau + mu_a) + i g_b/(d_j/tau + mu_b)
+  for (int e = threadIdx.x; e < S * Nt; e += blockDim.x) {
+    const int j = e / S, s = e - j * S;
+    const c64 z = dt[j];
+    const double xa = z.re + mus[2 * s], xb = z.re + mus[2 * s + 1];
+    const double ia = gh[2 * s] / (xa * xa + z.im * z.im);
+    const double ib = gh[2 * s + 1] / (xb * xb + z.im * z.im);
+    // A = ia (xa - i z.im), B = ib (xb - i z.im); u = A + i B
+    const c64 u = {ia * xa + ib * z.im, ib * xb - ia * z.im};
+    const int pos = fft_in_pos(a.fft, j);
+    if (pos < 0) side[s] = u;
+    else buf[(size_t)pos * S + s] = u;
+  }
+  __syncthreads();
+  if (a.fft.kind == kBluestein) fft_bluestein_prep(buf, S, a.fft);
+  fft_run<WIDE>(buf, S, a.fft, side);
+  // Step (c): gamma_l^{-1}/N_t * X_l; real part -> mode a, imaginary part -> mode b
+  const int tot = S * a.lev_count;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int li = e / S, s = e - li * S;
+    const c64 X = fft_out(buf, S, a.fft, s, a.lev_first + li, side);
+    const c64 v = cmul(gi[li], X);
+    const long long ka = k0 + 2 * s;
+    double* yl = a.y + (long long)(a.lev_dst0 + li) * a.ystride;
+    if (ka < a.nmodes) yl[ka] = v.re;
+    if (ka + 1 < a.nmodes) yl[ka + 1] = v.im;
+  }
+}
+
+
+// ============================================================= k_thomas ====
+// Step (b) in 1D: (d_j/tau + 2/h^2) s_i - (s_{i-1} + s_{i+1})/h^2 = f0_i for each shift j.
+__device__ __forceinline__ void thomas_body(const ThomasArgs& a, int j) {
+  const int Nt = a.Nt, m = a.m;
+  const SolveScalars sc = a.alpha_dev ? scalars_from_alpha(*a.alpha_dev, a.variant, a.tau) : a.sc;
+  const double croot = exp(sc.logabsw / (double)Nt);
+  const c64 z = shift_over_tau(j, Nt, croot, 1.0 / a.tau);
+  const double ih2 = 1.0 / (a.h * a.h);
+  const c64 bdiag = {z.re + 2.0 * ih2, z.im};
+  const double off = -ih2;
+  // forward sweep
+  c64 cp = {0.0, 0.0}, dp = {0.0, 0.0};
+  for (int i = 0; i < m; ++i) {
+    const c64 den = {bdiag.re - off * cp.re, bdiag.im - off * cp.im};
+    const double q = 1.0 / (den.re * den.re + den.im * den.im);
+    const c64 inv = {den.re * q, -den.im * q};
+    const double r = sc.f0s * a.g[i];
+    cp = cscale(inv, off);
+    dp = cmul({r - off * dp.re, -off * dp.im}, inv);
+    a.cp[(long long)i * Nt + j] = cp;
+    a.s2[(long long)i * Nt + j] = dp;
+  }
+  // back substitution
+  c64 x = dp;
+  for (int i = m - 2; i >= 0; --i) {
+    const c64 c = a.cp[(long long)i * Nt + j];
+    const c64 d = a.s2[(long long)i * Nt + j];
+    x = csub(d, cmul(c, x));
+    a.s2[(long long)i * Nt + j] = x;
+  }
+}
+
+
+// ============================================================= k_time1d ====
+// Step (c) in 1D: per grid point, X_l = sum_j S2(x, j) exp(-2 pi i jl/N_t); y^l = Re(gamma_l^{-1} X_l)/N_t.
+template <bool WIDE>
+__device__ __forceinline__ void time1d_body(const Time1dArgs& a, long long wg, c64* lds) {
+  const int S = a.S, Nt = a.Nt, nc = a.fft.nc, m = a.m;
+  c64* buf = lds;
+  c64* side = buf + (size_t)S * nc;
+  c64* gi = side + 2 * S;
+  const double gscale = 1.0 / (double)Nt;
+  const SolveScalars sc = a.alpha_dev ? scalars_from_alpha(*a.alpha_dev, a.variant, a.tau) : a.sc;
+  for (int li = threadIdx.x; li < a.lev_count; li += blockDim.x)
+    gi[li] = inv_gamma(a.lev_first + li, Nt, sc.logabsw, gscale);
+  const long long x0 = wg * 2LL * S;
+  for (int e = threadIdx.x; e < S * Nt; e += blockDim.x) {
+    const int s = e / Nt, j = e - s * Nt;
+    const long long xa = x0 + 2 * s, xb = xa + 1;
+    const c64 A = xa < m ? a.s2[xa * Nt + j] : c64{0.0, 0.0};
+    const c64 B = xb < m ? a.s2[xb * Nt + j] : c64{0.0, 0.0};
+    const c64 u = {A.re - B.im, A.im + B.re};
+    const int pos = fft_in_pos(a.fft, j);
+    if (pos < 0) side[s] = u;
+    else buf[(size_t)pos * S + s] = u;
+  }
+  __syncthreads();
+  if (a.fft.kind == kBluestein) fft_bluestein_prep(buf, S, a.fft);
+  fft_run<WIDE>(buf, S, a.fft, side);
+  const int tot = S * a.lev_count;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int li = e / S, s = e - li * S;
+    const c64 X = fft_out(buf, S, a.fft, s, a.lev_first + li, side);
+    const c64 v = cmul(gi[li], X);
+    const long long xa = x0 + 2 * s;
+    double* yl = a.y + (long long)li * a.ystride;
+    if (xa < m) yl[xa] = v.re;
+    if (xa + 1 < m) yl[xa + 1] = v.im;
+  }
+}
+
+
+}  // namespace qbvm

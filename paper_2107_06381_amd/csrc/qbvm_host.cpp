@@ -1,0 +1,739 @@
+// Host executor of the PinT quasi-boundary value solver: FFT planning, plans,
+// solve orchestration, regularisation-parameter choice, batched graphs, C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/qbvm.h"
+#include "qbvm_fft_plan.hpp"
+#include "qbvm_internal.hpp"
+#include "qbvm_schedule.hpp"
+
+using namespace qbvm;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess) {                                                                \
+      return set_error(_e == hipErrorOutOfMemory ? QBVM_ENOMEM : QBVM_EHIP,                \
+                       std::string(#expr) + ": " + hipGetErrorString(_e));                 \
+    }                                                                                      \
+  } while (0)
+
+// ------------------------------------------------------------- FFT planning
+namespace {
+
+constexpr long double kPiL = 3.141592653589793238462643383279502884L;
+constexpr int kThreads = 256;
+
+struct FftTables {
+  FftPlanDev dev{};
+  std::vector<void*> allocs;
+};
+
+template <class T>
+hipError_t upload(const std::vector<T>& v, const T** dst, std::vector<void*>& allocs) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(1, v.size()) * sizeof(T));
+  if (e != hipSuccess) return e;
+  allocs.push_back(p);
+  if (!v.empty()) e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  *dst = static_cast<const T*>(p);
+  return e;
+}
+
+// Build the device tables of a forward DFT of logical length n.
+int build_fft(int n, FftTables& t) {
+  plan::HostFft h;
+  std::string err;
+  if (!plan::build_tables(n, h, err)) return set_error(QBVM_EUNSUPPORTED, err);
+  t.dev = h.dev;
+  FftPlanDev& d = t.dev;
+  HIP_TRY(upload(h.tw, &d.tw, t.allocs));
+  HIP_TRY(upload(h.kspec, &d.kspec, t.allocs));
+  HIP_TRY(upload(h.chirp, &d.chirp, t.allocs));
+  HIP_TRY(upload(h.rin, &d.rin, t.allocs));
+  HIP_TRY(upload(h.rout, &d.rout, t.allocs));
+  return QBVM_OK;
+}
+
+std::mutex g_mu;
+std::map<std::pair<int, int>, std::unique_ptr<FftTables>> g_fft_cache;  // (device, n)
+std::map<int, bool> g_roots_ready;
+
+int get_fft(int device, int n, const FftTables** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_roots_ready[device]) {
+    const std::vector<c64> roots = plan::radix_roots();
+    upload_radix_roots(roots.data(), (int)roots.size());
+    HIP_TRY(hipGetLastError());
+    g_roots_ready[device] = true;
+  }
+  auto key = std::make_pair(device, n);
+  auto it = g_fft_cache.find(key);
+  if (it == g_fft_cache.end()) {
+    auto t = std::make_unique<FftTables>();
+    const int rc = build_fft(n, *t);
+    if (rc != QBVM_OK) {
+      for (void* p : t->allocs) (void)hipFree(p);
+      return rc;
+    }
+    it = g_fft_cache.emplace(key, std::move(t)).first;
+  }
+  *out = it->second.get();
+  return QBVM_OK;
+}
+
+
+
+}  // namespace
+
+// ------------------------------------------------------------------ plans
+struct qbvm_plan_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int d = 0, m = 0, n = 0, Nt = 0;
+  double L = 1, T = 1, h = 0, tau = 0, hd = 0;
+  long long nmodes = 0;
+  const FftTables* tfft = nullptr;  // length N_t
+  const FftTables* sfft = nullptr;  // length 2(m+1)
+  int S_time = 1, S_dst = 1;
+  double* mu1d = nullptr;
+  double* ghat = nullptr;
+  double* yrow = nullptr;
+  c64* s2 = nullptr;
+  c64* cp = nullptr;
+  double* partial = nullptr;
+  unsigned* counter = nullptr;
+  double* dscal = nullptr;   // [0] delta, [1] alpha_pred, [2] log10 alpha_pred, [3] D, [4] alpha_final, ...
+  double* bstate = nullptr;  // kBState doubles
+  float* feats = nullptr;
+  float* model = nullptr;
+  bool has_model = false;
+  int* bin_perm = nullptr;
+  int* bin_off = nullptr;
+  double* pinned = nullptr;  // host, 64 doubles
+  int wg_row = 1;
+  // grow-only batch workspace
+  double* bws = nullptr;
+  size_t bws_bytes = 0;
+  long long bytes = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+template <class T>
+hipError_t dalloc(qbvm_plan_s* p, T** out, size_t count) {
+  void* q = nullptr;
+  const size_t b = std::max<size_t>(1, count) * sizeof(T);
+  hipError_t e = hipMalloc(&q, b);
+  if (e != hipSuccess) return e;
+  p->allocs.push_back(q);
+  p->bytes += (long long)b;
+  *out = static_cast<T*>(q);
+  return hipSuccess;
+}
+
+int validate_grid(const qbvm_grid* g) {
+  if (!g) return set_error(QBVM_EINVAL, "grid is NULL");
+  if (g->d < 1 || g->d > 3) return set_error(QBVM_EINVAL, "d must be 1, 2 or 3");
+  if (g->m < 1 || g->n < 1) return set_error(QBVM_EINVAL, "m and n must be >= 1");
+  if (!(g->L > 0) || !(g->T > 0) || !std::isfinite(g->L) || !std::isfinite(g->T))
+    return set_error(QBVM_EINVAL, "L and T must be positive and finite");
+  const int mmax = g->d == 1 ? QBVM_MAX_M_1D : (g->d == 2 ? QBVM_MAX_M_2D : QBVM_MAX_M_3D);
+  if (g->m > mmax || g->n + 1 > QBVM_MAX_NT) return set_error(QBVM_EUNSUPPORTED, "grid exceeds the size limits");
+  return QBVM_OK;
+}
+
+// bins of the learned-alpha features (same arithmetic and order as the definition)
+void feature_bins(int d, int m, std::vector<int>& perm, std::vector<int>& off) {
+  long long nm = 1;
+  for (int i = 0; i < d; ++i) nm *= m;
+  std::vector<int> bin(nm);
+  const double lo = std::sqrt((double)d), hi = (double)m * std::sqrt((double)d);
+  for (long long k = 0; k < nm; ++k) {
+    long long r = k, ksq = 0;
+    for (int i = 0; i < d; ++i) {
+      const long long q = r / m, ki = r - q * m + 1;
+      ksq += ki * ki;
+      r = q;
+    }
+    int b = 0;
+    if (m > 1) {
+      const double rho = std::sqrt((double)ksq);
+      const double t = (rho - lo) / (hi - lo) * 32.0;
+      b = (int)std::floor(t);
+      b = std::min(31, std::max(0, b));
+    }
+    bin[k] = b;
+  }
+  off.assign(33, 0);
+  for (long long k = 0; k < nm; ++k) off[bin[k] + 1]++;
+  for (int b = 0; b < 32; ++b) off[b + 1] += off[b];
+  perm.assign(nm, 0);
+  std::vector<int> cur(off.begin(), off.end() - 1);
+  for (long long k = 0; k < nm; ++k) perm[cur[bin[k]]++] = (int)k;
+}
+
+void destroy_plan(qbvm_plan_s* p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  (void)hipStreamSynchronize(p->stream);
+  for (void* q : p->allocs) (void)hipFree(q);
+  if (p->bws) (void)hipFree(p->bws);
+  if (p->pinned) (void)hipHostFree(p->pinned);
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
+  *out = nullptr;
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  auto* p = new (std::nothrow) qbvm_plan_s();
+  if (!p) return set_error(QBVM_ENOMEM, "host allocation failed");
+  std::unique_ptr<qbvm_plan_s, void (*)(qbvm_plan_s*)> guard(p, destroy_plan);
+  HIP_TRY(hipGetDevice(&p->device));
+  p->stream = stream;
+  p->d = grid->d;
+  p->m = grid->m;
+  p->n = grid->n;
+  p->Nt = grid->n + 1;
+  p->L = grid->L;
+  p->T = grid->T;
+  p->h = grid->L / (grid->m + 1);
+  p->tau = grid->T / grid->n;
+  p->hd = std::pow(p->h, p->d);
+  p->nmodes = 1;
+  for (int i = 0; i < p->d; ++i) p->nmodes *= p->m;
+  rc = get_fft(p->device, p->Nt, &p->tfft);
+  if (rc) return rc;
+  rc = get_fft(p->device, 2 * (p->m + 1), &p->sfft);
+  if (rc) return rc;
+  p->S_time = plan::signals_for(p->tfft->dev.nc);
+  p->S_dst = plan::signals_for(p->sfft->dev.nc);
+  // eigenvalues of the 1D three-point stencil: (4/h^2) sin^2(k pi/(2(m+1)))
+  std::vector<double> mu(p->m);
+  for (int k = 1; k <= p->m; ++k) {
+    const long double s = sinl((long double)k * kPiL / (2.0L * (p->m + 1)));
+    mu[k - 1] = (double)(4.0L / ((long double)p->h * p->h) * s * s);
+  }
+  HIP_TRY(dalloc(p, &p->mu1d, p->m));
+  HIP_TRY(hipMemcpy(p->mu1d, mu.data(), sizeof(double) * p->m, hipMemcpyHostToDevice));
+  HIP_TRY(dalloc(p, &p->ghat, p->nmodes));
+  HIP_TRY(dalloc(p, &p->yrow, p->nmodes));
+  if (p->d == 1) {
+    HIP_TRY(dalloc(p, &p->s2, (size_t)p->Nt * p->m));
+    HIP_TRY(dalloc(p, &p->cp, (size_t)p->Nt * p->m));
+  }
+  p->wg_row = (int)std::max<long long>(1, std::min<long long>(1024, (p->nmodes + 255) / 256));
+  HIP_TRY(dalloc(p, &p->partial, p->wg_row));
+  HIP_TRY(dalloc(p, &p->counter, 1));
+  HIP_TRY(hipMemset(p->counter, 0, sizeof(unsigned)));
+  HIP_TRY(dalloc(p, &p->dscal, 16));
+  HIP_TRY(dalloc(p, &p->bstate, kBState));
+  HIP_TRY(dalloc(p, &p->feats, 33));
+  HIP_TRY(dalloc(p, &p->model, QBVM_MODEL_FLOATS));
+  std::vector<int> perm, off;
+  feature_bins(p->d, p->m, perm, off);
+  HIP_TRY(dalloc(p, &p->bin_perm, perm.size()));
+  HIP_TRY(dalloc(p, &p->bin_off, off.size()));
+  HIP_TRY(hipMemcpy(p->bin_perm, perm.data(), sizeof(int) * perm.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->bin_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipHostMalloc((void**)&p->pinned, 64 * sizeof(double), hipHostMallocDefault));
+  guard.release();
+  *out = p;
+  return QBVM_OK;
+}
+
+sched::Geom geom(const qbvm_plan_s* p) {
+  sched::Geom g{};
+  g.d = p->d;
+  g.m = p->m;
+  g.n = p->n;
+  g.Nt = p->Nt;
+  g.h = p->h;
+  g.tau = p->tau;
+  g.nmodes = p->nmodes;
+  g.S_time = p->S_time;
+  g.S_dst = p->S_dst;
+  g.tfft = p->tfft->dev;
+  g.sfft = p->sfft->dev;
+  g.mu1d = p->mu1d;
+  return g;
+}
+
+// d passes of the orthonormal DST-I over a [batch][m]^d array
+int run_dst(const qbvm_plan_s* p, const double* in, double* out, long long batch, NodeCtx* nc = nullptr,
+            hipStream_t stream = nullptr) {
+  hipStream_t s = nc ? stream : p->stream;
+  for (const auto& L : sched::dst_passes(geom(p), in, out, batch))
+    HIP_TRY(launch_dst(L.args, L.nwg, kThreads, L.lds, s, nc));
+  return QBVM_OK;
+}
+
+int check_alpha(double alpha, int variant) {
+  if (!(alpha > 0) || !std::isfinite(alpha)) return set_error(QBVM_EINVAL, "alpha must be positive and finite");
+  if (variant != QBVM_PQ && variant != QBVM_PM) return set_error(QBVM_EINVAL, "variant must be QBVM_PQ or QBVM_PM");
+  return QBVM_OK;
+}
+
+// Enqueue one full solve (every level).  alpha_dev (optional) overrides alpha.
+int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, int variant, const double* g,
+                 double* y, c64* s2, c64* cp, NodeCtx* nc, hipStream_t stream) {
+  const sched::Geom G = geom(p);
+  const SolveScalars sc = sched::host_scalars(alpha, variant, p->tau);
+  if (p->d == 1) {
+    HIP_TRY(launch_thomas(sched::thomas_step(G, sc, alpha_dev, variant, g, s2, cp), stream, nc));
+    const auto t = sched::time1d_step(G, sc, alpha_dev, variant, s2, y);
+    HIP_TRY(launch_time1d(t.args, t.nwg, kThreads, t.lds, stream, nc));
+    return QBVM_OK;
+  }
+  // g_hat = Q g_delta, kept in the level-0 slot of y (each time tile reads only its own modes)
+  int rc = run_dst(p, g, y, 1, nc, stream);
+  if (rc) return rc;
+  const auto t = sched::time_step(G, sc, alpha_dev, variant, y, y, 0, p->Nt);
+  HIP_TRY(launch_time(t.args, t.nwg, kThreads, t.lds, stream, nc));
+  return run_dst(p, y, y, p->Nt, nc, stream);
+}
+
+// one level of Step (c) per mode; optional mode output and discrepancy reduction
+int enqueue_row(const qbvm_plan_s* p, int count, const double* ghat, int level, double alpha,
+                const double* alpha_dev, int variant, double* yrow, bool reduce, double* bstate, int mode,
+                double* dout, double* partial, unsigned* counter, int wg_per_inst) {
+  RowArgs r{};
+  r.Nt = p->Nt;
+  r.d = p->d;
+  r.m = p->m;
+  r.level = level;
+  r.count = count;
+  r.nmodes = p->nmodes;
+  r.tau = p->tau;
+  r.hd = p->hd;
+  r.variant = variant;
+  r.mu1d = p->mu1d;
+  r.ghat = ghat;
+  r.yrow = yrow;
+  r.partial = reduce ? partial : nullptr;
+  r.counter = counter;
+  r.wg_per_inst = wg_per_inst;
+  r.alpha = alpha;
+  r.alpha_dev = alpha_dev;
+  r.bstate = bstate;
+  r.mode = mode;
+  r.dout = dout;
+  const size_t lds = sizeof(c64) * 2 * p->Nt;
+  HIP_TRY(launch_row(r, (long long)count * wg_per_inst, kThreads, lds, p->stream));
+  return QBVM_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+int qbvm_version(void) { return 1; }
+
+const char* qbvm_strerror(int code) {
+  switch (code) {
+    case QBVM_OK: return "ok";
+    case QBVM_EINVAL: return "invalid argument";
+    case QBVM_ENOMEM: return "out of memory";
+    case QBVM_EHIP: return "HIP runtime error";
+    case QBVM_ENOROOT: return "discrepancy principle has no root in the bracket";
+    case QBVM_EUNSUPPORTED: return "unsupported size";
+    case QBVM_ENOMODEL: return "no learned-alpha model attached to the plan";
+    default: return "unknown error";
+  }
+}
+
+const char* qbvm_last_error(void) { return g_last_error.c_str(); }
+
+int qbvm_plan(qbvm_plan_t* out, const qbvm_grid* grid, void* hip_stream) {
+  if (!out) return set_error(QBVM_EINVAL, "out is NULL");
+  *out = nullptr;
+  qbvm_plan_s* p = nullptr;
+  const int rc = create_plan(&p, grid, (hipStream_t)hip_stream);
+  if (rc) return rc;
+  *out = p;
+  return QBVM_OK;
+}
+
+void qbvm_plan_destroy(qbvm_plan_t p) { destroy_plan(p); }
+
+int qbvm_plan_set_stream(qbvm_plan_t p, void* hip_stream) {
+  if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
+  p->stream = (hipStream_t)hip_stream;
+  return QBVM_OK;
+}
+
+long long qbvm_plan_workspace_bytes(qbvm_plan_t p) { return p ? p->bytes : 0; }
+
+int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta, double* y, int output) {
+  if (!p || !g_delta || !y) return set_error(QBVM_EINVAL, "NULL argument");
+  int rc = check_alpha(alpha, variant);
+  if (rc) return rc;
+  if (output != QBVM_OUT_ALL && output != QBVM_OUT_Y0 && output != QBVM_OUT_YN)
+    return set_error(QBVM_EINVAL, "output must be QBVM_OUT_ALL, QBVM_OUT_Y0 or QBVM_OUT_YN");
+  if (output == QBVM_OUT_ALL)
+    return enqueue_full(p, alpha, nullptr, variant, g_delta, y, p->s2, p->cp, nullptr, p->stream);
+  rc = run_dst(p, g_delta, p->ghat, 1);
+  if (rc) return rc;
+  const int level = output == QBVM_OUT_Y0 ? 0 : p->n;
+  rc = enqueue_row(p, 1, p->ghat, level, alpha, nullptr, variant, p->yrow, false, nullptr, 0, nullptr, nullptr,
+                   nullptr, p->wg_row);
+  if (rc) return rc;
+  return run_dst(p, p->yrow, y, 1);
+}
+
+int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_delta, double* D_out) {
+  if (!p || !g_delta || !D_out) return set_error(QBVM_EINVAL, "NULL argument");
+  int rc = check_alpha(alpha, variant);
+  if (rc) return rc;
+  rc = run_dst(p, g_delta, p->ghat, 1);
+  if (rc) return rc;
+  rc = enqueue_row(p, 1, p->ghat, p->n, alpha, nullptr, variant, nullptr, true, nullptr, 0, p->dscal + 3,
+                   p->partial, p->counter, p->wg_row);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(p->pinned, p->dscal + 3, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  *D_out = p->pinned[0];
+  return QBVM_OK;
+}
+
+static int enqueue_bisection(qbvm_plan_t p, int variant, int count, const double* ghat, const double* deltas,
+                             const qbvm_alpha_opts* o, double* bstate, double* alphas_out, int* hits_out,
+                             double* partial, unsigned* counter, int wpi) {
+  HIP_TRY(launch_bisect_init(bstate, count, deltas, o->tau_dp, o->log10_lo, o->log10_hi, p->stream));
+  int rc = enqueue_row(p, count, ghat, p->n, 0.0, nullptr, variant, nullptr, true, bstate, 2, nullptr, partial,
+                       counter, wpi);
+  if (rc) return rc;
+  rc = enqueue_row(p, count, ghat, p->n, 0.0, nullptr, variant, nullptr, true, bstate, 3, nullptr, partial,
+                   counter, wpi);
+  if (rc) return rc;
+  for (int it = 0; it < o->steps; ++it) {
+    rc = enqueue_row(p, count, ghat, p->n, 0.0, nullptr, variant, nullptr, true, bstate, 1, nullptr, partial,
+                     counter, wpi);
+    if (rc) return rc;
+  }
+  HIP_TRY(launch_bisect_finish(bstate, count, alphas_out, hits_out, p->stream));
+  return QBVM_OK;
+}
+
+static int check_opts(const qbvm_alpha_opts* o) {
+  if (!o) return set_error(QBVM_EINVAL, "opts is NULL");
+  if (!(o->tau_dp > 0) || !(o->log10_lo < o->log10_hi) || o->steps < 0 || o->steps > 200)
+    return set_error(QBVM_EINVAL, "invalid bisection options");
+  return QBVM_OK;
+}
+
+int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double delta, const qbvm_alpha_opts* o,
+                      double* alpha_out, qbvm_alpha_info* info) {
+  if (!p || !g_delta || !alpha_out) return set_error(QBVM_EINVAL, "NULL argument");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (!(delta > 0) || !std::isfinite(delta)) return set_error(QBVM_EINVAL, "delta must be positive");
+  if (variant != QBVM_PQ && variant != QBVM_PM) return set_error(QBVM_EINVAL, "invalid variant");
+  if (o->use_learned && !p->has_model) return set_error(QBVM_ENOMODEL, "no model attached");
+  qbvm_alpha_info inf{};
+  p->pinned[0] = delta;
+  HIP_TRY(hipMemcpyAsync(p->dscal, p->pinned, sizeof(double), hipMemcpyHostToDevice, p->stream));
+  rc = run_dst(p, g_delta, p->ghat, 1);
+  if (rc) return rc;
+  if (o->use_learned) {
+    HIP_TRY(launch_features(1, p->nmodes, p->hd, p->ghat, p->dscal, p->bin_perm, p->bin_off, p->feats, p->stream));
+    HIP_TRY(launch_predict(p->model, p->feats, p->dscal + 1, p->stream));
+    rc = enqueue_row(p, 1, p->ghat, p->n, 0.0, p->dscal + 1, variant, nullptr, true, nullptr, 0, p->dscal + 3,
+                     p->partial, p->counter, p->wg_row);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(p->pinned + 8, p->dscal, 4 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    const double a_hat = p->pinned[9], D = p->pinned[11];
+    inf.alpha_learned = a_hat;
+    inf.iterations = 1;
+    inf.discrepancy = D;
+    const double ratio = D / delta;
+    if (std::isfinite(a_hat) && a_hat > 0 && ratio >= o->win_lo && ratio <= o->win_hi) {
+      *alpha_out = a_hat;
+      if (info) *info = inf;
+      return QBVM_OK;
+    }
+    inf.used_fallback = 1;
+  }
+  rc = enqueue_bisection(p, variant, 1, p->ghat, p->dscal, o, p->bstate, p->dscal + 4, nullptr, p->partial,
+                         p->counter, p->wg_row);
+  if (rc) return rc;
+  rc = enqueue_row(p, 1, p->ghat, p->n, 0.0, p->dscal + 4, variant, nullptr, true, nullptr, 0, p->dscal + 3,
+                   p->partial, p->counter, p->wg_row);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(p->pinned + 16, p->bstate, kBState * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->pinned + 24, p->dscal, 8 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  const double* bs = p->pinned + 16;
+  *alpha_out = p->pinned[24 + 4];
+  inf.discrepancy = p->pinned[24 + 3];
+  inf.iterations += (int)bs[5] + 1;
+  inf.bracket_hit = bs[6] != 0.0 ? 1 : 0;
+  if (info) *info = inf;
+  return inf.bracket_hit ? set_error(QBVM_ENOROOT, "discrepancy root outside the bracket") : QBVM_OK;
+}
+
+static int ensure_batch_ws(qbvm_plan_t p, size_t bytes) {
+  if (p->bws_bytes >= bytes) return QBVM_OK;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (p->bws) HIP_TRY(hipFree(p->bws));
+  p->bws = nullptr;
+  p->bws_bytes = 0;
+  HIP_TRY(hipMalloc((void**)&p->bws, bytes));
+  p->bws_bytes = bytes;
+  return QBVM_OK;
+}
+
+int qbvm_bisect_batched(qbvm_plan_t p, int variant, int count, const double* g_deltas, const double* deltas,
+                        const qbvm_alpha_opts* o, double* alphas_out, int* hits_out) {
+  if (!p || !g_deltas || !deltas || !alphas_out) return set_error(QBVM_EINVAL, "NULL argument");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (count < 1) return set_error(QBVM_EINVAL, "count must be >= 1");
+  if (variant != QBVM_PQ && variant != QBVM_PM) return set_error(QBVM_EINVAL, "invalid variant");
+  const int wpi = (int)std::max<long long>(1, std::min<long long>(64, (p->nmodes + 1023) / 1024));
+  const size_t gh = (size_t)count * p->nmodes * sizeof(double);
+  const size_t bs = (size_t)count * kBState * sizeof(double);
+  const size_t pa = (size_t)count * wpi * sizeof(double);
+  const size_t co = (size_t)count * sizeof(unsigned);
+  rc = ensure_batch_ws(p, gh + bs + pa + co + 256);
+  if (rc) return rc;
+  char* base = reinterpret_cast<char*>(p->bws);
+  double* ghat = reinterpret_cast<double*>(base);
+  double* bstate = reinterpret_cast<double*>(base + gh);
+  double* partial = reinterpret_cast<double*>(base + gh + bs);
+  unsigned* counter = reinterpret_cast<unsigned*>(base + gh + bs + pa);
+  HIP_TRY(hipMemsetAsync(counter, 0, co, p->stream));
+  rc = run_dst(p, g_deltas, ghat, count);
+  if (rc) return rc;
+  return enqueue_bisection(p, variant, count, ghat, deltas, o, bstate, alphas_out, hits_out, partial, counter, wpi);
+}
+
+int qbvm_features(qbvm_plan_t p, int count, const double* g_deltas, const double* deltas, float* feats) {
+  if (!p || !g_deltas || !deltas || !feats) return set_error(QBVM_EINVAL, "NULL argument");
+  if (count < 1) return set_error(QBVM_EINVAL, "count must be >= 1");
+  const size_t gh = (size_t)count * p->nmodes * sizeof(double);
+  int rc = ensure_batch_ws(p, gh + 256);
+  if (rc) return rc;
+  double* ghat = p->bws;
+  rc = run_dst(p, g_deltas, ghat, count);
+  if (rc) return rc;
+  HIP_TRY(launch_features(count, p->nmodes, p->hd, ghat, deltas, p->bin_perm, p->bin_off, feats, p->stream));
+  return QBVM_OK;
+}
+
+int qbvm_set_alpha_model(qbvm_plan_t p, const float* model) {
+  if (!p || !model) return set_error(QBVM_EINVAL, "NULL argument");
+  for (int i = 0; i < QBVM_MODEL_FLOATS; ++i)
+    if (!std::isfinite(model[i])) return set_error(QBVM_EINVAL, "model contains a non-finite value");
+  for (int i = 0; i < 33; ++i)
+    if (!(model[QBVM_MLP_PARAMS + 33 + i] > 0)) return set_error(QBVM_EINVAL, "feature std must be positive");
+  HIP_TRY(hipMemcpyAsync(p->model, model, sizeof(float) * QBVM_MODEL_FLOATS, hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->has_model = true;
+  return QBVM_OK;
+}
+
+// ------------------------------------------------------------- network ABI
+static std::mutex g_mlp_mu;
+static std::map<int, std::pair<float*, size_t>> g_mlp_scratch;
+
+int qbvm_mlp_forward(const float* params, int B, const float* X, float* out, void* stream) {
+  if (!params || !X || !out || B < 1) return set_error(QBVM_EINVAL, "invalid argument");
+  HIP_TRY(launch_mlp_forward(params, B, X, out, (hipStream_t)stream));
+  return QBVM_OK;
+}
+
+int qbvm_mlp_loss_grad(const float* params, int B, const float* X, const float* y, float* grad, float* loss,
+                       void* stream) {
+  if (!params || !X || !y || !grad || !loss || B < 1) return set_error(QBVM_EINVAL, "invalid argument");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  const size_t need = (size_t)B * (64 * 3 + 1) * sizeof(float);
+  float* scratch = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mlp_mu);
+    auto& e = g_mlp_scratch[dev];
+    if (e.second < need) {
+      HIP_TRY(hipDeviceSynchronize());
+      if (e.first) HIP_TRY(hipFree(e.first));
+      e.first = nullptr;
+      e.second = 0;
+      HIP_TRY(hipMalloc((void**)&e.first, need));
+      e.second = need;
+    }
+    scratch = e.first;
+  }
+  HIP_TRY(launch_mlp_loss_grad(params, B, X, y, grad, loss, scratch, 0, (hipStream_t)stream));
+  return QBVM_OK;
+}
+
+int qbvm_adam_step(float* params, const float* grad, float* m, float* v, int n, int step, float lr, float beta1,
+                   float beta2, float eps, void* stream) {
+  if (!params || !grad || !m || !v || n < 1 || step < 1) return set_error(QBVM_EINVAL, "invalid argument");
+  HIP_TRY(launch_adam(params, grad, m, v, n, step, lr, beta1, beta2, eps, (hipStream_t)stream));
+  return QBVM_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ batched
+namespace {
+
+struct BatchEntry {
+  int device = 0;
+  std::vector<qbvm_grid> grids;
+  std::vector<int> variants, outputs;
+  std::vector<const double*> gs;
+  std::vector<double*> ys;
+  std::vector<qbvm_plan_s*> plans;  // owned by g_batch_plans
+  double* alphas_dev = nullptr;
+  std::vector<void*> ws;  // per-instance workspaces
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+std::mutex g_batch_mu;
+std::vector<std::unique_ptr<BatchEntry>> g_batches;
+std::map<std::tuple<int, int, int, int, double, double>, qbvm_plan_s*> g_batch_plans;
+
+bool same_grid(const qbvm_grid& a, const qbvm_grid& b) {
+  return a.d == b.d && a.m == b.m && a.n == b.n && a.L == b.L && a.T == b.T;
+}
+
+void free_entry(BatchEntry* e) {
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
+  if (e->graph) (void)hipGraphDestroy(e->graph);
+  for (void* w : e->ws) (void)hipFree(w);
+  if (e->alphas_dev) (void)hipFree(e->alphas_dev);
+}
+
+int build_entry(BatchEntry* e, int count, hipStream_t stream) {
+  e->plans.resize(count);
+  for (int i = 0; i < count; ++i) {
+    const qbvm_grid& g = e->grids[i];
+    auto key = std::make_tuple(e->device, g.d, g.m, g.n, g.L, g.T);
+    auto it = g_batch_plans.find(key);
+    if (it == g_batch_plans.end()) {
+      qbvm_plan_s* p = nullptr;
+      const int rc = create_plan(&p, &g, stream);
+      if (rc) return rc;
+      it = g_batch_plans.emplace(key, p).first;
+    }
+    e->plans[i] = it->second;
+  }
+  HIP_TRY(hipMalloc((void**)&e->alphas_dev, sizeof(double) * count));
+  HIP_TRY(hipGraphCreate(&e->graph, 0));
+  for (int i = 0; i < count; ++i) {
+    qbvm_plan_s* p = e->plans[i];
+    NodeCtx nc{e->graph, nullptr, false};
+    c64* s2 = nullptr;
+    c64* cp = nullptr;
+    const int out = e->outputs[i];
+    if (out == QBVM_OUT_ALL && p->d == 1) {
+      void* w = nullptr;
+      HIP_TRY(hipMalloc(&w, sizeof(c64) * 2 * (size_t)p->Nt * p->m));
+      e->ws.push_back(w);
+      s2 = static_cast<c64*>(w);
+      cp = s2 + (size_t)p->Nt * p->m;
+    }
+    // one plan may serve many instances: only its tables and geometry are used here
+    int rc;
+    if (out == QBVM_OUT_ALL) {
+      rc = enqueue_full(p, 1.0, e->alphas_dev + i, e->variants[i], e->gs[i], e->ys[i], s2, cp, &nc, stream);
+      if (rc) return rc;
+    } else {
+      return set_error(QBVM_EUNSUPPORTED, "batched solve supports QBVM_OUT_ALL");
+    }
+  }
+  HIP_TRY(hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0));
+  return QBVM_OK;
+}
+
+}  // namespace
+
+extern "C" int qbvm_solve_batched(int count, const qbvm_grid* grids, const double* alphas, const int* variants,
+                                  const double* const* g_deltas, double* const* ys, const int* outputs,
+                                  void* hip_stream) {
+  if (count < 1 || !grids || !alphas || !variants || !g_deltas || !ys || !outputs)
+    return set_error(QBVM_EINVAL, "NULL argument or count < 1");
+  for (int i = 0; i < count; ++i) {
+    int rc = validate_grid(&grids[i]);
+    if (rc) return rc;
+    rc = check_alpha(alphas[i], variants[i]);
+    if (rc) return rc;
+    if (!g_deltas[i] || !ys[i]) return set_error(QBVM_EINVAL, "NULL instance pointer");
+    if (outputs[i] != QBVM_OUT_ALL) return set_error(QBVM_EUNSUPPORTED, "batched solve supports QBVM_OUT_ALL");
+  }
+  hipStream_t stream = (hipStream_t)hip_stream;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  BatchEntry* hit = nullptr;
+  for (auto& e : g_batches) {
+    if (e->device != dev || (int)e->grids.size() != count) continue;
+    bool ok = true;
+    for (int i = 0; i < count && ok; ++i)
+      ok = same_grid(e->grids[i], grids[i]) && e->variants[i] == variants[i] && e->outputs[i] == outputs[i] &&
+           e->gs[i] == g_deltas[i] && e->ys[i] == ys[i];
+    if (ok) {
+      hit = e.get();
+      break;
+    }
+  }
+  if (!hit) {
+    auto e = std::make_unique<BatchEntry>();
+    e->device = dev;
+    e->grids.assign(grids, grids + count);
+    e->variants.assign(variants, variants + count);
+    e->outputs.assign(outputs, outputs + count);
+    e->gs.assign(g_deltas, g_deltas + count);
+    e->ys.assign(ys, ys + count);
+    const int rc = build_entry(e.get(), count, stream);
+    if (rc) {
+      free_entry(e.get());
+      return rc;
+    }
+    g_batches.push_back(std::move(e));
+    hit = g_batches.back().get();
+  }
+  // pageable source: the runtime stages it before returning, so no host-side wait is needed
+  HIP_TRY(hipMemcpyAsync(hit->alphas_dev, alphas, sizeof(double) * count, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipGraphLaunch(hit->exec, stream));
+  return QBVM_OK;
+}
+
+extern "C" void qbvm_batched_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  (void)hipDeviceSynchronize();
+  for (auto& e : g_batches) free_entry(e.get());
+  g_batches.clear();
+  for (auto& kv : g_batch_plans) destroy_plan(kv.second);
+  g_batch_plans.clear();
+}

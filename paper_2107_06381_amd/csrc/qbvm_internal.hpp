@@ -1,0 +1,45 @@
+// Internal interface between the host executor and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qbvm_types.hpp"
+
+namespace qbvm {
+
+// Optional graph target: when non-null the launch wrappers add a kernel node that
+// depends on `dep` (if has_dep) instead of launching, and update `dep`.
+struct NodeCtx {
+  hipGraph_t graph;
+  hipGraphNode_t dep;
+  bool has_dep;
+};
+
+// ---- launch wrappers (defined in qbvm_kernels.hip) ------------------------
+void upload_radix_roots(const c64* roots, int count);  // constant-memory roots per device
+hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,
+                      NodeCtx* nc = nullptr);
+hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,
+                       NodeCtx* nc = nullptr);
+hipError_t launch_thomas(const ThomasArgs& a, hipStream_t s, NodeCtx* nc = nullptr);
+hipError_t launch_time1d(const Time1dArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,
+                         NodeCtx* nc = nullptr);
+hipError_t launch_row(const RowArgs& a, long long nwg, int threads, size_t lds, hipStream_t s);
+hipError_t launch_bisect_init(double* bstate, int count, const double* deltas, double tau_dp,
+                              double lo, double hi, hipStream_t s);
+hipError_t launch_bisect_finish(const double* bstate, int count, double* alphas, int* hits,
+                                hipStream_t s);
+hipError_t launch_features(int count, long long nm, double hd, const double* ghat,
+                           const double* deltas, const int* perm, const int* off, float* feats,
+                           hipStream_t s);
+hipError_t launch_predict(const float* model, const float* feats, double* alpha_out,
+                          hipStream_t s);
+hipError_t launch_mlp_forward(const float* p, int B, const float* X, float* out, hipStream_t s);
+hipError_t launch_mlp_loss_grad(const float* p, int B, const float* X, const float* y,
+                                float* grad, float* loss, float* scratch, int nscratch_wg,
+                                hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int step, float lr,
+                       float b1, float b2, float eps, hipStream_t s);
+hipError_t launch_copy_scale(const double* in, double* out, long long n, double s, hipStream_t st);
+
+}  // namespace qbvm

@@ -1,0 +1,491 @@
+// gfx950 kernels of the PinT quasi-boundary value solver (arXiv 2107.06381).
+//
+// Solve pipeline for one instance (Section 3.3, eq. "3step"):
+//   d = 2, 3: the Dirichlet stencil is diagonalised by the orthonormal type-I sine
+//     transform Q in every dimension, so Step (b)'s N_t complex-shifted solves
+//     (d_j/tau - Lap_h) S2(:,j) = S1(:,j) become Q diag(1/(d_j/tau + mu_k)) Q.
+//     Q commutes with the time transforms (they act on different Kronecker
+//     factors), so Q is applied once to g_delta before and once per level after:
+//        k_dst   : g_hat = Q g_delta                        (d passes)
+//        k_time  : per mode k, Step (a) for the rank-one right-hand side
+//                  (S1(k,j) = f0_hat_k/sqrt(N_t) for every j), Step (b) as a
+//                  division, Step (c) as a length-N_t DFT with the inverse omega
+//                  scaling, real part -> y_hat[t][k]
+//        k_dst   : y[t] = Q y_hat[t]                        (d passes per level)
+//   d = 1: paper order, Step (b) by a complex Thomas sweep per shift d_j
+//     (k_thomas), Step (c) as a length-N_t DFT per grid point (k_time1d).
+// Two real sequences are packed into one complex transform wherever the result
+// of each is real (sine transforms; time transforms after the inverse scaling).
+#include "qbvm_internal.hpp"
+#include "qbvm_bodies.hpp"
+
+#include <cmath>
+
+namespace qbvm {
+
+__constant__ c64 c_root[2080];
+
+void upload_radix_roots(const c64* roots, int count) {
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_root), roots, sizeof(c64) * count, 0, hipMemcpyHostToDevice);
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_dst(DstArgs a) {
+  extern __shared__ c64 lds[];
+  dst_body<WIDE>(a, blockIdx.x, lds);
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_time(TimeArgs a) {
+  extern __shared__ c64 lds[];
+  time_body<WIDE>(a, blockIdx.x, lds);
+}
+
+__global__ __launch_bounds__(256) void k_thomas(ThomasArgs a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < a.Nt) thomas_body(a, j);
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_time1d(Time1dArgs a) {
+  extern __shared__ c64 lds[];
+  time1d_body<WIDE>(a, blockIdx.x, lds);
+}
+
+// ================================================================ k_row ====
+// One level l of Step (c) per sine mode, directly as one DFT row:
+//   Y_k(l) = Re( f0s/N_t * gamma_l^{-1} * g_hat_k * sum_j exp(-2 pi i jl/N_t) / (d_j/tau + mu_k) ).
+// Optionally writes Y_k(l), and reduces sum_k (Y_k(l) - g_hat_k)^2 per instance (the
+// discrepancy by Parseval), finishing in the last workgroup of each instance.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_row(RowArgs a) {
+  extern __shared__ c64 lds[];
+  const int Nt = a.Nt;
+  c64* dt = lds;          // d_j / tau
+  c64* w = dt + Nt;       // exp(-2 pi i j l / N_t)
+  __shared__ double red[8];
+  __shared__ int s_skip;
+  __shared__ double s_alpha;
+  const int inst = blockIdx.x / a.wg_per_inst;
+  const int wsub = blockIdx.x - inst * a.wg_per_inst;
+  double* bs = a.bstate ? a.bstate + (size_t)inst * kBState : nullptr;
+  if (threadIdx.x == 0) {
+    double alpha = a.alpha_dev ? *a.alpha_dev : a.alpha;
+    int skip = 0;
+    if (bs) {
+      const bool done = bs[6] != 0.0 || bs[7] != 0.0;  // hit flag or end reached
+      if (a.mode == 1) { alpha = exp10(0.5 * (bs[0] + bs[1])); skip = done; }
+      else if (a.mode == 2) { alpha = exp10(bs[1]); skip = done; }
+      else if (a.mode == 3) { alpha = exp10(bs[0]); skip = done; }
+    }
+    s_alpha = alpha;
+    s_skip = skip;
+  }
+  __syncthreads();
+  if (s_skip) return;
+  const SolveScalars sc = scalars_from_alpha(s_alpha, a.variant, a.tau);
+  const double croot = exp(sc.logabsw / (double)Nt);
+  const double inv_tau = 1.0 / a.tau;
+  for (int j = threadIdx.x; j < Nt; j += blockDim.x) {
+    dt[j] = shift_over_tau(j, Nt, croot, inv_tau);
+    double sn, cs;
+    const long long jl = ((long long)j * a.level) % Nt;
+    sincospi(2.0 * (double)jl / (double)Nt, &sn, &cs);
+    w[j] = {cs, -sn};
+  }
+  __syncthreads();
+  const c64 gi = inv_gamma(a.level, Nt, sc.logabsw, sc.f0s / (double)Nt);
+  const double* gh = a.ghat + (size_t)inst * a.nmodes;
+  double acc = 0.0;
+  const long long per = ((a.nmodes + a.wg_per_inst - 1) / a.wg_per_inst);
+  const long long kb = wsub * per;
+  const long long ke = kb + per < a.nmodes ? kb + per : a.nmodes;
+  for (long long k = kb + threadIdx.x; k < ke; k += blockDim.x) {
+    const double mu = mode_mu(k, a.d, a.m, a.mu1d);
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < Nt; ++j) {
+      const c64 z = dt[j];
+      const double x = z.re + mu;
+      const double q = 1.0 / (x * x + z.im * z.im);
+      // w_j / (x + i z.im) = w_j (x - i z.im) q
+      const c64 ww = w[j];
+      sr += (ww.re * x + ww.im * z.im) * q;
+      si += (ww.im * x - ww.re * z.im) * q;
+    }
+    const double g = gh[k];
+    const double Y = (gi.re * sr - gi.im * si) * g;
+    if (a.yrow) a.yrow[(size_t)inst * a.nmodes + k] = Y;
+    const double r = Y - g;
+    acc += r * r;
+  }
+  if (!a.partial) return;
+  acc = wave_sum(acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = acc;
+  __syncthreads();
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+    __hip_atomic_store(&a.partial[blockIdx.x], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned prev = __hip_atomic_fetch_add(&a.counter[inst], 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (prev == (unsigned)(a.wg_per_inst - 1));
+  }
+  __syncthreads();
+  if (!s_last) return;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    double t = 0.0;
+    for (int i = 0; i < a.wg_per_inst; ++i) t += __hip_atomic_load(&a.partial[(size_t)inst * a.wg_per_inst + i], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    const double D = sqrt(a.hd * t);
+    __hip_atomic_store(&a.counter[inst], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (a.dout) a.dout[inst] = D;
+    if (bs) {
+      const double target = bs[2];
+      if (a.mode == 1) {
+        const double mid = 0.5 * (bs[0] + bs[1]);
+        if (D > target) bs[1] = mid;
+        else bs[0] = mid;
+        bs[5] += 1.0;
+      } else if (a.mode == 2) {          // D(10^hi) <= target: root above the bracket
+        if (D <= target) { bs[6] = 1.0; bs[7] = 2.0; }
+        bs[5] += 1.0;
+      } else if (a.mode == 3) {          // D(10^lo) > target: root below the bracket
+        if (D > target) { bs[6] = 1.0; bs[7] = 1.0; }
+        bs[5] += 1.0;
+      }
+      bs[3] = D;
+      bs[4] = s_alpha;
+    }
+  }
+}
+
+__global__ void k_bisect_init(double* bs, int count, const double* deltas, double tau_dp, double lo,
+                              double hi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double* b = bs + (size_t)i * kBState;
+  b[0] = lo;
+  b[1] = hi;
+  b[2] = tau_dp * deltas[i];
+  b[3] = 0.0;
+  b[4] = 0.0;
+  b[5] = 0.0;
+  b[6] = 0.0;
+  b[7] = 0.0;
+}
+
+__global__ void k_bisect_finish(const double* bs, int count, double* alphas, int* hits) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const double* b = bs + (size_t)i * kBState;
+  double u = 0.5 * (b[0] + b[1]);
+  if (b[6] != 0.0) u = (b[7] == 2.0) ? b[1] : b[0];
+  alphas[i] = exp10(u);
+  if (hits) hits[i] = b[6] != 0.0 ? 1 : 0;
+}
+
+// ========================================================== k_features ====
+// One workgroup per instance: 32 bins of rho = |k|_2 over [sqrt(d), m sqrt(d)],
+// feature_b = log10(h^d sum_{k in b} g_hat_k^2 + 1e-300); feature_32 = log10(delta).
+// The modes of bin b are perm[off[b] .. off[b+1]) (built on the host); each bin is
+// reduced in a fixed order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_features(long long nm, double hd, const double* ghat,
+                                                  const double* deltas, const int* perm,
+                                                  const int* off, float* feats) {
+  __shared__ double red[4];
+  const int inst = blockIdx.x;
+  const double* g = ghat + (size_t)inst * nm;
+  for (int b = 0; b < 32; ++b) {
+    double t = 0.0;
+    for (int i = off[b] + threadIdx.x; i < off[b + 1]; i += blockDim.x) {
+      const double v = g[perm[i]];
+      t += v * v;
+    }
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double e = (red[0] + red[1]) + (red[2] + red[3]);
+      feats[(size_t)inst * 33 + b] = (float)log10(e * hd + 1e-300);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) feats[(size_t)inst * 33 + 32] = (float)log10(deltas[inst]);
+}
+
+// ================================================================ network ==
+// 33 -> 64 -> 64 -> 1 with exact-erf GELU; FP32.
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+constexpr int kW1 = 0, kB1 = 64 * 33, kW2 = kB1 + 64, kB2 = kW2 + 64 * 64, kW3 = kB2 + 64, kB3 = kW3 + 64,
+              kNP = kB3 + 1;
+
+// thread per sample; parameters staged in LDS
+__device__ __forceinline__ float mlp_eval(const float* P, const float* x, float* h1, float* h2) {
+  float a1[64];
+#pragma unroll 4
+  for (int o = 0; o < 64; ++o) {
+    float t = P[kB1 + o];
+    for (int i = 0; i < 33; ++i) t += P[kW1 + o * 33 + i] * x[i];
+    if (h1) h1[o] = t;
+    a1[o] = gelu_f(t);
+  }
+  float out = P[kB3];
+  for (int o = 0; o < 64; ++o) {
+    float t = P[kB2 + o];
+#pragma unroll 8
+    for (int i = 0; i < 64; ++i) t += P[kW2 + o * 64 + i] * a1[i];
+    if (h2) h2[o] = t;
+    out += P[kW3 + o] * gelu_f(t);
+  }
+  return out;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* params, int B, const float* X, float* out) {
+  __shared__ float P[kNP];
+  for (int i = threadIdx.x; i < kNP; i += blockDim.x) P[i] = params[i];
+  __syncthreads();
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  float x[33];
+  for (int i = 0; i < 33; ++i) x[i] = X[(size_t)b * 33 + i];
+  out[b] = mlp_eval(P, x, nullptr, nullptr);
+}
+
+// Per-sample forward and backward: stores a1, dH2, dH1 and the residual for the
+// parameter-gradient reduction that follows.
+__global__ __launch_bounds__(256) void k_mlp_sample_grad(const float* params, int B, const float* X,
+                                                         const float* y, float* A1, float* DH2,
+                                                         float* DH1, float* R) {
+  __shared__ float P[kNP];
+  for (int i = threadIdx.x; i < kNP; i += blockDim.x) P[i] = params[i];
+  __syncthreads();
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  float x[33], h1[64], h2[64];
+  for (int i = 0; i < 33; ++i) x[i] = X[(size_t)b * 33 + i];
+  const float out = mlp_eval(P, x, h1, h2);
+  const float r = out - y[b];
+  R[b] = r;
+  const float dout = 2.0f * r / (float)B;
+  float dh2[64];
+  for (int o = 0; o < 64; ++o) {
+    dh2[o] = dout * P[kW3 + o] * gelu_grad_f(h2[o]);
+    DH2[(size_t)b * 64 + o] = dh2[o];
+    A1[(size_t)b * 64 + o] = gelu_f(h1[o]);
+  }
+  for (int i = 0; i < 64; ++i) {
+    float t = 0.0f;
+    for (int o = 0; o < 64; ++o) t += dh2[o] * P[kW2 + o * 64 + i];
+    DH1[(size_t)b * 64 + i] = t * gelu_grad_f(h1[i]);
+  }
+}
+
+// One thread per parameter: sum over the batch in sample order (deterministic).
+__global__ __launch_bounds__(256) void k_mlp_param_grad(int B, const float* X, const float* A1,
+                                                        const float* DH2, const float* DH1,
+                                                        const float* R, const float* params,
+                                                        float* grad, float* loss) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kNP) return;
+  float g = 0.0f;
+  if (t < kB1) {  // W1[o][i] = sum_b DH1[b][o] X[b][i]
+    const int o = t / 33, i = t - o * 33;
+    for (int b = 0; b < B; ++b) g += DH1[(size_t)b * 64 + o] * X[(size_t)b * 33 + i];
+  } else if (t < kW2) {
+    const int o = t - kB1;
+    for (int b = 0; b < B; ++b) g += DH1[(size_t)b * 64 + o];
+  } else if (t < kB2) {
+    const int o = (t - kW2) / 64, i = (t - kW2) - o * 64;
+    for (int b = 0; b < B; ++b) g += DH2[(size_t)b * 64 + o] * A1[(size_t)b * 64 + i];
+  } else if (t < kW3) {
+    const int o = t - kB2;
+    for (int b = 0; b < B; ++b) g += DH2[(size_t)b * 64 + o];
+  } else if (t < kB3) {  // W3[o] = sum_b dout_b * gelu(h2_b[o]); gelu(h2) recovered from DH2? no: recompute
+    g = 0.0f;            // filled by k_mlp_w3_grad
+  } else {
+    for (int b = 0; b < B; ++b) g += 2.0f * R[b] / (float)B;
+  }
+  grad[t] = g;
+  if (t == 0) {
+    float l = 0.0f;
+    for (int b = 0; b < B; ++b) l += R[b] * R[b];
+    *loss = l / (float)B;
+  }
+}
+
+// W3 gradient needs a2 = gelu(h2): recompute h2 per sample, thread per (sample), then reduce.
+__global__ __launch_bounds__(64) void k_mlp_w3_grad(const float* params, int B, const float* A1,
+                                                    const float* R, float* grad) {
+  // one workgroup of 64 threads: thread o accumulates sum_b dout_b gelu(h2_b[o]) in sample order
+  const int o = threadIdx.x;
+  float w2[64];
+  for (int i = 0; i < 64; ++i) w2[i] = params[kW2 + o * 64 + i];
+  const float b2 = params[kB2 + o];
+  float g = 0.0f;
+  for (int b = 0; b < B; ++b) {
+    float t = b2;
+    for (int i = 0; i < 64; ++i) t += w2[i] * A1[(size_t)b * 64 + i];
+    g += (2.0f * R[b] / (float)B) * gelu_f(t);
+  }
+  grad[kW3 + o] = g;
+}
+
+__global__ void k_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Single-instance alpha prediction: standardise features, evaluate, de-standardise.
+// Thread o of one 64-lane wave owns hidden unit o of both layers.
+__global__ __launch_bounds__(64) void k_predict(const float* model, const float* feats, double* alpha_out) {
+  __shared__ float x[33];
+  __shared__ float a1[64];
+  const int o = threadIdx.x;
+  if (o < 33) x[o] = (feats[o] - model[kNP + o]) / model[kNP + 33 + o];
+  __syncthreads();
+  float t = model[kB1 + o];
+  for (int i = 0; i < 33; ++i) t += model[kW1 + o * 33 + i] * x[i];
+  a1[o] = gelu_f(t);
+  __syncthreads();
+  float u = model[kB2 + o];
+  for (int i = 0; i < 64; ++i) u += model[kW2 + o * 64 + i] * a1[i];
+  float c = model[kW3 + o] * gelu_f(u);
+  // sum over the wave in a fixed tree order
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+  if (o == 0) {
+    const float out = c + model[kB3];
+    const double l10 = (double)(out * model[kNP + 67] + model[kNP + 66]);
+    alpha_out[0] = exp10(l10);
+    alpha_out[1] = l10;
+  }
+}
+
+__global__ void k_copy_scale(const double* in, double* out, long long n, double s) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] * s;
+}
+
+// ================================================================ launches ==
+template <class A>
+static hipError_t enqueue1(const void* f, dim3 grid, dim3 block, size_t lds, hipStream_t s, const A& a,
+                           NodeCtx* nc) {
+  void* args[] = {const_cast<A*>(&a)};
+  if (!nc) return hipLaunchKernel(f, grid, block, args, lds, s);
+  hipKernelNodeParams p{};
+  p.func = const_cast<void*>(f);
+  p.gridDim = grid;
+  p.blockDim = block;
+  p.sharedMemBytes = (unsigned)lds;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  hipGraphNode_t node;
+  const hipError_t e = hipGraphAddKernelNode(&node, nc->graph, nc->has_dep ? &nc->dep : nullptr,
+                                             nc->has_dep ? 1 : 0, &p);
+  if (e == hipSuccess) {
+    nc->dep = node;
+    nc->has_dep = true;
+  }
+  return e;
+}
+
+hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, hipStream_t s, NodeCtx* nc) {
+  const void* f = a.fft.wide ? (const void*)&k_dst<true> : (const void*)&k_dst<false>;
+  return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
+}
+
+hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds, hipStream_t s, NodeCtx* nc) {
+  const void* f = a.fft.wide ? (const void*)&k_time<true> : (const void*)&k_time<false>;
+  return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
+}
+
+hipError_t launch_thomas(const ThomasArgs& a, hipStream_t s, NodeCtx* nc) {
+  const int threads = 64;
+  return enqueue1((const void*)&k_thomas, dim3((a.Nt + threads - 1) / threads), dim3(threads), 0, s, a, nc);
+}
+
+hipError_t launch_time1d(const Time1dArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,
+                         NodeCtx* nc) {
+  const void* f = a.fft.wide ? (const void*)&k_time1d<true> : (const void*)&k_time1d<false>;
+  return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
+}
+
+hipError_t launch_row(const RowArgs& a, long long nwg, int threads, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(k_row, dim3((unsigned)nwg), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bisect_init(double* bstate, int count, const double* deltas, double tau_dp, double lo,
+                              double hi, hipStream_t s) {
+  hipLaunchKernelGGL(k_bisect_init, dim3((count + 255) / 256), dim3(256), 0, s, bstate, count, deltas,
+                     tau_dp, lo, hi);
+  return hipGetLastError();
+}
+
+hipError_t launch_bisect_finish(const double* bstate, int count, double* alphas, int* hits, hipStream_t s) {
+  hipLaunchKernelGGL(k_bisect_finish, dim3((count + 255) / 256), dim3(256), 0, s, bstate, count, alphas,
+                     hits);
+  return hipGetLastError();
+}
+
+hipError_t launch_features(int count, long long nm, double hd, const double* ghat, const double* deltas,
+                           const int* perm, const int* off, float* feats, hipStream_t s) {
+  hipLaunchKernelGGL(k_features, dim3(count), dim3(256), 0, s, nm, hd, ghat, deltas, perm, off, feats);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict(const float* model, const float* feats, double* alpha_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_predict, dim3(1), dim3(64), 0, s, model, feats, alpha_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float* p, int B, const float* X, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_forward, dim3((B + 255) / 256), dim3(256), 0, s, p, B, X, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_loss_grad(const float* p, int B, const float* X, const float* y, float* grad,
+                                float* loss, float* scratch, int, hipStream_t s) {
+  float* A1 = scratch;
+  float* DH2 = A1 + (size_t)B * 64;
+  float* DH1 = DH2 + (size_t)B * 64;
+  float* R = DH1 + (size_t)B * 64;
+  hipLaunchKernelGGL(k_mlp_sample_grad, dim3((B + 255) / 256), dim3(256), 0, s, p, B, X, y, A1, DH2, DH1, R);
+  hipLaunchKernelGGL(k_mlp_param_grad, dim3((kNP + 255) / 256), dim3(256), 0, s, B, X, A1, DH2, DH1, R, p,
+                     grad, loss);
+  hipLaunchKernelGGL(k_mlp_w3_grad, dim3(1), dim3(64), 0, s, p, B, A1, R, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int step, float lr, float b1,
+                       float b2, float eps, hipStream_t s) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_scale(const double* in, double* out, long long n, double sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n, sc);
+  return hipGetLastError();
+}
+
+}  // namespace qbvm

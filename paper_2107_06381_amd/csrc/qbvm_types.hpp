@@ -1,0 +1,144 @@
+// Plain data types shared by the host planner, the kernels and the CPU build of
+// the kernel bodies (no HIP runtime dependency).
+#pragma once
+
+#include <cstdint>
+
+namespace qbvm {
+
+// Complex FP64 value; 16-byte aligned so LDS and global accesses are b128.
+struct alignas(16) c64 {
+  double re, im;
+};
+
+constexpr int kMaxStages = 16;
+constexpr int kElemsPerThread = 16;   // complex values a thread holds in one FFT stage
+constexpr int kMaxOddRadixWide = 47;  // largest odd prime radix of the wide kernel variant
+constexpr int kMaxOddRadixNarrow = 7; // largest odd prime radix of the narrow variant
+
+// One Stockham stage on a core transform of length nc: radix R, ns = product of the
+// radices already applied, twiddle of element r of butterfly j: tw[(j % ns) * r * twstride].
+struct FftStage {
+  int radix;
+  int ns;
+  int twstride;
+};
+
+enum FftKind : int { kStockham = 0, kRader = 1, kBluestein = 2 };
+
+// Forward DFT X_k = sum_j x_j exp(-2 pi i jk/n) of logical length n, computed on a
+// core Stockham transform of length nc (= n, n-1 for Rader, P for Bluestein).
+struct FftPlanDev {
+  int n;
+  int kind;
+  int nc;
+  int nstages;
+  int wide;  // 1 if some stage radix exceeds the narrow variant
+  FftStage st[kMaxStages];
+  const c64* tw;     // nc values exp(-2 pi i k/nc)
+  const c64* kspec;  // Rader: FFT_{n-1}(b)/(n-1); Bluestein: FFT_P(b)/P
+  const c64* chirp;  // Bluestein: exp(i pi (k^2 mod 2n)/n), k < n
+  const int* rin;    // Rader: rin[j] = q with g^q = j (mod n), j = 1..n-1
+  const int* rout;   // Rader: rout[k] = p with g^{-p} = k (mod n), k = 1..n-1
+};
+
+// Per-solve scalars derived from (alpha, variant, tau).
+struct SolveScalars {
+  double logabsw;   // ln|omega|
+  double f0s;       // f0 = f0s * g_delta
+};
+
+// Arguments of the spectral time kernel: one tile of sine modes x all N_t levels.
+struct TimeArgs {
+  int Nt;
+  int d;
+  int m;
+  int S;              // complex signals per workgroup (2 S modes)
+  long long nmodes;   // m^d
+  long long ystride;  // distance between levels in y
+  int lev_first;      // first level written
+  int lev_count;      // number of levels written
+  int lev_dst0;       // level index in y of lev_first (0 when writing one level)
+  double tau;
+  SolveScalars sc;
+  const double* mu1d;   // m eigenvalues of the 1D stencil
+  const double* ghat;   // nmodes sine coefficients of g_delta
+  double* y;
+  const double* alpha_dev;  // if non-null, alpha is read from here (device-side choice)
+  int variant;
+  FftPlanDev fft;
+};
+
+// Sine-transform pass: data viewed as [outer][len][inner]; transform along len.
+struct DstArgs {
+  const double* in;
+  double* out;
+  long long outer;
+  long long inner;
+  int len;     // m
+  int S;       // complex signals per workgroup (2 S lines)
+  long long tiles_per_outer;  // ceil(inner / (2S)) when inner > 1
+  double scale;
+  FftPlanDev fft;
+};
+
+// 1D paper-order Step (b): complex Thomas per shift j.
+struct ThomasArgs {
+  int Nt;
+  int m;
+  double tau;
+  double h;
+  SolveScalars sc;
+  const double* alpha_dev;  // if non-null, alpha is read from here
+  int variant;
+  const double* g;   // m
+  c64* s2;           // [m][Nt] solution of (d_j/tau - Lap_h) s = f0
+  c64* cp;           // [m][Nt] Thomas scratch
+};
+
+// 1D Step (c) from the Thomas output: inverse DFT per spatial point.
+struct Time1dArgs {
+  int Nt;
+  int m;
+  int S;
+  int lev_first, lev_count;
+  long long ystride;
+  SolveScalars sc;
+  const double* alpha_dev;
+  int variant;
+  double tau;
+  const c64* s2;
+  double* y;
+  FftPlanDev fft;
+};
+
+// One level of Step (c) computed directly (one DFT row per sine mode), with
+// optional output of the mode amplitudes and of the squared misfit to ghat.
+struct RowArgs {
+  int Nt;
+  int d;
+  int m;
+  int level;
+  int count;          // instances (batched label generation), each nmodes modes
+  long long nmodes;
+  double tau;
+  double hd;          // h^d
+  int variant;
+  const double* mu1d;
+  const double* ghat;     // count * nmodes
+  double* yrow;           // optional output count * nmodes
+  double* partial;        // per-workgroup partial sums (count * wg_per_inst)
+  unsigned int* counter;  // per-instance completion counters
+  int wg_per_inst;
+  // alpha source: fixed value, or per-instance device-side bisection state
+  double alpha;
+  const double* alpha_dev;  // if non-null (mode 0), alpha is read from here
+  double* bstate;         // if non-null: per instance {lo, hi, target, D, alpha, it, hit, pad}
+  int mode;               // 0: fixed alpha (D to dout); 1: bisection step; 2: endpoint check
+  double* dout;           // per-instance D (device)
+};
+
+// Bisection state layout (doubles per instance).
+constexpr int kBState = 8;  // lo, hi, target, D, alpha, iters, hit, done
+
+}  // namespace qbvm

@@ -1,0 +1,31 @@
+// Minimal stand-ins for the HIP device model so the kernel bodies compile as
+// plain C++: one std::thread per lane, a std::barrier for __syncthreads, and the
+// LDS block as an exactly sized heap buffer (so AddressSanitizer sees overruns).
+#pragma once
+
+#include <barrier>
+#include <cmath>
+
+#define __device__
+#define __global__
+#define __host__
+#define __forceinline__ inline
+#define __constant__
+#define __launch_bounds__(x)
+
+struct EmuDim {
+  unsigned x = 0, y = 0, z = 0;
+};
+inline thread_local EmuDim threadIdx;
+inline thread_local EmuDim blockDim;
+inline thread_local EmuDim blockIdx;
+inline std::barrier<>* g_emu_barrier = nullptr;
+
+inline void __syncthreads() { g_emu_barrier->arrive_and_wait(); }
+
+inline void sincospi(double x, double* s, double* c) {
+  const long double a = 3.141592653589793238462643383279502884L * (long double)x;
+  *s = (double)sinl(a);
+  *c = (double)cosl(a);
+}
+inline double exp10(double x) { return std::pow(10.0, x); }

@@ -1,0 +1,213 @@
+// CPU build of the solve-path kernel bodies and of the launch schedule, for the
+// host-side tests: indexing is checked by AddressSanitizer, results against the
+// oracle.  Usage:
+//   kernels_cpu fft   n S in.bin out.bin          (S signals, signal-major complex)
+//   kernels_cpu solve d m n L T alpha variant in.bin out.bin
+//   kernels_cpu dst   d m batch in.bin out.bin
+#include "hip_cpu_shim.hpp"
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../paper_2107_06381_amd/csrc/qbvm_bodies.hpp"
+#include "../../paper_2107_06381_amd/csrc/qbvm_fft_plan.hpp"
+#include "../../paper_2107_06381_amd/csrc/qbvm_schedule.hpp"
+
+namespace qbvm {
+c64 c_root[2080];
+}
+using namespace qbvm;
+
+template <class F>
+static void run_grid(long long nwg, int T, size_t lds_bytes, F body) {
+  std::barrier<> bar(T);
+  g_emu_barrier = &bar;
+  char* lds = new char[lds_bytes > 0 ? lds_bytes : 1];
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t)
+    th.emplace_back([&, t] {
+      threadIdx.x = t;
+      blockDim.x = T;
+      for (long long wg = 0; wg < nwg; ++wg) {
+        blockIdx.x = (unsigned)wg;
+        body(wg, reinterpret_cast<c64*>(lds));
+        bar.arrive_and_wait();
+      }
+    });
+  for (auto& x : th) x.join();
+  delete[] lds;
+  g_emu_barrier = nullptr;
+}
+
+struct Tables {
+  plan::HostFft h;
+  FftPlanDev dev;
+};
+
+static Tables make_tables(int n) {
+  Tables t;
+  std::string err;
+  if (!plan::build_tables(n, t.h, err)) {
+    fprintf(stderr, "plan failed: %s\n", err.c_str());
+    exit(3);
+  }
+  t.dev = t.h.dev;
+  t.dev.tw = t.h.tw.data();
+  t.dev.kspec = t.h.kspec.empty() ? nullptr : t.h.kspec.data();
+  t.dev.chirp = t.h.chirp.empty() ? nullptr : t.h.chirp.data();
+  t.dev.rin = t.h.rin.empty() ? nullptr : t.h.rin.data();
+  t.dev.rout = t.h.rout.empty() ? nullptr : t.h.rout.data();
+  return t;
+}
+
+static std::vector<char> read_file(const char* path) {
+  FILE* f = fopen(path, "rb");
+  if (!f) exit(4);
+  fseek(f, 0, SEEK_END);
+  long n = ftell(f);
+  fseek(f, 0, SEEK_SET);
+  std::vector<char> b(n);
+  if (n && fread(b.data(), 1, n, f) != (size_t)n) exit(4);
+  fclose(f);
+  return b;
+}
+
+static void write_file(const char* path, const void* p, size_t n) {
+  FILE* f = fopen(path, "wb");
+  if (!f || fwrite(p, 1, n, f) != n) exit(5);
+  fclose(f);
+}
+
+template <bool W>
+static void fft_signals(const Tables& t, int S, const c64* in, c64* out) {
+  const FftPlanDev& p = t.dev;
+  const size_t lds = sizeof(c64) * ((size_t)S * p.nc + 2 * S);
+  run_grid(1, 256, lds, [&](long long, c64* L) {
+    c64* buf = L;
+    c64* side = L + (size_t)S * p.nc;
+    for (int e = threadIdx.x; e < S * p.n; e += blockDim.x) {
+      const int j = e / S, s = e - j * S;
+      const int pos = fft_in_pos(p, j);
+      if (pos < 0) side[s] = in[(size_t)s * p.n + j];
+      else buf[(size_t)pos * S + s] = in[(size_t)s * p.n + j];
+    }
+    __syncthreads();
+    if (p.kind == kBluestein) fft_bluestein_prep(buf, S, p);
+    fft_run<W>(buf, S, p, side);
+    for (int e = threadIdx.x; e < S * p.n; e += blockDim.x) {
+      const int k = e / S, s = e - k * S;
+      out[(size_t)s * p.n + k] = fft_out(buf, S, p, s, k, side);
+    }
+  });
+}
+
+static sched::Geom geom(int d, int m, int n, double L, double T, const Tables& tt, const Tables& st,
+                        const std::vector<double>& mu) {
+  sched::Geom g{};
+  g.d = d;
+  g.m = m;
+  g.n = n;
+  g.Nt = n + 1;
+  g.h = L / (m + 1);
+  g.tau = T / n;
+  g.nmodes = 1;
+  for (int i = 0; i < d; ++i) g.nmodes *= m;
+  g.tfft = tt.dev;
+  g.sfft = st.dev;
+  g.S_time = plan::signals_for(tt.dev.nc);
+  g.S_dst = plan::signals_for(st.dev.nc);
+  g.mu1d = mu.data();
+  return g;
+}
+
+static void run_dst(const sched::Geom& g, const double* in, double* out, long long batch) {
+  for (const auto& Lz : sched::dst_passes(g, in, out, batch)) {
+    if (Lz.args.fft.wide) run_grid(Lz.nwg, 256, Lz.lds, [&](long long wg, c64* l) { dst_body<true>(Lz.args, wg, l); });
+    else run_grid(Lz.nwg, 256, Lz.lds, [&](long long wg, c64* l) { dst_body<false>(Lz.args, wg, l); });
+  }
+}
+
+int main(int argc, char** argv) {
+  if (argc < 2) return 2;
+  const std::vector<c64> roots = plan::radix_roots();
+  std::memcpy(c_root, roots.data(), sizeof(c64) * roots.size());
+  const std::string cmd = argv[1];
+  if (cmd == "fft" && argc == 6) {
+    const int n = atoi(argv[2]), S = atoi(argv[3]);
+    Tables t = make_tables(n);
+    if ((long long)S * t.dev.nc > 4096) return 6;
+    auto raw = read_file(argv[4]);
+    if (raw.size() != sizeof(c64) * (size_t)S * n) return 7;
+    std::vector<c64> in(S * (size_t)n), out(S * (size_t)n);
+    std::memcpy(in.data(), raw.data(), raw.size());
+    if (t.dev.wide) fft_signals<true>(t, S, in.data(), out.data());
+    else fft_signals<false>(t, S, in.data(), out.data());
+    write_file(argv[5], out.data(), sizeof(c64) * out.size());
+    printf("kind=%d nc=%d wide=%d stages=%d\n", t.dev.kind, t.dev.nc, t.dev.wide, t.dev.nstages);
+    return 0;
+  }
+  if (cmd == "dst" && argc == 7) {
+    const int d = atoi(argv[2]), m = atoi(argv[3]);
+    const long long batch = atoll(argv[4]);
+    Tables tt = make_tables(2), st = make_tables(2 * (m + 1));
+    std::vector<double> mu(m, 0.0);
+    const sched::Geom g = geom(d, m, 1, 1.0, 1.0, tt, st, mu);
+    auto raw = read_file(argv[5]);
+    const size_t N = (size_t)batch * g.nmodes;
+    if (raw.size() != N * sizeof(double)) return 7;
+    double* in = new double[N];
+    double* out = new double[N];
+    std::memcpy(in, raw.data(), raw.size());
+    run_dst(g, in, out, batch);
+    write_file(argv[6], out, N * sizeof(double));
+    delete[] in;
+    delete[] out;
+    return 0;
+  }
+  if (cmd == "solve" && argc == 11) {
+    const int d = atoi(argv[2]), m = atoi(argv[3]), n = atoi(argv[4]);
+    const double L = atof(argv[5]), T = atof(argv[6]), alpha = atof(argv[7]);
+    const int variant = atoi(argv[8]);
+    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1));
+    const double h = L / (m + 1);
+    std::vector<double> mu(m);
+    for (int k = 1; k <= m; ++k) {
+      const long double s = sinl((long double)k * plan::kPiL / (2.0L * (m + 1)));
+      mu[k - 1] = (double)(4.0L / ((long double)h * h) * s * s);
+    }
+    const sched::Geom g = geom(d, m, n, L, T, tt, st, mu);
+    auto raw = read_file(argv[9]);
+    if (raw.size() != (size_t)g.nmodes * sizeof(double)) return 7;
+    double* gd = new double[g.nmodes];
+    std::memcpy(gd, raw.data(), raw.size());
+    const size_t ny = (size_t)g.Nt * g.nmodes;
+    double* y = new double[ny];
+    const SolveScalars sc = sched::host_scalars(alpha, variant, g.tau);
+    if (d == 1) {
+      c64* s2 = new c64[(size_t)g.Nt * m];
+      c64* cp = new c64[(size_t)g.Nt * m];
+      const ThomasArgs ta = sched::thomas_step(g, sc, nullptr, variant, gd, s2, cp);
+      for (int j = 0; j < g.Nt; ++j) thomas_body(ta, j);
+      const auto t = sched::time1d_step(g, sc, nullptr, variant, s2, y);
+      if (t.args.fft.wide) run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time1d_body<true>(t.args, wg, l); });
+      else run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time1d_body<false>(t.args, wg, l); });
+      delete[] s2;
+      delete[] cp;
+    } else {
+      run_dst(g, gd, y, 1);
+      const auto t = sched::time_step(g, sc, nullptr, variant, y, y, 0, g.Nt);
+      if (t.args.fft.wide) run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_body<true>(t.args, wg, l); });
+      else run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_body<false>(t.args, wg, l); });
+      run_dst(g, y, y, g.Nt);
+    }
+    write_file(argv[10], y, ny * sizeof(double));
+    delete[] gd;
+    delete[] y;
+    return 0;
+  }
+  return 2;
+}
