@@ -197,6 +197,23 @@ int qbvm_mlp_loss_grad(const float* params, int B, const float* X, const float* 
 int qbvm_adam_step(float* params, const float* grad, float* m, float* v, int n, int step,
                    float lr, float beta1, float beta2, float eps, void* hip_stream);
 
+/* ------------------------------------------------------ kernel timing ---- */
+/* For benchmarks: while enabled, every kernel that a plan launches directly on
+ * its stream is bracketed by two HIP events recorded on that stream (kernels
+ * inside captured graphs are not).  Aggregates are kept per kernel kind. */
+void qbvm_profile_enable(int on);
+void qbvm_profile_reset(void);
+/* Waits for the recorded events, folds them into the aggregates and returns the
+ * number of kernel kinds seen so far. */
+int qbvm_profile_count(void);
+/* Kernel kind i (0 <= i < qbvm_profile_count()): its name (copied into name_buf,
+ * HOST, buf_len bytes), number of launches, summed duration in milliseconds and
+ * the summed algorithmic bytes (compulsory reads and writes of the kernel's
+ * design) and FLOPs (5 n log2 n per complex FFT of length n plus the pointwise
+ * work).  All outputs are HOST pointers. */
+int qbvm_profile_get(int i, char* name_buf, int buf_len, long long* launches, double* total_ms,
+                     double* bytes, double* flops);
+
 /* ------------------------------------------------------------- errors ---- */
 const char* qbvm_strerror(int code);
 const char* qbvm_last_error(void);

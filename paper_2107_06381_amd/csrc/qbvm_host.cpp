@@ -106,6 +106,126 @@ int get_fft(int device, int n, const FftTables** out) {
 
 }  // namespace
 
+
+// ------------------------------------------------------------- profiling
+namespace {
+
+struct ProfPending {
+  int kind;
+  hipEvent_t a, b;
+  double bytes, flops;
+};
+struct ProfAgg {
+  std::string name;
+  long long n = 0;
+  double ms = 0, bytes = 0, flops = 0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfPending> g_pending;
+std::vector<ProfAgg> g_agg;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t prof_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+int prof_kind(const char* name) {
+  for (size_t i = 0; i < g_agg.size(); ++i)
+    if (g_agg[i].name == name) return (int)i;
+  g_agg.push_back(ProfAgg{name});
+  return (int)g_agg.size() - 1;
+}
+
+// Brackets one direct launch with events when profiling is on (never for graph nodes).
+struct ProfScope {
+  bool on = false;
+  ProfPending p{};
+  hipStream_t s = nullptr;
+  ProfScope(const char* name, hipStream_t stream, double bytes, double flops, const NodeCtx* nc) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on || nc) return;
+    on = true;
+    s = stream;
+    p.kind = prof_kind(name);
+    p.a = prof_event();
+    p.b = prof_event();
+    p.bytes = bytes;
+    p.flops = flops;
+    (void)hipEventRecord(p.a, s);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(p.b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_pending.push_back(p);
+  }
+};
+
+double fft_flops(const FftPlanDev& f) {
+  const double core = 5.0 * f.nc * std::log2((double)f.nc);
+  return f.kind == kStockham ? core : 2.0 * core + 6.0 * f.nc;
+}
+
+}  // namespace
+
+extern "C" void qbvm_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+}
+
+extern "C" void qbvm_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& p : g_pending) {
+    (void)hipEventSynchronize(p.b);
+    g_event_pool.push_back(p.a);
+    g_event_pool.push_back(p.b);
+  }
+  g_pending.clear();
+  g_agg.clear();
+}
+
+extern "C" int qbvm_profile_count(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& p : g_pending) {
+    (void)hipEventSynchronize(p.b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    ProfAgg& a = g_agg[p.kind];
+    a.n += 1;
+    a.ms += ms;
+    a.bytes += p.bytes;
+    a.flops += p.flops;
+    g_event_pool.push_back(p.a);
+    g_event_pool.push_back(p.b);
+  }
+  g_pending.clear();
+  return (int)g_agg.size();
+}
+
+extern "C" int qbvm_profile_get(int i, char* name_buf, int buf_len, long long* launches, double* total_ms,
+                                double* bytes, double* flops) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (i < 0 || i >= (int)g_agg.size()) return set_error(QBVM_EINVAL, "profile index out of range");
+  const ProfAgg& a = g_agg[i];
+  if (name_buf && buf_len > 0) {
+    std::strncpy(name_buf, a.name.c_str(), buf_len - 1);
+    name_buf[buf_len - 1] = 0;
+  }
+  if (launches) *launches = a.n;
+  if (total_ms) *total_ms = a.ms;
+  if (bytes) *bytes = a.bytes;
+  if (flops) *flops = a.flops;
+  return QBVM_OK;
+}
+
 // ------------------------------------------------------------------ plans
 struct qbvm_plan_s {
   int device = 0;
@@ -288,8 +408,11 @@ sched::Geom geom(const qbvm_plan_s* p) {
 int run_dst(const qbvm_plan_s* p, const double* in, double* out, long long batch, NodeCtx* nc = nullptr,
             hipStream_t stream = nullptr) {
   hipStream_t s = nc ? stream : p->stream;
-  for (const auto& L : sched::dst_passes(geom(p), in, out, batch))
+  for (const auto& L : sched::dst_passes(geom(p), in, out, batch)) {
+    const double elems = (double)L.args.outer * L.args.inner * L.args.len;
+    ProfScope ps("dst_pass", s, 16.0 * elems, 0.5 * (double)L.args.outer * L.args.inner * fft_flops(L.args.fft), nc);
     HIP_TRY(launch_dst(L.args, L.nwg, kThreads, L.lds, s, nc));
+  }
   return QBVM_OK;
 }
 
@@ -305,8 +428,13 @@ int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, in
   const sched::Geom G = geom(p);
   const SolveScalars sc = sched::host_scalars(alpha, variant, p->tau);
   if (p->d == 1) {
-    HIP_TRY(launch_thomas(sched::thomas_step(G, sc, alpha_dev, variant, g, s2, cp), stream, nc));
+    const double cells = (double)p->Nt * p->m;
+    {
+      ProfScope ps("thomas_1d", stream, 8.0 * p->m + 64.0 * cells, 40.0 * cells, nc);
+      HIP_TRY(launch_thomas(sched::thomas_step(G, sc, alpha_dev, variant, g, s2, cp), stream, nc));
+    }
     const auto t = sched::time1d_step(G, sc, alpha_dev, variant, s2, y);
+    ProfScope ps("time_1d", stream, 24.0 * cells, 0.5 * p->m * (fft_flops(p->tfft->dev) + 8.0 * p->Nt), nc);
     HIP_TRY(launch_time1d(t.args, t.nwg, kThreads, t.lds, stream, nc));
     return QBVM_OK;
   }
@@ -314,7 +442,12 @@ int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, in
   int rc = run_dst(p, g, y, 1, nc, stream);
   if (rc) return rc;
   const auto t = sched::time_step(G, sc, alpha_dev, variant, y, y, 0, p->Nt);
-  HIP_TRY(launch_time(t.args, t.nwg, kThreads, t.lds, stream, nc));
+  {
+    const double nm = (double)p->nmodes;
+    ProfScope ps("time_spectral", stream, 8.0 * nm * (1.0 + p->Nt),
+                 0.5 * nm * (fft_flops(p->tfft->dev) + 28.0 * p->Nt), nc);
+    HIP_TRY(launch_time(t.args, t.nwg, kThreads, t.lds, stream, nc));
+  }
   return run_dst(p, y, y, p->Nt, nc, stream);
 }
 
@@ -344,6 +477,8 @@ int enqueue_row(const qbvm_plan_s* p, int count, const double* ghat, int level, 
   r.mode = mode;
   r.dout = dout;
   const size_t lds = sizeof(c64) * 2 * p->Nt;
+  ProfScope ps("dft_row", p->stream, 8.0 * count * p->nmodes * (yrow ? 2.0 : 1.0),
+               14.0 * count * (double)p->nmodes * p->Nt, nullptr);
   HIP_TRY(launch_row(r, (long long)count * wg_per_inst, kThreads, lds, p->stream));
   return QBVM_OK;
 }

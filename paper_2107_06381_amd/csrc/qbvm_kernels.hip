@@ -20,6 +20,8 @@
 #include "qbvm_bodies.hpp"
 
 #include <cmath>
+#include <mutex>
+#include <set>
 
 namespace qbvm {
 
@@ -386,10 +388,29 @@ __global__ void k_copy_scale(const double* in, double* out, long long n, double 
 }
 
 // ================================================================ launches ==
+// Dynamic LDS above 64 KiB: declare the device's per-workgroup maximum once per
+// kernel.  The runtime may not need (or accept) the attribute; a refusal is
+// cleared here so it cannot surface later as a stale error of another call.
+static void allow_big_lds(const void* f) {
+  static std::mutex mu;
+  static std::set<const void*> done;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!done.insert(f).second) return;
+  int dev = 0, maxlds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds) != hipSuccess)
+    (void)hipGetLastError();
+}
+
 template <class A>
 static hipError_t enqueue1(const void* f, dim3 grid, dim3 block, size_t lds, hipStream_t s, const A& a,
                            NodeCtx* nc) {
   void* args[] = {const_cast<A*>(&a)};
+  allow_big_lds(f);
   if (!nc) return hipLaunchKernel(f, grid, block, args, lds, s);
   hipKernelNodeParams p{};
   p.func = const_cast<void*>(f);
@@ -430,8 +451,7 @@ hipError_t launch_time1d(const Time1dArgs& a, long long nwg, int threads, size_t
 }
 
 hipError_t launch_row(const RowArgs& a, long long nwg, int threads, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_row, dim3((unsigned)nwg), dim3(threads), lds, s, a);
-  return hipGetLastError();
+  return enqueue1((const void*)&k_row, dim3((unsigned)nwg), dim3(threads), lds, s, a, nullptr);
 }
 
 hipError_t launch_bisect_init(double* bstate, int count, const double* deltas, double tau_dp, double lo,

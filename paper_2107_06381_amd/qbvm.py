@@ -30,7 +30,8 @@ EXPORTS = [
     "qbvm_solve", "qbvm_solve_batched", "qbvm_batched_cache_clear", "qbvm_discrepancy",
     "qbvm_choose_alpha", "qbvm_bisect_batched", "qbvm_features", "qbvm_set_alpha_model",
     "qbvm_mlp_forward", "qbvm_mlp_loss_grad", "qbvm_adam_step", "qbvm_strerror",
-    "qbvm_last_error", "qbvm_version",
+    "qbvm_last_error", "qbvm_version", "qbvm_profile_enable", "qbvm_profile_reset",
+    "qbvm_profile_count", "qbvm_profile_get",
 ]
 
 
@@ -92,6 +93,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qbvm_strerror": (ctypes.c_char_p, [i]),
         "qbvm_last_error": (ctypes.c_char_p, []),
         "qbvm_version": (i, []),
+        "qbvm_profile_enable": (None, [i]),
+        "qbvm_profile_reset": (None, []),
+        "qbvm_profile_count": (i, []),
+        "qbvm_profile_get": (i, [i, ctypes.c_char_p, i, ctypes.POINTER(ll), ctypes.POINTER(d),
+                                 ctypes.POINTER(d), ctypes.POINTER(d)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -287,3 +293,26 @@ def adam_step(params, grad, m, v, step: int, lr: float, b1: float = 0.9, b2: flo
                                  _dev_tensor(m, n, torch.float32, "m"),
                                  _dev_tensor(v, n, torch.float32, "v"), n, int(step), float(lr),
                                  float(b1), float(b2), float(eps), ctypes.c_void_p(_stream(stream))))
+
+
+def profile_enable(on: bool = True):
+    load().qbvm_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    load().qbvm_profile_reset()
+
+
+def profile_report() -> dict:
+    """{kernel kind: {launches, total_ms, bytes, flops}} folded from the recorded events."""
+    L_ = load()
+    out = {}
+    for i in range(L_.qbvm_profile_count()):
+        name = ctypes.create_string_buffer(64)
+        n = ctypes.c_longlong()
+        ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(L_.qbvm_profile_get(i, name, 64, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                   ctypes.byref(fl)))
+        out[name.value.decode()] = {"launches": n.value, "total_ms": ms.value, "bytes": by.value,
+                                    "flops": fl.value}
+    return out

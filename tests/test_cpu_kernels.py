@@ -1,0 +1,106 @@
+"""Host-side checks of the kernel code: the solve-path kernel bodies and the launch
+schedule compiled for the CPU (one thread per lane, AddressSanitizer on), compared
+with numpy's FFT and with the oracle.  Also: the C ABI loads and exports every
+declared symbol, and argument validation rejects bad grids without a GPU."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import qbvm_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "tests", "cpu_build", "kernels_cpu.cpp")
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    out = str(tmp_path_factory.mktemp("cpu_build") / "kernels_cpu")
+    r = subprocess.run([gxx, "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
+                        "-Wno-unknown-pragmas", "-pthread", SRC, "-o", out], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return out
+
+
+def _run(exe, args, tmp):
+    r = subprocess.run([exe, *map(str, args)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, (args, r.returncode, r.stderr[-3000:])
+    return r.stdout
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 16, 12, 43, 129, 257, 256, 512, 53, 97, 202, 127, 255, 1000, 2018])
+def test_fft_engine(exe, tmp_path, n):
+    """Stockham, Rader (prime n with smooth n-1) and Bluestein paths vs numpy.fft."""
+    S = max(1, min(3, 4096 // (2 * n + 64)))
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((S, n)) + 1j * rng.standard_normal((S, n))
+    fi, fo = tmp_path / "i.bin", tmp_path / "o.bin"
+    x.astype(np.complex128).tofile(fi)
+    info = _run(exe, ["fft", n, S, fi, fo], tmp_path)
+    y = np.fromfile(fo, dtype=np.complex128).reshape(S, n)
+    ref = np.fft.fft(x, axis=1)
+    assert np.linalg.norm(y - ref) <= 2e-15 * np.linalg.norm(ref) * max(1.0, np.log2(n)), info
+
+
+@pytest.mark.parametrize("d,m,batch", [(1, 9, 3), (2, 13, 2), (2, 100, 1), (3, 6, 2)])
+def test_dst_passes(exe, tmp_path, d, m, batch):
+    rng = np.random.default_rng(m)
+    x = rng.standard_normal((batch,) + (m,) * d)
+    fi, fo = tmp_path / "i.bin", tmp_path / "o.bin"
+    x.tofile(fi)
+    _run(exe, ["dst", d, m, batch, fi, fo], tmp_path)
+    y = np.fromfile(fo).reshape(x.shape)
+    ref = np.stack([O.dst_ortho(x[b]) for b in range(batch)])
+    assert np.linalg.norm(y - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("d,m,n,alpha,variant", [
+    (1, 7, 6, 1e-2, 0), (1, 127, 128, 1e-3, 0), (1, 33, 40, 1e-6, 1), (1, 64, 63, 1e-6, 0),
+    (2, 5, 4, 1e-3, 0), (2, 15, 16, 1e-4, 1), (2, 20, 11, 1e-2, 0), (2, 31, 100, 1e-8, 0),
+    (3, 4, 5, 1e-3, 0), (3, 9, 8, 1e-5, 1), (2, 1, 1, 0.5, 0), (1, 1, 3, 0.1, 1),
+])
+def test_solve_schedule_vs_oracle(exe, tmp_path, d, m, n, alpha, variant):
+    """Full solve (1D Thomas path, 2D/3D sine-transform path) vs the closed form."""
+    L, T = 1.0, 0.9
+    g = np.random.default_rng(d * 100 + m).standard_normal((m,) * d)
+    fi, fo = tmp_path / "i.bin", tmp_path / "o.bin"
+    g.tofile(fi)
+    _run(exe, ["solve", d, m, n, repr(L), repr(T), repr(alpha), variant, fi, fo], tmp_path)
+    y = np.fromfile(fo).reshape((n + 1,) + (m,) * d)
+    yc = O.closed_form(g, d, m, n, L, T, alpha, variant)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert rel(y, yc) < 1e-10
+    assert rel(y[0], yc[0]) < 1e-10
+    assert rel(y[-1], yc[-1]) < 1e-10
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2107_06381_amd import qbvm
+    L = qbvm.load()
+    hdr = open(os.path.join(ROOT, "include", "qbvm.h")).read()
+    declared = set(re.findall(r"\b(qbvm_[a-z_]+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(qbvm.EXPORTS) == declared
+    assert L.qbvm_version() >= 1
+
+
+def test_invalid_grids_rejected_without_gpu():
+    from paper_2107_06381_amd import qbvm
+    L = qbvm.load()
+    h = ctypes.c_void_p()
+    for g in [qbvm.Grid(4, 8, 8, 1.0, 1.0), qbvm.Grid(1, 0, 8, 1.0, 1.0), qbvm.Grid(2, 8, 0, 1.0, 1.0),
+              qbvm.Grid(1, 8, 8, -1.0, 1.0), qbvm.Grid(1, 8, 8, 1.0, float("nan"))]:
+        rc = L.qbvm_plan(ctypes.byref(h), ctypes.byref(g), None)
+        assert rc == -1, (g.d, g.m, g.n, rc)
+        assert not h.value
+    assert L.qbvm_plan(None, None, None) == -1
+    assert L.qbvm_strerror(-4).decode().startswith("discrepancy")

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU FP64 oracle.
+
+Tolerance: relative 2-norm 1e-8 on the full solution and, separately, on y^0 and
+y^N (the bar the design targets); measured errors are ~1e-13.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import qbvm_oracle as O  # noqa: E402
+from oracle import mlp_oracle as M  # noqa: E402
+from paper_2107_06381_amd import qbvm, workloads as W  # noqa: E402
+
+TOL = 1e-8
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(DEV)
+
+
+def gpu_solve(d, m, n, L, T, alpha, variant, g, output=qbvm.OUT_ALL):
+    p = qbvm.Plan(d, m, n, L, T)
+    y = p.solve(alpha, variant, to_dev(g), output=output)
+    torch.cuda.synchronize()
+    out = y.cpu().numpy()
+    p.close()
+    return out
+
+
+CASES = [
+    # d, m, n, alpha, variant  (prime / composite / Rader / Bluestein lengths, ragged tiles)
+    (1, 7, 6, 1e-2, 0), (1, 127, 128, 1e-3, 0), (1, 33, 40, 1e-6, 1), (1, 64, 63, 1e-6, 0),
+    (1, 1, 1, 0.5, 0), (1, 300, 211, 1e-4, 0), (1, 1023, 512, 1e-5, 0),
+    (2, 1, 1, 0.5, 0), (2, 5, 4, 1e-3, 0), (2, 15, 16, 1e-4, 1), (2, 20, 11, 1e-2, 0),
+    (2, 31, 100, 1e-8, 0), (2, 63, 256, 1e-4, 0), (2, 100, 52, 1e-6, 1), (2, 47, 129, 1e-12, 0),
+    (3, 4, 5, 1e-3, 0), (3, 9, 8, 1e-5, 1), (3, 31, 42, 1e-3, 0),
+]
+
+
+@pytest.mark.parametrize("d,m,n,alpha,variant", CASES)
+def test_solve_vs_oracle(d, m, n, alpha, variant):
+    say(f"[case] d={d} m={m} n={n} alpha={alpha} variant={variant}")
+    L, T = 1.0, 0.9
+    g = np.random.default_rng(d * 1000 + m * 7 + n).standard_normal((m,) * d)
+    y = gpu_solve(d, m, n, L, T, alpha, variant, g)
+    yc = O.closed_form(g, d, m, n, L, T, alpha, variant)
+    assert np.all(np.isfinite(y))
+    assert rel(y, yc) < TOL
+    assert rel(y[0], yc[0]) < TOL
+    assert rel(y[-1], yc[-1]) < TOL
+
+
+@pytest.mark.parametrize("d,m,n,alpha,variant", [(1, 31, 30, 1e-3, 0), (2, 12, 10, 1e-5, 1), (2, 5, 6, 1e-1, 0)])
+def test_solve_vs_sparse_lu(d, m, n, alpha, variant):
+    """Against the assembled all-at-once system solved by SuperLU (no structure used)."""
+    say(f"[case] splu d={d} m={m} n={n}")
+    g = np.random.default_rng(3).standard_normal((m,) * d)
+    y = gpu_solve(d, m, n, 1.0, 1.0, alpha, variant, g)
+    ys = O.solve_splu(g, d, m, n, 1.0, 1.0, alpha, variant)
+    assert rel(y, ys) < TOL and rel(y[0], ys[0]) < TOL and rel(y[-1], ys[-1]) < TOL
+
+
+def test_config_1d_full():
+    """1D, m=127, n=128, alpha=1e-3, 1% noise: against SuperLU of the all-at-once system."""
+    say("[case] config 1d")
+    inst = W.config_1d()
+    y = gpu_solve(1, 127, 128, 1.0, 1.0, 1e-3, 0, inst.g_delta)
+    ys = O.solve_splu(inst.g_delta, 1, 127, 128, 1.0, 1.0, 1e-3, O.PQ)
+    assert rel(y, ys) < TOL and rel(y[0], ys[0]) < TOL and rel(y[-1], ys[-1]) < TOL
+    assert O.residual(y, inst.g_delta, 1, 127, 128, 1.0, 1.0, 1e-3, O.PQ) < 1e-11
+
+
+def test_config_2d_full():
+    """2D, m=255, n=256 (N_t = 257, prime), alpha=1e-4: every level against the closed form."""
+    say("[case] config 2d")
+    inst = W.config_2d()
+    y = gpu_solve(2, 255, 256, 1.0, 1.0, 1e-4, 0, inst.g_delta)
+    yc = O.closed_form(inst.g_delta, 2, 255, 256, 1.0, 1.0, 1e-4, O.PQ)
+    assert rel(y, yc) < TOL and rel(y[0], yc[0]) < TOL and rel(y[-1], yc[-1]) < TOL
+    # sampled levels against the all-at-once rows (residual of levels 1..n)
+    assert O.residual(y, inst.g_delta, 2, 255, 256, 1.0, 1.0, 1e-4, O.PQ) < 1e-8
+
+
+def test_config_3d_sampled_levels():
+    """3D, m=127, n=128, T=0.5, alpha=1e-5 (2.1 GB output): levels 0, 1, 64, n against the closed form."""
+    say("[case] config 3d")
+    inst = W.config_3d()
+    m, n = 127, 128
+    p = qbvm.Plan(3, m, n, 1.0, 0.5)
+    y = p.solve(1e-5, 0, to_dev(inst.g_delta))
+    torch.cuda.synchronize()
+    levels = [0, 1, 64, n]
+    yl = y[levels].cpu().numpy()
+    assert bool(torch.isfinite(y).all())
+    del y
+    p.close()
+    yc = O.closed_form(inst.g_delta, 3, m, n, 1.0, 0.5, 1e-5, O.PQ, levels=levels)
+    for i, t in enumerate(levels):
+        assert rel(yl[i], yc[i]) < TOL, t
+
+
+@pytest.mark.parametrize("d,m,n", [(1, 50, 33), (2, 40, 31), (3, 10, 12)])
+def test_single_level_outputs(d, m, n):
+    say(f"[case] out modes d={d}")
+    g = np.random.default_rng(4).standard_normal((m,) * d)
+    for out, lev in [(qbvm.OUT_Y0, 0), (qbvm.OUT_YN, n)]:
+        y = gpu_solve(d, m, n, 1.0, 1.0, 1e-4, 0, g, output=out)
+        yc = O.closed_form(g, d, m, n, 1.0, 1.0, 1e-4, O.PQ, levels=[lev])[0]
+        assert rel(y, yc) < TOL
+
+
+def test_pq_pm_identity_and_determinism():
+    """PinT-MQBVM with alpha equals PinT-QBVM with alpha/tau (Section 4); repeated solves are bitwise equal."""
+    say("[case] identity")
+    d, m, n = 2, 33, 40
+    tau = 1.0 / n
+    g = to_dev(np.random.default_rng(5).standard_normal((m, m)))
+    p = qbvm.Plan(d, m, n)
+    ym = p.solve(1e-6, qbvm.QBVM_PM, g).clone()
+    yq = p.solve(1e-6 / tau, qbvm.QBVM_PQ, g).clone()
+    ym2 = p.solve(1e-6, qbvm.QBVM_PM, g).clone()
+    torch.cuda.synchronize()
+    assert rel(ym.cpu().numpy(), yq.cpu().numpy()) < 1e-12
+    assert torch.equal(ym, ym2)
+
+
+def test_invalid_arguments():
+    p = qbvm.Plan(1, 8, 8)
+    g = torch.zeros(8, dtype=torch.float64, device=DEV)
+    for a in [0.0, -1.0, float("nan"), float("inf")]:
+        with pytest.raises(qbvm.QbvmError) as e:
+            p.solve(a, 0, g)
+        assert e.value.code == -1
+    with pytest.raises(qbvm.QbvmError):
+        p.solve(1e-3, 7, g)
+    with pytest.raises(ValueError):
+        p.solve(1e-3, 0, torch.zeros(9, dtype=torch.float64, device=DEV))
+
+
+# ---------------------------------------------------------------- discrepancy / bisection
+def test_discrepancy_vs_oracle():
+    say("[case] discrepancy")
+    inst = W.sine_mode_instance(2, 63, 64, 1.0, 0.0, 0.01, np.random.default_rng(6))
+    p = qbvm.Plan(2, 63, 64)
+    g = to_dev(inst.g_delta)
+    for a in [1e-14, 1e-10, 1e-6, 1e-2]:
+        Dg = p.discrepancy(a, 0, g)
+        Do = O.discrepancy(a, inst.g_delta, 2, 63, 64, 1.0, 1.0)
+        assert abs(Dg - Do) <= 1e-9 * Do
+
+
+def test_choose_alpha_bisection_vs_oracle():
+    say("[case] bisection")
+    inst = W.sine_mode_instance(2, 127, 128, 1.0, 0.0, 0.01, np.random.default_rng(7))
+    p = qbvm.Plan(2, 127, 128)
+    a, info = p.choose_alpha(0, to_dev(inst.g_delta), inst.delta)
+    ao, hit = O.bisect_alpha(inst.g_delta, inst.delta, 2, 127, 128, 1.0, 1.0)
+    assert hit == 0 and info.bracket_hit == 0
+    # both bisect the same bracket; decisions agree except within rounding of D near the root
+    assert abs(math.log10(a) - math.log10(ao)) < 1e-6
+    assert abs(info.discrepancy / (1.1 * inst.delta) - 1.0) < 1e-5
+    assert info.iterations == 33
+
+
+def test_bisect_batched_matches_single():
+    say("[case] bisect batched")
+    rng = np.random.default_rng(8)
+    insts = [W.sine_mode_instance(2, 31, 32, 1.0, 0.0, eps, rng) for eps in [0.002, 0.01, 0.03, 0.05, 1e-9]]
+    p = qbvm.Plan(2, 31, 32)
+    G = to_dev(np.stack([i.g_delta for i in insts]))
+    Dl = to_dev(np.array([i.delta for i in insts]))
+    alphas, hits = p.bisect_batched(0, G, Dl)
+    torch.cuda.synchronize()
+    for k, inst in enumerate(insts):
+        ao, hit = O.bisect_alpha(inst.g_delta, inst.delta, 2, 31, 32, 1.0, 1.0)
+        assert int(hits[k]) == hit
+        assert abs(math.log10(float(alphas[k])) - math.log10(ao)) < 1e-6
+
+
+def test_features_vs_oracle():
+    say("[case] features")
+    gd, deltas, _, _ = W.config_learned(11, 6, m=127, n=128)
+    p = qbvm.Plan(2, 127, 128)
+    f = p.features(to_dev(gd), to_dev(deltas)).cpu().numpy()
+    for i in range(6):
+        fo = O.features(gd[i], deltas[i])
+        np.testing.assert_allclose(f[i], fo.astype(np.float32), rtol=2e-6, atol=2e-5)
+
+
+# ---------------------------------------------------------------- network kernels
+def test_mlp_forward_and_gradient_vs_fp64():
+    say("[case] mlp")
+    rng = np.random.default_rng(9)
+    theta = M.init_params(rng)
+    X = rng.standard_normal((300, 33))
+    y = rng.standard_normal(300)
+    P = torch.tensor(theta, dtype=torch.float32, device=DEV)
+    Xd = torch.tensor(X, dtype=torch.float32, device=DEV)
+    yd = torch.tensor(y, dtype=torch.float32, device=DEV)
+    out = qbvm.mlp_forward(P, Xd).cpu().numpy()
+    ref, _ = M.forward(theta.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(out, ref, rtol=1e-4, atol=1e-5)
+    loss, grad = qbvm.mlp_loss_grad(P, Xd, yd)
+    lo, go = M.loss_and_grad(theta.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64),
+                             y.astype(np.float32).astype(np.float64))
+    assert abs(float(loss) - lo) <= 1e-4 * lo
+    g = grad.cpu().numpy()
+    assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go)
+
+
+def test_adam_vs_reference():
+    rng = np.random.default_rng(10)
+    th = rng.standard_normal(1000)
+    gr = rng.standard_normal(1000)
+    m = np.zeros(1000); v = np.zeros(1000)
+    P = torch.tensor(th, dtype=torch.float32, device=DEV)
+    Gd = torch.tensor(gr, dtype=torch.float32, device=DEV)
+    Md = torch.zeros(1000, dtype=torch.float32, device=DEV)
+    Vd = torch.zeros(1000, dtype=torch.float32, device=DEV)
+    for t in range(1, 4):
+        qbvm.adam_step(P, Gd, Md, Vd, t, 1e-2)
+        th, m, v = M.adam_step(th, gr, m, v, t, lr=1e-2)
+    np.testing.assert_allclose(P.cpu().numpy(), th, rtol=1e-5, atol=1e-6)
+
+
+# ---------------------------------------------------------------- batched
+def test_batched_matches_single_and_oracle():
+    say("[case] batched")
+    rng = np.random.default_rng(12)
+    specs = [(1, 63, 64), (1, 200, 129), (1, 1023, 300), (2, 63, 64), (2, 100, 257), (2, 31, 90),
+             (1, 63, 64), (2, 63, 64), (3, 9, 10)]
+    grids, alphas, variants, gs, ys, ref = [], [], [], [], [], []
+    for d, m, n in specs:
+        grids.append((d, m, n, 1.0, 1.0))
+        alphas.append(10.0 ** rng.uniform(-6, -1))
+        variants.append(int(rng.integers(0, 2)))
+        g = rng.standard_normal((m,) * d)
+        gs.append(to_dev(g))
+        ys.append(torch.empty((n + 1,) + (m,) * d, dtype=torch.float64, device=DEV))
+        ref.append(g)
+    qbvm.solve_batched(grids, alphas, variants, gs, ys)
+    torch.cuda.synchronize()
+    for i, (d, m, n) in enumerate(specs):
+        y1 = gpu_solve(d, m, n, 1.0, 1.0, alphas[i], variants[i], ref[i])
+        yb = ys[i].cpu().numpy()
+        assert np.array_equal(yb, y1), i
+        yc = O.closed_form(ref[i], d, m, n, 1.0, 1.0, alphas[i], variants[i])
+        assert rel(yb, yc) < TOL
+    # replay with new alphas (graph reused, alpha table re-uploaded)
+    alphas2 = [a * 3.0 for a in alphas]
+    qbvm.solve_batched(grids, alphas2, variants, gs, ys)
+    torch.cuda.synchronize()
+    for i, (d, m, n) in enumerate(specs):
+        yc = O.closed_form(ref[i], d, m, n, 1.0, 1.0, alphas2[i], variants[i])
+        assert rel(ys[i].cpu().numpy(), yc) < TOL
+    qbvm.batched_cache_clear()
