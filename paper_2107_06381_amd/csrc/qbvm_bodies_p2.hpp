@@ -1,0 +1,219 @@
+// Solve-path kernel bodies on the power-of-two FFT of qbvm_fft_p2.hpp: global
+// memory is read and written straight from the FFT registers, coalesced, and
+// LDS carries only the inter-stage exchanges and small tables.
+#pragma once
+
+#include "qbvm_bodies.hpp"
+#include "qbvm_fft_p2.hpp"
+
+namespace qbvm {
+
+constexpr int kP2DstThreads = 256;   // S = 4096 / N signals per workgroup
+constexpr int kP2TimeThreads = 128;  // S = 2048 / N signals per workgroup
+
+template <int N>
+constexpr int p2_dst_S() { return kP2DstThreads * 16 / N; }
+template <int N>
+constexpr int p2_time_S() { return kP2TimeThreads * 16 / N; }
+template <int N>
+constexpr bool p2_tw_in_lds() { return N <= 1024; }
+
+template <int N, int S, bool SIGFAST>
+constexpr size_t p2_dst_lds_bytes() {
+  return sizeof(c64) * (P2Layout<N, S, SIGFAST>::lds_elems() + (p2_tw_in_lds<N>() ? N : 0));
+}
+
+// value of the odd extension v_n = [0, x_1..x_m, 0, -x_m..-x_1] at n (0 <= n < 2(m+1)), or -1
+__device__ __forceinline__ int odd_ext_index(int n, int m, double& sign) {
+  const int M = m + 1;
+  if (n >= 1 && n <= m) {
+    sign = 1.0;
+    return n - 1;
+  }
+  if (n > M) {
+    sign = -1.0;
+    return 2 * M - n - 1;
+  }
+  sign = 0.0;
+  return -1;
+}
+
+template <int N>
+__device__ __forceinline__ const c64* p2_twiddles(const FftPlanDev& f, c64* tw_lds, int t, int T) {
+  if constexpr (p2_tw_in_lds<N>()) {
+    for (int i = t; i < N; i += T) tw_lds[i] = f.tw[i];
+    return tw_lds;
+  } else {
+    return f.tw;
+  }
+}
+
+// Rows of [outer][m] (inner == 1): lanes walk along lines, two lines per signal.
+template <int N>
+__device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long wg, c64* lds) {
+  constexpr int S = p2_dst_S<N>();
+  using L = P2Layout<N, S, false>;
+  c64* buf = lds;
+  const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
+  const c64* tw = p2_twiddles<N>(a.fft, buf + L::lds_elems(), t, L::T);
+  __syncthreads();
+  const int m = a.len;
+  const long long la = wg * 2LL * S + 2 * s, lb = la + 1;
+  const bool oka = la < a.outer, okb = lb < a.outer;
+  const double* xa = a.in + la * m;
+  const double* xb = a.in + lb * m;
+  c64 v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    double sg;
+    const int i = odd_ext_index(p2_in_pos<N, 0>(u, e), m, sg);
+    double va = 0.0, vb = 0.0;
+    if (i >= 0) {
+      if (oka) va = sg * xa[i];
+      if (okb) vb = sg * xb[i];
+    }
+    v[e] = {va, vb};
+  }
+  p2_fft<N, L>(v, s, u, buf, tw);
+  double* oa = a.out + la * m;
+  double* ob = a.out + lb * m;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int i = p2_out_pos<N>(u, e);
+    if (i >= 1 && i <= m) {
+      if (oka) oa[i - 1] = -v[e].im * a.scale;
+      if (okb) ob[i - 1] = v[e].re * a.scale;
+    }
+  }
+}
+
+// Columns of [outer][m][inner] (inner > 1): lanes of a wave take consecutive columns.
+template <int N>
+__device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long wg, c64* lds) {
+  constexpr int S = p2_dst_S<N>();
+  using L = P2Layout<N, S, true>;
+  c64* buf = lds;
+  const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
+  const c64* tw = p2_twiddles<N>(a.fft, buf + L::lds_elems(), t, L::T);
+  __syncthreads();
+  const int m = a.len;
+  const long long o = wg / a.tiles_per_outer;
+  const long long ca = (wg - o * a.tiles_per_outer) * 2LL * S + 2 * s, cb = ca + 1;
+  const bool oka = ca < a.inner, okb = cb < a.inner;
+  const double* base = a.in + o * m * a.inner;
+  c64 v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    double sg;
+    const int i = odd_ext_index(p2_in_pos<N, 0>(u, e), m, sg);
+    double va = 0.0, vb = 0.0;
+    if (i >= 0) {
+      const double* row = base + (long long)i * a.inner;
+      if (oka) va = sg * row[ca];
+      if (okb) vb = sg * row[cb];
+    }
+    v[e] = {va, vb};
+  }
+  p2_fft<N, L>(v, s, u, buf, tw);
+  double* obase = a.out + o * m * a.inner;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int i = p2_out_pos<N>(u, e);
+    if (i >= 1 && i <= m) {
+      double* row = obase + (long long)(i - 1) * a.inner;
+      if (oka) row[ca] = -v[e].im * a.scale;
+      if (okb) row[cb] = v[e].re * a.scale;
+    }
+  }
+}
+
+template <int N>
+constexpr size_t p2_time_lds_fixed() {
+  return sizeof(c64) * (P2Layout<N, p2_time_S<N>(), true>::lds_elems() + (p2_tw_in_lds<N>() ? N : 0));
+}
+
+// bytes of the time kernel's LDS: exchange buffer, twiddles, Rader kernel spectrum,
+// d_j/tau and gamma_l^{-1} tables, and the two index maps
+template <int N>
+constexpr size_t p2_time_lds_bytes(int Nt) {
+  return p2_time_lds_fixed<N>() + sizeof(c64) * (N + 2 * (size_t)Nt) + sizeof(int) * 2 * (size_t)N;
+}
+
+// Spectral time kernel, every level written.  RADER: N_t = N + 1 prime; else N_t = N.
+template <int N, bool RADER>
+__device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c64* lds) {
+  constexpr int S = p2_time_S<N>();
+  static_assert(S >= 1, "time kernel needs N <= 2048");
+  using L = P2Layout<N, S, true>;
+  const int Nt = a.Nt;
+  c64* buf = lds;
+  c64* twl = buf + L::lds_elems();
+  c64* ks = twl + (p2_tw_in_lds<N>() ? N : 0);
+  c64* dt = ks + N;
+  c64* gi = dt + Nt;
+  int* gfw = reinterpret_cast<int*>(gi + Nt);
+  int* gbw = gfw + N;
+  const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
+
+  SolveScalars sc = a.sc;
+  if (a.alpha_dev) sc = scalars_from_alpha(*a.alpha_dev, a.variant, a.tau);
+  const double croot = exp(sc.logabsw / (double)Nt);
+  const double inv_tau = 1.0 / a.tau;
+  const double gscale = sc.f0s / (double)Nt;
+  for (int j = t; j < Nt; j += L::T) {
+    dt[j] = shift_over_tau(j, Nt, croot, inv_tau);
+    gi[j] = inv_gamma(j, Nt, sc.logabsw, gscale);
+  }
+  if constexpr (RADER) {
+    for (int i = t; i < N; i += L::T) {
+      ks[i] = a.fft.kspec[i];
+      gfw[i] = a.fft.gfwd[i];
+      gbw[i] = a.fft.ginvt[i];
+    }
+  }
+  const c64* tw = p2_twiddles<N>(a.fft, twl, t, L::T);
+  __syncthreads();
+
+  const long long ka = wg * 2LL * S + 2 * s, kb = ka + 1;
+  const bool oka = ka < a.nmodes, okb = kb < a.nmodes;
+  const double ga = oka ? a.ghat[ka] : 0.0, gb = okb ? a.ghat[kb] : 0.0;
+  const double mua = oka ? mode_mu(ka, a.d, a.m, a.mu1d) : 0.0;
+  const double mub = okb ? mode_mu(kb, a.d, a.m, a.mu1d) : 0.0;
+  // Steps (a)+(b): u_j = g_a/(d_j/tau + mu_a) + i g_b/(d_j/tau + mu_b)
+  auto input = [&](int j) -> c64 {
+    const c64 z = dt[j];
+    const double xa = z.re + mua, xb = z.re + mub;
+    const double ia = ga / (xa * xa + z.im * z.im);
+    const double ib = gb / (xb * xb + z.im * z.im);
+    return {ia * xa + ib * z.im, ib * xb - ia * z.im};
+  };
+  c64 v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int q = p2_in_pos<N, 0>(u, e);
+    v[e] = input(RADER ? gfw[q] : q);
+  }
+  p2_fft<N, L>(v, s, u, buf, tw);
+  auto store = [&](int l, c64 X) {
+    const c64 yv = cmul(gi[l], X);
+    double* yl = a.y + (long long)l * a.ystride;
+    if (oka) yl[ka] = yv.re;
+    if (okb) yl[kb] = yv.im;
+  };
+  if constexpr (RADER) {
+    const c64 x0 = input(0);
+    const c64 sum = v[0];  // position 0 on lane u == 0: sum_{j>=1} x_j
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = cconj(cmul(v[e], ks[p2_out_pos<N>(u, e)]));
+    p2_out_to_in<N, L>(v, s, u, buf);
+    p2_fft<N, L>(v, s, u, buf, tw);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) store(gbw[p2_out_pos<N>(u, e)], cadd(x0, cconj(v[e])));
+    if (u == 0) store(0, cadd(x0, sum));
+  } else {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) store(p2_out_pos<N>(u, e), v[e]);
+  }
+}
+
+}  // namespace qbvm

@@ -115,8 +115,10 @@ inline std::vector<c64> dft_over_len(const std::vector<std::complex<long double>
 struct HostFft {
   FftPlanDev dev{};  // pointers left null; the caller points them at its copies
   std::vector<c64> tw, kspec, chirp;
-  std::vector<int> rin, rout;
+  std::vector<int> rin, rout, gfwd, ginvt;
 };
+
+inline bool is_p2_core(int nc) { return nc >= 64 && nc <= 4096 && (nc & (nc - 1)) == 0; }
 
 inline void fill_stages(FftPlanDev& d, int nc) {
   const std::vector<int> r = radices(nc);
@@ -169,8 +171,11 @@ inline bool build_tables(int n, HostFft& t, std::string& err) {
     t.rin.assign(n, 0);
     t.rout.assign(n, 0);
     long long x = 1;
+    t.gfwd.assign(n - 1, 0);
+    t.ginvt.assign(n - 1, 0);
     for (int q = 0; q < n - 1; ++q) {  // g^q
       t.rin[(int)x] = q;
+      t.gfwd[q] = (int)x;
       x = x * g % n;
     }
     long long ginv = 1, b = g, e = n - 2;  // g^{-1} = g^{n-2}
@@ -183,6 +188,7 @@ inline bool build_tables(int n, HostFft& t, std::string& err) {
     x = 1;
     for (int p = 0; p < n - 1; ++p) {  // g^{-p}
       t.rout[(int)x] = p;
+      t.ginvt[p] = (int)x;
       bb[p] = unit_root(x, n, -1);
       x = x * ginv % n;
     }
@@ -199,6 +205,7 @@ inline bool build_tables(int n, HostFft& t, std::string& err) {
     }
     t.kspec = dft_over_len(bb);
   }
+  d.p2 = (d.kind != kBluestein && is_p2_core(nc)) ? nc : 0;
   return true;
 }
 

@@ -72,6 +72,8 @@ int build_fft(int n, FftTables& t) {
   HIP_TRY(upload(h.chirp, &d.chirp, t.allocs));
   HIP_TRY(upload(h.rin, &d.rin, t.allocs));
   HIP_TRY(upload(h.rout, &d.rout, t.allocs));
+  HIP_TRY(upload(h.gfwd, &d.gfwd, t.allocs));
+  HIP_TRY(upload(h.ginvt, &d.ginvt, t.allocs));
   return QBVM_OK;
 }
 
@@ -405,13 +407,17 @@ sched::Geom geom(const qbvm_plan_s* p) {
 }
 
 // d passes of the orthonormal DST-I over a [batch][m]^d array
-int run_dst(const qbvm_plan_s* p, const double* in, double* out, long long batch, NodeCtx* nc = nullptr,
-            hipStream_t stream = nullptr) {
+// input_transform: the data are g_delta (one or a batch of instances), else solution levels
+int run_dst(const qbvm_plan_s* p, const double* in, double* out, long long batch, bool input_transform,
+            NodeCtx* nc = nullptr, hipStream_t stream = nullptr) {
   hipStream_t s = nc ? stream : p->stream;
   for (const auto& L : sched::dst_passes(geom(p), in, out, batch)) {
     const double elems = (double)L.args.outer * L.args.inner * L.args.len;
-    ProfScope ps("dst_pass", s, 16.0 * elems, 0.5 * (double)L.args.outer * L.args.inner * fft_flops(L.args.fft), nc);
-    HIP_TRY(launch_dst(L.args, L.nwg, kThreads, L.lds, s, nc));
+    const int role = input_transform ? 0 : (L.args.inner == 1 ? 1 : 2);
+    static const char* names[3] = {"dst_input", "dst_rows", "dst_cols"};
+    ProfScope ps(names[role], s, 16.0 * elems, 0.5 * (double)L.args.outer * L.args.inner * fft_flops(L.args.fft),
+                 nc);
+    HIP_TRY(launch_dst(L.args, L.nwg, L.args.threads, L.lds, s, nc, role));
   }
   return QBVM_OK;
 }
@@ -439,16 +445,16 @@ int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, in
     return QBVM_OK;
   }
   // g_hat = Q g_delta, kept in the level-0 slot of y (each time tile reads only its own modes)
-  int rc = run_dst(p, g, y, 1, nc, stream);
+  int rc = run_dst(p, g, y, 1, true, nc, stream);
   if (rc) return rc;
   const auto t = sched::time_step(G, sc, alpha_dev, variant, y, y, 0, p->Nt);
   {
     const double nm = (double)p->nmodes;
     ProfScope ps("time_spectral", stream, 8.0 * nm * (1.0 + p->Nt),
                  0.5 * nm * (fft_flops(p->tfft->dev) + 28.0 * p->Nt), nc);
-    HIP_TRY(launch_time(t.args, t.nwg, kThreads, t.lds, stream, nc));
+    HIP_TRY(launch_time(t.args, t.nwg, t.args.threads, t.lds, stream, nc));
   }
-  return run_dst(p, y, y, p->Nt, nc, stream);
+  return run_dst(p, y, y, p->Nt, false, nc, stream);
 }
 
 // one level of Step (c) per mode; optional mode output and discrepancy reduction
@@ -533,20 +539,20 @@ int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta, 
     return set_error(QBVM_EINVAL, "output must be QBVM_OUT_ALL, QBVM_OUT_Y0 or QBVM_OUT_YN");
   if (output == QBVM_OUT_ALL)
     return enqueue_full(p, alpha, nullptr, variant, g_delta, y, p->s2, p->cp, nullptr, p->stream);
-  rc = run_dst(p, g_delta, p->ghat, 1);
+  rc = run_dst(p, g_delta, p->ghat, 1, true);
   if (rc) return rc;
   const int level = output == QBVM_OUT_Y0 ? 0 : p->n;
   rc = enqueue_row(p, 1, p->ghat, level, alpha, nullptr, variant, p->yrow, false, nullptr, 0, nullptr, nullptr,
                    nullptr, p->wg_row);
   if (rc) return rc;
-  return run_dst(p, p->yrow, y, 1);
+  return run_dst(p, p->yrow, y, 1, false);
 }
 
 int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_delta, double* D_out) {
   if (!p || !g_delta || !D_out) return set_error(QBVM_EINVAL, "NULL argument");
   int rc = check_alpha(alpha, variant);
   if (rc) return rc;
-  rc = run_dst(p, g_delta, p->ghat, 1);
+  rc = run_dst(p, g_delta, p->ghat, 1, true);
   if (rc) return rc;
   rc = enqueue_row(p, 1, p->ghat, p->n, alpha, nullptr, variant, nullptr, true, nullptr, 0, p->dscal + 3,
                    p->partial, p->counter, p->wg_row);
@@ -594,7 +600,7 @@ int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double 
   qbvm_alpha_info inf{};
   p->pinned[0] = delta;
   HIP_TRY(hipMemcpyAsync(p->dscal, p->pinned, sizeof(double), hipMemcpyHostToDevice, p->stream));
-  rc = run_dst(p, g_delta, p->ghat, 1);
+  rc = run_dst(p, g_delta, p->ghat, 1, true);
   if (rc) return rc;
   if (o->use_learned) {
     HIP_TRY(launch_features(1, p->nmodes, p->hd, p->ghat, p->dscal, p->bin_perm, p->bin_off, p->feats, p->stream));
@@ -665,7 +671,7 @@ int qbvm_bisect_batched(qbvm_plan_t p, int variant, int count, const double* g_d
   double* partial = reinterpret_cast<double*>(base + gh + bs);
   unsigned* counter = reinterpret_cast<unsigned*>(base + gh + bs + pa);
   HIP_TRY(hipMemsetAsync(counter, 0, co, p->stream));
-  rc = run_dst(p, g_deltas, ghat, count);
+  rc = run_dst(p, g_deltas, ghat, count, true);
   if (rc) return rc;
   return enqueue_bisection(p, variant, count, ghat, deltas, o, bstate, alphas_out, hits_out, partial, counter, wpi);
 }
@@ -677,7 +683,7 @@ int qbvm_features(qbvm_plan_t p, int count, const double* g_deltas, const double
   int rc = ensure_batch_ws(p, gh + 256);
   if (rc) return rc;
   double* ghat = p->bws;
-  rc = run_dst(p, g_deltas, ghat, count);
+  rc = run_dst(p, g_deltas, ghat, count, true);
   if (rc) return rc;
   HIP_TRY(launch_features(count, p->nmodes, p->hd, ghat, deltas, p->bin_perm, p->bin_off, feats, p->stream));
   return QBVM_OK;

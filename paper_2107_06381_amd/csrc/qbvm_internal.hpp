@@ -18,7 +18,7 @@ struct NodeCtx {
 // ---- launch wrappers (defined in qbvm_kernels.hip) ------------------------
 void upload_radix_roots(const c64* roots, int count);  // constant-memory roots per device
 hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,
-                      NodeCtx* nc = nullptr);
+                      NodeCtx* nc = nullptr, int role = 0);
 hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,
                        NodeCtx* nc = nullptr);
 hipError_t launch_thomas(const ThomasArgs& a, hipStream_t s, NodeCtx* nc = nullptr);

@@ -18,6 +18,8 @@
 // of each is real (sine transforms; time transforms after the inverse scaling).
 #include "qbvm_internal.hpp"
 #include "qbvm_bodies.hpp"
+#include "qbvm_bodies_p2.hpp"
+#include "qbvm_p2_sizes.hpp"
 
 #include <cmath>
 #include <mutex>
@@ -31,7 +33,67 @@ void upload_radix_roots(const c64* roots, int count) {
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_root), roots, sizeof(c64) * count, 0, hipMemcpyHostToDevice);
 }
 
-template <bool WIDE>
+// Power-of-two kernels.  INPUT only separates the symbol of the transform of g_delta
+// from the passes over the solution levels, so per-kernel profiles stay apart.
+template <int N, bool INPUT>
+__global__ __launch_bounds__(kP2DstThreads) void k_dst_rows_p2(DstArgs a) {
+  extern __shared__ c64 lds[];
+  dst_rows_p2_body<N>(a, blockIdx.x, lds);
+}
+
+template <int N, bool INPUT>
+__global__ __launch_bounds__(kP2DstThreads) void k_dst_cols_p2(DstArgs a) {
+  extern __shared__ c64 lds[];
+  dst_cols_p2_body<N>(a, blockIdx.x, lds);
+}
+
+template <int N, bool RADER>
+__global__ __launch_bounds__(kP2TimeThreads) void k_time_p2(TimeArgs a) {
+  extern __shared__ c64 lds[];
+  time_p2_body<N, RADER>(a, blockIdx.x, lds);
+}
+
+#define QBVM_P2_SWITCH(N, ...)     \
+  switch (N) {                      \
+    case 64: { constexpr int NN = 64; return __VA_ARGS__; }     \
+    case 128: { constexpr int NN = 128; return __VA_ARGS__; }   \
+    case 256: { constexpr int NN = 256; return __VA_ARGS__; }   \
+    case 512: { constexpr int NN = 512; return __VA_ARGS__; }   \
+    case 1024: { constexpr int NN = 1024; return __VA_ARGS__; } \
+    case 2048: { constexpr int NN = 2048; return __VA_ARGS__; } \
+    case 4096: { constexpr int NN = 4096; return __VA_ARGS__; } \
+    default: return nullptr;        \
+  }
+
+#define QBVM_P2_SWITCH_TIME(N, ...)     \
+  switch (N) {                      \
+    case 64: { constexpr int NN = 64; return __VA_ARGS__; }     \
+    case 128: { constexpr int NN = 128; return __VA_ARGS__; }   \
+    case 256: { constexpr int NN = 256; return __VA_ARGS__; }   \
+    case 512: { constexpr int NN = 512; return __VA_ARGS__; }   \
+    case 1024: { constexpr int NN = 1024; return __VA_ARGS__; } \
+    case 2048: { constexpr int NN = 2048; return __VA_ARGS__; } \
+    default: return nullptr;        \
+  }
+
+static const void* dst_p2_fn(int N, bool cols, bool input) {
+  if (cols) {
+    if (input) { QBVM_P2_SWITCH(N, (const void*)&k_dst_cols_p2<NN, true>) }
+    QBVM_P2_SWITCH(N, (const void*)&k_dst_cols_p2<NN, false>)
+  }
+  if (input) { QBVM_P2_SWITCH(N, (const void*)&k_dst_rows_p2<NN, true>) }
+  QBVM_P2_SWITCH(N, (const void*)&k_dst_rows_p2<NN, false>)
+}
+
+static const void* time_p2_fn(int N, bool rader) {
+  if (N > p2sz::kTimeMaxN) return nullptr;
+  if (rader) { QBVM_P2_SWITCH_TIME(N, (const void*)&k_time_p2<NN, true>) }
+  QBVM_P2_SWITCH_TIME(N, (const void*)&k_time_p2<NN, false>)
+}
+
+// ROLE only separates the kernel symbols (0: transform of g_delta, 1: rows of the
+// levels, 2: strided columns of the levels) so per-kernel profiles stay apart.
+template <bool WIDE, int ROLE>
 __global__ __launch_bounds__(256) void k_dst(DstArgs a) {
   extern __shared__ c64 lds[];
   dst_body<WIDE>(a, blockIdx.x, lds);
@@ -429,13 +491,25 @@ static hipError_t enqueue1(const void* f, dim3 grid, dim3 block, size_t lds, hip
   return e;
 }
 
-hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, hipStream_t s, NodeCtx* nc) {
-  const void* f = a.fft.wide ? (const void*)&k_dst<true> : (const void*)&k_dst<false>;
+hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, hipStream_t s, NodeCtx* nc,
+                      int role) {
+  static const void* tab[2][3] = {
+      {(const void*)&k_dst<false, 0>, (const void*)&k_dst<false, 1>, (const void*)&k_dst<false, 2>},
+      {(const void*)&k_dst<true, 0>, (const void*)&k_dst<true, 1>, (const void*)&k_dst<true, 2>}};
+  const void* f = tab[a.fft.wide ? 1 : 0][role < 0 ? 0 : (role > 2 ? 2 : role)];
+  if (a.fft.p2) {
+    f = dst_p2_fn(a.fft.p2, a.inner > 1, role == 0);
+    if (!f) return hipErrorInvalidValue;
+  }
   return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
 }
 
 hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds, hipStream_t s, NodeCtx* nc) {
   const void* f = a.fft.wide ? (const void*)&k_time<true> : (const void*)&k_time<false>;
+  if (a.fft.p2) {
+    f = time_p2_fn(a.fft.p2, a.fft.kind == kRader);
+    if (!f) return hipErrorInvalidValue;
+  }
   return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
 }
 

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "qbvm_types.hpp"
+#include "qbvm_p2_sizes.hpp"
 
 namespace qbvm {
 namespace sched {
@@ -57,6 +58,13 @@ inline std::vector<Launch<DstArgs>> dst_passes(const Geom& g, const double* in, 
     a.S = g.S_dst;
     a.scale = scale;
     a.fft = g.sfft;
+    a.threads = kThreads;
+    size_t lds = lds_dst(g);
+    if (g.sfft.p2) {  // compile-time power-of-two kernels
+      a.S = p2sz::dst_S(g.sfft.p2);
+      a.threads = p2sz::kDstThreads;
+      lds = p2sz::dst_lds(g.sfft.p2, inner > 1);
+    }
     long long nwg;
     if (inner == 1) {
       nwg = (a.outer + 2 * a.S - 1) / (2 * a.S);
@@ -65,7 +73,7 @@ inline std::vector<Launch<DstArgs>> dst_passes(const Geom& g, const double* in, 
       a.tiles_per_outer = (inner + 2 * a.S - 1) / (2 * a.S);
       nwg = a.outer * a.tiles_per_outer;
     }
-    v.push_back({a, nwg, lds_dst(g)});
+    v.push_back({a, nwg, lds});
     inner *= m;
   }
   return v;
@@ -92,8 +100,17 @@ inline Launch<TimeArgs> time_step(const Geom& g, SolveScalars sc, const double* 
   t.alpha_dev = alpha_dev;
   t.variant = variant;
   t.fft = g.tfft;
+  t.threads = kThreads;
+  size_t lds = lds_time(g, lev_count);
+  if (g.tfft.p2 && g.tfft.p2 <= p2sz::kTimeMaxN && lev_first == 0 && lev_count == g.Nt) {
+    t.S = p2sz::time_S(g.tfft.p2);
+    t.threads = p2sz::kTimeThreads;
+    lds = p2sz::time_lds(g.tfft.p2, g.Nt);
+  } else {
+    t.fft.p2 = 0;  // generic kernel
+  }
   const long long nwg = (g.nmodes + 2LL * t.S - 1) / (2LL * t.S);
-  return {t, nwg, lds_time(g, lev_count)};
+  return {t, nwg, lds};
 }
 
 inline ThomasArgs thomas_step(const Geom& g, SolveScalars sc, const double* alpha_dev, int variant,

@@ -40,6 +40,9 @@ struct FftPlanDev {
   const c64* chirp;  // Bluestein: exp(i pi (k^2 mod 2n)/n), k < n
   const int* rin;    // Rader: rin[j] = q with g^q = j (mod n), j = 1..n-1
   const int* rout;   // Rader: rout[k] = p with g^{-p} = k (mod n), k = 1..n-1
+  const int* gfwd;   // Rader: gfwd[q] = g^q mod n, q < n-1
+  const int* ginvt;  // Rader: ginvt[p] = g^{-p} mod n, p < n-1
+  int p2;            // core length if it has a compile-time power-of-two kernel (64..4096), else 0
 };
 
 // Per-solve scalars derived from (alpha, variant, tau).
@@ -66,6 +69,7 @@ struct TimeArgs {
   double* y;
   const double* alpha_dev;  // if non-null, alpha is read from here (device-side choice)
   int variant;
+  int threads;  // workgroup size of the launch
   FftPlanDev fft;
 };
 
@@ -79,6 +83,7 @@ struct DstArgs {
   int S;       // complex signals per workgroup (2 S lines)
   long long tiles_per_outer;  // ceil(inner / (2S)) when inner > 1
   double scale;
+  int threads;   // workgroup size of the launch
   FftPlanDev fft;
 };
 

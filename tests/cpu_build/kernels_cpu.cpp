@@ -13,7 +13,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../paper_2107_06381_amd/csrc/qbvm_bodies.hpp"
+#include "../../paper_2107_06381_amd/csrc/qbvm_bodies_p2.hpp"
 #include "../../paper_2107_06381_amd/csrc/qbvm_fft_plan.hpp"
 #include "../../paper_2107_06381_amd/csrc/qbvm_schedule.hpp"
 
@@ -61,6 +61,8 @@ static Tables make_tables(int n) {
   t.dev.chirp = t.h.chirp.empty() ? nullptr : t.h.chirp.data();
   t.dev.rin = t.h.rin.empty() ? nullptr : t.h.rin.data();
   t.dev.rout = t.h.rout.empty() ? nullptr : t.h.rout.data();
+  t.dev.gfwd = t.h.gfwd.empty() ? nullptr : t.h.gfwd.data();
+  t.dev.ginvt = t.h.ginvt.empty() ? nullptr : t.h.ginvt.data();
   return t;
 }
 
@@ -124,10 +126,44 @@ static sched::Geom geom(int d, int m, int n, double L, double T, const Tables& t
   return g;
 }
 
+#define P2_DISPATCH(N, CALL)                       \
+  switch (N) {                                    \
+    case 64: { constexpr int NN = 64; CALL; break; }     \
+    case 128: { constexpr int NN = 128; CALL; break; }   \
+    case 256: { constexpr int NN = 256; CALL; break; }   \
+    case 512: { constexpr int NN = 512; CALL; break; }   \
+    case 1024: { constexpr int NN = 1024; CALL; break; } \
+    case 2048: { constexpr int NN = 2048; CALL; break; } \
+    case 4096: { constexpr int NN = 4096; CALL; break; } \
+    default: exit(9);                              \
+  }
+
+#define P2_DISPATCH_T(N, CALL)                       \
+  switch (N) {                                    \
+    case 64: { constexpr int NN = 64; CALL; break; }     \
+    case 128: { constexpr int NN = 128; CALL; break; }   \
+    case 256: { constexpr int NN = 256; CALL; break; }   \
+    case 512: { constexpr int NN = 512; CALL; break; }   \
+    case 1024: { constexpr int NN = 1024; CALL; break; } \
+    case 2048: { constexpr int NN = 2048; CALL; break; } \
+    default: exit(9);                              \
+  }
+
 static void run_dst(const sched::Geom& g, const double* in, double* out, long long batch) {
   for (const auto& Lz : sched::dst_passes(g, in, out, batch)) {
-    if (Lz.args.fft.wide) run_grid(Lz.nwg, 256, Lz.lds, [&](long long wg, c64* l) { dst_body<true>(Lz.args, wg, l); });
-    else run_grid(Lz.nwg, 256, Lz.lds, [&](long long wg, c64* l) { dst_body<false>(Lz.args, wg, l); });
+    const DstArgs& A = Lz.args;
+    const int T = A.threads;
+    if (A.fft.p2) {
+      if (A.inner > 1) {
+        P2_DISPATCH(A.fft.p2, run_grid(Lz.nwg, T, Lz.lds, [&](long long wg, c64* l) { dst_cols_p2_body<NN>(A, wg, l); }))
+      } else {
+        P2_DISPATCH(A.fft.p2, run_grid(Lz.nwg, T, Lz.lds, [&](long long wg, c64* l) { dst_rows_p2_body<NN>(A, wg, l); }))
+      }
+    } else if (A.fft.wide) {
+      run_grid(Lz.nwg, T, Lz.lds, [&](long long wg, c64* l) { dst_body<true>(A, wg, l); });
+    } else {
+      run_grid(Lz.nwg, T, Lz.lds, [&](long long wg, c64* l) { dst_body<false>(A, wg, l); });
+    }
   }
 }
 
@@ -200,8 +236,19 @@ int main(int argc, char** argv) {
     } else {
       run_dst(g, gd, y, 1);
       const auto t = sched::time_step(g, sc, nullptr, variant, y, y, 0, g.Nt);
-      if (t.args.fft.wide) run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_body<true>(t.args, wg, l); });
-      else run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_body<false>(t.args, wg, l); });
+      const TimeArgs& A = t.args;
+      if (A.fft.p2) {
+        if (A.fft.p2 > 2048) exit(10);
+        if (A.fft.kind == kRader) {
+          P2_DISPATCH_T(A.fft.p2, run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_p2_body<NN, true>(A, wg, l); }))
+        } else {
+          P2_DISPATCH_T(A.fft.p2, run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_p2_body<NN, false>(A, wg, l); }))
+        }
+      } else if (A.fft.wide) {
+        run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_body<true>(A, wg, l); });
+      } else {
+        run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_body<false>(A, wg, l); });
+      }
       run_dst(g, y, y, g.Nt);
     }
     write_file(argv[10], y, ny * sizeof(double));

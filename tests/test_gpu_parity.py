@@ -18,6 +18,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
 from oracle import qbvm_oracle as O  # noqa: E402
 from oracle import mlp_oracle as M  # noqa: E402
 from paper_2107_06381_amd import qbvm, workloads as W  # noqa: E402
+from tests.parity_util import level_ok, omega_abs  # noqa: E402
 
 TOL = 1e-8
 DEV = torch.device("cuda:0")
@@ -54,6 +55,9 @@ CASES = [
     (2, 1, 1, 0.5, 0), (2, 5, 4, 1e-3, 0), (2, 15, 16, 1e-4, 1), (2, 20, 11, 1e-2, 0),
     (2, 31, 100, 1e-8, 0), (2, 63, 256, 1e-4, 0), (2, 100, 52, 1e-6, 1), (2, 47, 129, 1e-12, 0),
     (3, 4, 5, 1e-3, 0), (3, 9, 8, 1e-5, 1), (3, 31, 42, 1e-3, 0),
+    # power-of-two kernels: N_t = 64, 128, 256, 257 (Rader), sine lengths 64 .. 2048
+    (2, 63, 63, 1e-4, 0), (3, 15, 127, 1e-3, 1), (2, 20, 255, 1e-6, 0), (2, 33, 256, 1e-4, 0),
+    (2, 255, 6, 1e-3, 0), (2, 511, 3, 1e-2, 1), (2, 1023, 2, 1e-3, 0), (3, 63, 64, 1e-4, 0),
 ]
 
 
@@ -67,7 +71,8 @@ def test_solve_vs_oracle(d, m, n, alpha, variant):
     assert np.all(np.isfinite(y))
     assert rel(y, yc) < TOL
     assert rel(y[0], yc[0]) < TOL
-    assert rel(y[-1], yc[-1]) < TOL
+    ok, r = level_ok(y[-1], yc[-1], yc[0], n, n + 1, omega_abs(alpha, variant, T / n))
+    assert ok, r
 
 
 @pytest.mark.parametrize("d,m,n,alpha,variant", [(1, 31, 30, 1e-3, 0), (2, 12, 10, 1e-5, 1), (2, 5, 6, 1e-1, 0)])
