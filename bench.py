@@ -68,6 +68,126 @@ def cpu_baseline(inst, alpha, budget_s: float):
                       f"(orthonormal DST-I via scipy, per-mode formula, all {n + 1} levels), {wall:.1f} s"}
 
 
+def alpha_choice_bench(train_count: int, test_count: int, lat_count: int, steps: int):
+    """Learned vs bisection alpha choice on 2D m=127, n=128, T=1 (noise 0.1%..5%)."""
+    import numpy as np
+    import torch
+
+    from paper_2107_06381_amd import alpha_model as AM, qbvm
+
+    plan = qbvm.Plan(2, 127, 128, 1.0, 1.0)
+    t0 = time.perf_counter()
+    train_ds = AM.make_dataset(plan, seed=4, count=train_count)
+    t_label = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    model, hist = AM.train(train_ds, steps=steps, batch=256, lr=3e-3, log_every=steps)
+    t_train = time.perf_counter() - t0
+    del train_ds
+    test_ds = AM.make_dataset(plan, seed=5, count=test_count, keep_z0=True)
+    plan.set_alpha_model(model.blob())
+    idx = np.arange(test_count)
+    AM.choose_all(plan, test_ds, idx[:20], use_learned=True)  # warm-up
+    AM.choose_all(plan, test_ds, idx[:20], use_learned=False)
+    a_l, lat_l, fb = AM.choose_all(plan, test_ds, idx, use_learned=True)
+    li = idx[:lat_count]
+    a_b, lat_b, _ = AM.choose_all(plan, test_ds, li, use_learned=False)
+    e_l = AM.reconstruction_errors(plan, test_ds, a_l, idx)
+    e_dp = AM.reconstruction_errors(plan, test_ds, test_ds.alpha_dp, idx)
+    e_prior = AM.reconstruction_errors(plan, test_ds, test_ds.delta, idx)
+    ok = test_ds.hits == 0
+    r = e_l[ok] / e_dp[ok]
+    return {
+        "workload": f"2D m=127 n=128 T=1, {train_count} training / {test_count} held-out instances, "
+                    "labels: 30-step discrepancy bisection (tau=1.1) on [1e-20, 1]",
+        "label_gen_s": round(t_label, 2), "train_s": round(t_train, 2), "train_steps": steps,
+        "final_train_mse_std": round(hist[-1][1], 6) if hist else None,
+        "error_ratio_learned_over_dp": {"mean": round(float(r.mean()), 5), "median": round(float(np.median(r)), 5),
+                                        "p95": round(float(np.quantile(r, 0.95)), 5)},
+        "error_ratio_alpha_eq_delta_over_dp": round(float(np.mean(e_prior[ok] / e_dp[ok])), 4),
+        "fallback_rate": round(float(fb.mean()), 4),
+        "latency_us": {"learned_mean": round(float(lat_l.mean() * 1e6), 1),
+                       "learned_median": round(float(np.median(lat_l) * 1e6), 1),
+                       "bisection_mean": round(float(lat_b.mean() * 1e6), 1),
+                       "bisection_median": round(float(np.median(lat_b) * 1e6), 1),
+                       "speedup_median": round(float(np.median(lat_b) / np.median(lat_l)), 2),
+                       "bisection_sample": int(lat_count)},
+    }
+
+
+def batched_bench(reps: int = 3):
+    """512 uneven 1D/2D instances: one batched graph launch vs 512 qbvm_solve calls."""
+    import numpy as np
+    import torch
+
+    from paper_2107_06381_amd import qbvm, workloads as W
+
+    dev = torch.device("cuda:0")
+    insts = W.config_batched()
+    grids = [(i.d, i.m, i.n, i.L, i.T) for i in insts]
+    alphas = [i.alpha for i in insts]
+    variants = [0] * len(insts)
+    gs = [torch.from_numpy(i.g_delta).to(dev) for i in insts]
+    ys = [torch.empty((i.n + 1,) + (i.m,) * i.d, dtype=torch.float64, device=dev) for i in insts]
+    t0 = time.perf_counter()
+    plans = {}
+    for gr in grids:
+        if gr not in plans:
+            plans[gr] = qbvm.Plan(*gr)
+    t_plans = time.perf_counter() - t0
+
+    def seq(sel):
+        for k in sel:
+            plans[grids[k]].solve(alphas[k], 0, gs[k], ys[k])
+
+    def bat(sel):
+        qbvm.solve_batched([grids[k] for k in sel], [alphas[k] for k in sel], [0] * len(sel),
+                           [gs[k] for k in sel], [ys[k] for k in sel])
+
+    def timed(fn, sel):
+        best = 1e30
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn(sel)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return best
+
+    classes = {"all": list(range(len(insts))),
+               "1d": [k for k in range(len(insts)) if grids[k][0] == 1],
+               "2d_small": [k for k in range(len(insts)) if grids[k][0] == 2 and grids[k][1] < 160],
+               "2d_large": [k for k in range(len(insts)) if grids[k][0] == 2 and grids[k][1] >= 160]}
+    out = {}
+    t0 = time.perf_counter()
+    for name, sel in classes.items():
+        bat(sel)  # builds and caches the graph for this set
+        seq(sel)
+    t_graph = time.perf_counter() - t0
+    for name, sel in classes.items():
+        ts = timed(seq, sel)
+        tb = timed(bat, sel)
+        unk = sum(grids[k][2] * grids[k][1] ** grids[k][0] for k in sel)
+        out[name] = {"instances": len(sel), "sequential_ms": round(ts * 1e3, 3), "batched_ms": round(tb * 1e3, 3),
+                     "speedup": round(ts / tb, 3), "batched_Munknowns_per_s": round(unk / tb / 1e6, 1)}
+    # sampled parity of the batched output
+    from oracle import qbvm_oracle as O
+    errs = []
+    bat(classes["all"])
+    torch.cuda.synchronize()
+    for k in [0, 1, 255, 256, 300, 511]:
+        i = insts[k]
+        lv = [0, i.n]
+        yc = O.closed_form(i.g_delta, i.d, i.m, i.n, i.L, i.T, i.alpha, 0, levels=lv)
+        yk = ys[k][lv].cpu().numpy()
+        errs.append(max(float(np.linalg.norm(yk[j] - yc[j]) / np.linalg.norm(yc[j])) for j in range(2)))
+    qbvm.batched_cache_clear()
+    return {"workload": "512 instances: 256 1D m in [63,1023] + 256 2D m in [63,255], n in [64,512], "
+                        "alpha in [1e-6,1e-1], noise 0.1%..5%, every level output",
+            "plan_build_s": round(t_plans, 2), "graph_build_s": round(t_graph, 2),
+            "timing": "host clock around the enqueue and the final synchronize, best of %d" % reps,
+            "classes": out, "sampled_parity_max_rel_err": max(errs)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +195,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-alpha", action="store_true", help="skip the learned/bisection alpha-choice section")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched section")
+    ap.add_argument("--alpha-train", type=int, default=20000)
+    ap.add_argument("--alpha-test", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; run it with --gpus 1", file=sys.stderr)
@@ -90,6 +214,7 @@ def main():
     dev = torch.device("cuda:0")
     g = torch.from_numpy(inst.g_delta).to(dev)
     plan = qbvm.Plan(d, m, n, 1.0, 1.0)
+    tune = plan.autotune()  # kernel-variant choice, excluded from the timed region
     y = torch.empty((n + 1, m, m), dtype=torch.float64, device=dev)
     for _ in range(args.warmup):
         plan.solve(alpha, qbvm.QBVM_PQ, g, y)
@@ -145,6 +270,10 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
     step_bytes = sum(v["bytes"] for v in rep.values()) / args.steps
+    del y
+    torch.cuda.empty_cache()
+    alpha = None if args.no_alpha else alpha_choice_bench(args.alpha_train, args.alpha_test, 200, 3000)
+    batched = None if args.no_batched else batched_bench()
     line = {
         "metric": "PinT solve Munknowns/s (n*m^d, FP64)",
         "value": round(value, 2),
@@ -164,6 +293,9 @@ def main():
         "roofline": roofline,
         "step_hbm_roofline_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels": kernels,
+        "autotune": tune,
+        "alpha_choice": alpha,
+        "batched": batched,
         "parity_rel_err": parity,
         "cpu_baseline": cpu,
     }

@@ -117,6 +117,19 @@ int qbvm_plan_set_stream(qbvm_plan_t p, void* hip_stream);
 /* Device bytes held by the plan (tables + workspace). */
 long long qbvm_plan_workspace_bytes(qbvm_plan_t p);
 
+/* Autotuner (an addition): for the power-of-two kernels of this plan's shape, time
+ * every kernel variant (complex values per lane, signals per workgroup) of the
+ * sine passes over the levels and of the time transform on a scratch array of
+ * the full solution size, and keep the fastest in the plan.  Results are also
+ * cached per (device, kernel role, transform length) and used as the defaults of
+ * later plans.  Synchronous; allocates and frees (n+1) m^d doubles of scratch.
+ * ms_out (HOST, may be NULL) receives 12 timings in milliseconds (-1 where not
+ * applicable): rows variants 0, 1, 3, 4; columns variants 0, 1, 3, 4; time 0..3. */
+int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out);
+
+/* The kernel variants a plan uses (HOST outputs): sine rows, sine columns, time. */
+int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var_time);
+
 /* -------------------------------------------------------------- solving ---- */
 
 /* Solve one PinT system (Sections 3.1-3.3).  g_delta: DEVICE, m^d doubles.

@@ -5,23 +5,12 @@
 
 #include "qbvm_bodies.hpp"
 #include "qbvm_fft_p2.hpp"
+#include "qbvm_p2_sizes.hpp"
 
 namespace qbvm {
 
-constexpr int kP2DstThreads = 256;   // S = 4096 / N signals per workgroup
-constexpr int kP2TimeThreads = 128;  // S = 2048 / N signals per workgroup
-
 template <int N>
-constexpr int p2_dst_S() { return kP2DstThreads * 16 / N; }
-template <int N>
-constexpr int p2_time_S() { return kP2TimeThreads * 16 / N; }
-template <int N>
-constexpr bool p2_tw_in_lds() { return N <= 1024; }
-
-template <int N, int S, bool SIGFAST>
-constexpr size_t p2_dst_lds_bytes() {
-  return sizeof(c64) * (P2Layout<N, S, SIGFAST>::lds_elems() + (p2_tw_in_lds<N>() ? N : 0));
-}
+constexpr bool p2_tw_in_lds() { return p2sz::tw_in_lds(N); }
 
 // value of the odd extension v_n = [0, x_1..x_m, 0, -x_m..-x_1] at n (0 <= n < 2(m+1)), or -1
 __device__ __forceinline__ int odd_ext_index(int n, int m, double& sign) {
@@ -49,10 +38,9 @@ __device__ __forceinline__ const c64* p2_twiddles(const FftPlanDev& f, c64* tw_l
 }
 
 // Rows of [outer][m] (inner == 1): lanes walk along lines, two lines per signal.
-template <int N>
+template <int N, int E, int S>
 __device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long wg, c64* lds) {
-  constexpr int S = p2_dst_S<N>();
-  using L = P2Layout<N, S, false>;
+  using L = P2Layout<N, E, S, false>;
   c64* buf = lds;
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
   const c64* tw = p2_twiddles<N>(a.fft, buf + L::lds_elems(), t, L::T);
@@ -62,11 +50,11 @@ __device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long wg,
   const bool oka = la < a.outer, okb = lb < a.outer;
   const double* xa = a.in + la * m;
   const double* xb = a.in + lb * m;
-  c64 v[16];
+  c64 v[E];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
+  for (int e = 0; e < E; ++e) {
     double sg;
-    const int i = odd_ext_index(p2_in_pos<N, 0>(u, e), m, sg);
+    const int i = odd_ext_index(p2_in_pos<N, E, 0>(u, e), m, sg);
     double va = 0.0, vb = 0.0;
     if (i >= 0) {
       if (oka) va = sg * xa[i];
@@ -74,12 +62,12 @@ __device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long wg,
     }
     v[e] = {va, vb};
   }
-  p2_fft<N, L>(v, s, u, buf, tw);
+  p2_fft<N, E, L>(v, s, u, buf, tw);
   double* oa = a.out + la * m;
   double* ob = a.out + lb * m;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int i = p2_out_pos<N>(u, e);
+  for (int e = 0; e < E; ++e) {
+    const int i = p2_out_pos<N, E>(u, e);
     if (i >= 1 && i <= m) {
       if (oka) oa[i - 1] = -v[e].im * a.scale;
       if (okb) ob[i - 1] = v[e].re * a.scale;
@@ -88,10 +76,9 @@ __device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long wg,
 }
 
 // Columns of [outer][m][inner] (inner > 1): lanes of a wave take consecutive columns.
-template <int N>
+template <int N, int E, int S>
 __device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long wg, c64* lds) {
-  constexpr int S = p2_dst_S<N>();
-  using L = P2Layout<N, S, true>;
+  using L = P2Layout<N, E, S, true>;
   c64* buf = lds;
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
   const c64* tw = p2_twiddles<N>(a.fft, buf + L::lds_elems(), t, L::T);
@@ -101,11 +88,11 @@ __device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long wg,
   const long long ca = (wg - o * a.tiles_per_outer) * 2LL * S + 2 * s, cb = ca + 1;
   const bool oka = ca < a.inner, okb = cb < a.inner;
   const double* base = a.in + o * m * a.inner;
-  c64 v[16];
+  c64 v[E];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
+  for (int e = 0; e < E; ++e) {
     double sg;
-    const int i = odd_ext_index(p2_in_pos<N, 0>(u, e), m, sg);
+    const int i = odd_ext_index(p2_in_pos<N, E, 0>(u, e), m, sg);
     double va = 0.0, vb = 0.0;
     if (i >= 0) {
       const double* row = base + (long long)i * a.inner;
@@ -114,11 +101,11 @@ __device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long wg,
     }
     v[e] = {va, vb};
   }
-  p2_fft<N, L>(v, s, u, buf, tw);
+  p2_fft<N, E, L>(v, s, u, buf, tw);
   double* obase = a.out + o * m * a.inner;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int i = p2_out_pos<N>(u, e);
+  for (int e = 0; e < E; ++e) {
+    const int i = p2_out_pos<N, E>(u, e);
     if (i >= 1 && i <= m) {
       double* row = obase + (long long)(i - 1) * a.inner;
       if (oka) row[ca] = -v[e].im * a.scale;
@@ -127,24 +114,11 @@ __device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long wg,
   }
 }
 
-template <int N>
-constexpr size_t p2_time_lds_fixed() {
-  return sizeof(c64) * (P2Layout<N, p2_time_S<N>(), true>::lds_elems() + (p2_tw_in_lds<N>() ? N : 0));
-}
-
-// bytes of the time kernel's LDS: exchange buffer, twiddles, Rader kernel spectrum,
-// d_j/tau and gamma_l^{-1} tables, and the two index maps
-template <int N>
-constexpr size_t p2_time_lds_bytes(int Nt) {
-  return p2_time_lds_fixed<N>() + sizeof(c64) * (N + 2 * (size_t)Nt) + sizeof(int) * 2 * (size_t)N;
-}
-
 // Spectral time kernel, every level written.  RADER: N_t = N + 1 prime; else N_t = N.
-template <int N, bool RADER>
+template <int N, int E, int S, bool RADER, bool PAD = true>
 __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c64* lds) {
-  constexpr int S = p2_time_S<N>();
   static_assert(S >= 1, "time kernel needs N <= 2048");
-  using L = P2Layout<N, S, true>;
+  using L = P2Layout<N, E, S, true, PAD>;
   const int Nt = a.Nt;
   c64* buf = lds;
   c64* twl = buf + L::lds_elems();
@@ -187,13 +161,13 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
     const double ib = gb / (xb * xb + z.im * z.im);
     return {ia * xa + ib * z.im, ib * xb - ia * z.im};
   };
-  c64 v[16];
+  c64 v[E];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int q = p2_in_pos<N, 0>(u, e);
+  for (int e = 0; e < E; ++e) {
+    const int q = p2_in_pos<N, E, 0>(u, e);
     v[e] = input(RADER ? gfw[q] : q);
   }
-  p2_fft<N, L>(v, s, u, buf, tw);
+  p2_fft<N, E, L>(v, s, u, buf, tw);
   auto store = [&](int l, c64 X) {
     const c64 yv = cmul(gi[l], X);
     double* yl = a.y + (long long)l * a.ystride;
@@ -204,16 +178,28 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
     const c64 x0 = input(0);
     const c64 sum = v[0];  // position 0 on lane u == 0: sum_{j>=1} x_j
 #pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = cconj(cmul(v[e], ks[p2_out_pos<N>(u, e)]));
-    p2_out_to_in<N, L>(v, s, u, buf);
-    p2_fft<N, L>(v, s, u, buf, tw);
+    for (int e = 0; e < E; ++e) v[e] = cconj(cmul(v[e], ks[p2_out_pos<N, E>(u, e)]));
+    p2_out_to_in<N, E, L>(v, s, u, buf);
+    p2_fft<N, E, L>(v, s, u, buf, tw);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) store(gbw[p2_out_pos<N>(u, e)], cadd(x0, cconj(v[e])));
+    for (int e = 0; e < E; ++e) store(gbw[p2_out_pos<N, E>(u, e)], cadd(x0, cconj(v[e])));
     if (u == 0) store(0, cadd(x0, sum));
   } else {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) store(p2_out_pos<N>(u, e), v[e]);
+    for (int e = 0; e < E; ++e) store(p2_out_pos<N, E>(u, e), v[e]);
   }
 }
 
+}  // namespace qbvm
+
+namespace qbvm {
+// the host-side LDS sizes must cover the layouts used by the bodies
+template <int N>
+constexpr bool p2_first_radix_ok() {
+  return p2sz::first_radix(N, 16) == P2Radices<N, 16>::R[0] && p2sz::first_radix(N, 8) == P2Radices<N, 8>::R[0];
+}
+static_assert(p2_first_radix_ok<64>() && p2_first_radix_ok<128>() && p2_first_radix_ok<256>() &&
+                  p2_first_radix_ok<512>() && p2_first_radix_ok<1024>() && p2_first_radix_ok<2048>() &&
+                  p2_first_radix_ok<4096>(),
+              "first-radix table out of step with P2Radices");
 }  // namespace qbvm

@@ -1,15 +1,15 @@
 // Compile-time FFT of a power-of-two length N (64..4096) for gfx950, FP64.
 //
-// Every lane owns E = 16 complex values throughout: P = N/16 lanes form the team
-// of one signal and a workgroup of T lanes carries S = T/P signals.  A stage of
-// radix R (16 or 8) gives each lane 16/R butterflies; inputs and outputs of a
+// Every lane owns E (8 or 16) complex values throughout: P = N/E lanes form the
+// team of one signal and a workgroup of T lanes carries S = T/P signals.  A
+// stage of radix R <= E gives each lane E/R butterflies; inputs and outputs of a
 // stage stay in registers, and LDS is used only to exchange values between
 // consecutive stages.  Two lane layouts:
 //   SigFast: lanes of a wave belong to different signals (lane = s + S u); LDS
 //            holds [position][signal], so every exchange access is consecutive.
 //   PosFast: lanes of a wave walk along one signal (lane = u + P s); LDS holds
 //            [signal][position] with one pad slot per 16 positions.
-// Stockham autosort indexing: a butterfly j of a stage with radix R, after the
+// Stockham autosort indexing: butterfly j of a stage with radix R, after the
 // radices NS already applied, reads positions j + r N/R and writes
 // (j - k) R + k + r NS with k = j mod NS, after twiddling input r by
 // exp(-2 pi i k r / (NS R)).  After the last stage lane (u, b) holds X at
@@ -20,59 +20,82 @@
 
 namespace qbvm {
 
-template <int N>
+// Radix sequences per (N, E); every radix divides E.
+template <int N, int E>
 struct P2Radices;
-template <> struct P2Radices<64> { static constexpr int K = 2; static constexpr int R[2] = {8, 8}; };
-template <> struct P2Radices<128> { static constexpr int K = 2; static constexpr int R[2] = {16, 8}; };
-template <> struct P2Radices<256> { static constexpr int K = 2; static constexpr int R[2] = {16, 16}; };
-template <> struct P2Radices<512> { static constexpr int K = 3; static constexpr int R[3] = {8, 8, 8}; };
-template <> struct P2Radices<1024> { static constexpr int K = 3; static constexpr int R[3] = {16, 8, 8}; };
-template <> struct P2Radices<2048> { static constexpr int K = 3; static constexpr int R[3] = {16, 16, 8}; };
-template <> struct P2Radices<4096> { static constexpr int K = 3; static constexpr int R[3] = {16, 16, 16}; };
+#define QBVM_P2_RADICES(NN, EE, ...)                          \
+  template <>                                                 \
+  struct P2Radices<NN, EE> {                                  \
+    static constexpr int R[] = {__VA_ARGS__};                 \
+    static constexpr int K = sizeof(R) / sizeof(int);         \
+  };
+QBVM_P2_RADICES(64, 16, 8, 8)
+QBVM_P2_RADICES(128, 16, 16, 8)
+QBVM_P2_RADICES(256, 16, 16, 16)
+QBVM_P2_RADICES(512, 16, 8, 8, 8)
+QBVM_P2_RADICES(1024, 16, 16, 8, 8)
+QBVM_P2_RADICES(2048, 16, 16, 16, 8)
+QBVM_P2_RADICES(4096, 16, 16, 16, 16)
+QBVM_P2_RADICES(64, 8, 8, 8)
+QBVM_P2_RADICES(128, 8, 8, 8, 2)
+QBVM_P2_RADICES(256, 8, 8, 8, 4)
+QBVM_P2_RADICES(512, 8, 8, 8, 8)
+QBVM_P2_RADICES(1024, 8, 8, 8, 8, 2)
+QBVM_P2_RADICES(2048, 8, 8, 8, 8, 4)
+QBVM_P2_RADICES(4096, 8, 8, 8, 8, 8)
+#undef QBVM_P2_RADICES
 
-template <int N>
+template <int N, int E>
 constexpr int p2_ns(int stage) {
   int ns = 1;
-  for (int i = 0; i < stage; ++i) ns *= P2Radices<N>::R[i];
+  for (int i = 0; i < stage; ++i) ns *= P2Radices<N, E>::R[i];
   return ns;
 }
 
-template <int N, int S, bool SIGFAST>
+constexpr int p2_log2(int x) { return x <= 1 ? 0 : 1 + p2_log2(x / 2); }
+
+// SigFast pads one slot per R0 positions (R0 = first radix): the stage-0 writes of
+// consecutive lane groups are R0 apart, and the pad makes their LDS bank groups
+// alternate.  PosFast pads one slot per 16 positions.
+template <int N, int E, int S, bool SIGFAST, bool SPAD = true>
 struct P2Layout {
-  static constexpr int P = N / 16;
+  static constexpr int P = N / E;
   static constexpr int T = S * P;
+  static constexpr int R0 = P2Radices<N, E>::R[0];
+  static constexpr int LR0 = SPAD ? p2_log2(R0) : 30;  // no pad: pos >> 30 == 0
   static constexpr int NPAD = N + N / 16;
-  static constexpr size_t lds_elems() { return SIGFAST ? (size_t)N * S : (size_t)NPAD * S; }
+  static constexpr int NPADS = SPAD ? N + N / R0 : N;
+  static constexpr size_t lds_elems() { return SIGFAST ? (size_t)NPADS * S : (size_t)NPAD * S; }
   static __device__ __forceinline__ int sig(int t) { return SIGFAST ? (t % S) : (t / P); }
   static __device__ __forceinline__ int lane(int t) { return SIGFAST ? (t / S) : (t % P); }
   static __device__ __forceinline__ int at(int s, int pos) {
-    return SIGFAST ? pos * S + s : s * NPAD + pos + (pos >> 4);
+    return SIGFAST ? (pos + (pos >> LR0)) * S + s : s * NPAD + pos + (pos >> 4);
   }
 };
 
-// Position held in register slot e (= b R + r) before stage `stage`.
-template <int N, int STAGE>
+// Position held in register slot e (= b R + r) before stage STAGE.
+template <int N, int E, int STAGE>
 __device__ __forceinline__ int p2_in_pos(int u, int e) {
-  constexpr int R = P2Radices<N>::R[STAGE];
-  return u + (e / R) * (N / 16) + (e % R) * (N / R);
+  constexpr int R = P2Radices<N, E>::R[STAGE];
+  return u + (e / R) * (N / E) + (e % R) * (N / R);
 }
 
 // Position of register slot e after the last stage.
-template <int N>
+template <int N, int E>
 __device__ __forceinline__ int p2_out_pos(int u, int e) {
-  return p2_in_pos<N, P2Radices<N>::K - 1>(u, e);
+  return p2_in_pos<N, E, P2Radices<N, E>::K - 1>(u, e);
 }
 
-// Twiddle and butterflies of stage STAGE on the lane's 16 registers.
-template <int N, int STAGE>
-__device__ __forceinline__ void p2_compute(c64 (&v)[16], int u, const c64* __restrict__ tw) {
-  constexpr int R = P2Radices<N>::R[STAGE];
-  constexpr int NS = p2_ns<N>(STAGE);
-  constexpr int B = 16 / R;
+// Twiddle and butterflies of stage STAGE on the lane's E registers.
+template <int N, int E, int STAGE>
+__device__ __forceinline__ void p2_compute(c64 (&v)[E], int u, const c64* __restrict__ tw) {
+  constexpr int R = P2Radices<N, E>::R[STAGE];
+  constexpr int NS = p2_ns<N, E>(STAGE);
+  constexpr int B = E / R;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     if constexpr (NS > 1) {
-      const int j = u + b * (N / 16);
+      const int j = u + b * (N / E);
       const int k = j & (NS - 1);
       if (k != 0) {
 #pragma unroll
@@ -83,50 +106,51 @@ __device__ __forceinline__ void p2_compute(c64 (&v)[16], int u, const c64* __res
   }
 }
 
-// Exchange after stage STAGE: write outputs, read inputs of stage STAGE+1.
-template <int N, int STAGE, class L>
-__device__ __forceinline__ void p2_exchange(c64 (&v)[16], int s, int u, c64* __restrict__ buf) {
-  constexpr int R = P2Radices<N>::R[STAGE];
-  constexpr int NS = p2_ns<N>(STAGE);
-  constexpr int B = 16 / R;
+// Exchange after stage STAGE: write its outputs, read the inputs of STAGE+1.
+template <int N, int E, int STAGE, class L>
+__device__ __forceinline__ void p2_exchange(c64 (&v)[E], int s, int u, c64* __restrict__ buf) {
+  constexpr int R = P2Radices<N, E>::R[STAGE];
+  constexpr int NS = p2_ns<N, E>(STAGE);
+  constexpr int B = E / R;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    const int j = u + b * (N / 16);
+    const int j = u + b * (N / E);
     const int k = j & (NS - 1);
 #pragma unroll
     for (int r = 0; r < R; ++r) buf[L::at(s, (j - k) * R + k + r * NS)] = v[b * R + r];
   }
   __syncthreads();
 #pragma unroll
-  for (int e = 0; e < 16; ++e) v[e] = buf[L::at(s, p2_in_pos<N, STAGE + 1>(u, e))];
+  for (int e = 0; e < E; ++e) v[e] = buf[L::at(s, p2_in_pos<N, E, STAGE + 1>(u, e))];
   __syncthreads();
 }
 
-// Whole forward DFT on registers loaded in stage-0 order (slot e = position p2_in_pos<N,0>).
-template <int N, class L>
-__device__ __forceinline__ void p2_fft(c64 (&v)[16], int s, int u, c64* buf, const c64* tw) {
-  p2_compute<N, 0>(v, u, tw);
-  if constexpr (P2Radices<N>::K >= 2) {
-    p2_exchange<N, 0, L>(v, s, u, buf);
-    p2_compute<N, 1>(v, u, tw);
+template <int N, int E, int STAGE, class L>
+__device__ __forceinline__ void p2_stages(c64 (&v)[E], int s, int u, c64* buf, const c64* tw) {
+  p2_compute<N, E, STAGE>(v, u, tw);
+  if constexpr (STAGE + 1 < P2Radices<N, E>::K) {
+    p2_exchange<N, E, STAGE, L>(v, s, u, buf);
+    p2_stages<N, E, STAGE + 1, L>(v, s, u, buf, tw);
   }
-  if constexpr (P2Radices<N>::K >= 3) {
-    p2_exchange<N, 1, L>(v, s, u, buf);
-    p2_compute<N, 2>(v, u, tw);
-  }
+}
+
+// Whole forward DFT on registers loaded in stage-0 order (slot e = position p2_in_pos<N,E,0>).
+template <int N, int E, class L>
+__device__ __forceinline__ void p2_fft(c64 (&v)[E], int s, int u, c64* buf, const c64* tw) {
+  p2_stages<N, E, 0, L>(v, s, u, buf, tw);
 }
 
 // Re-order registers from the final layout to the stage-0 layout (identity when
 // the first and last radices agree, else one exchange through LDS).
-template <int N, class L>
-__device__ __forceinline__ void p2_out_to_in(c64 (&v)[16], int s, int u, c64* buf) {
-  constexpr int K = P2Radices<N>::K;
-  if constexpr (P2Radices<N>::R[0] != P2Radices<N>::R[K - 1]) {
+template <int N, int E, class L>
+__device__ __forceinline__ void p2_out_to_in(c64 (&v)[E], int s, int u, c64* buf) {
+  constexpr int K = P2Radices<N, E>::K;
+  if constexpr (P2Radices<N, E>::R[0] != P2Radices<N, E>::R[K - 1]) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) buf[L::at(s, p2_out_pos<N>(u, e))] = v[e];
+    for (int e = 0; e < E; ++e) buf[L::at(s, p2_out_pos<N, E>(u, e))] = v[e];
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = buf[L::at(s, p2_in_pos<N, 0>(u, e))];
+    for (int e = 0; e < E; ++e) v[e] = buf[L::at(s, p2_in_pos<N, E, 0>(u, e))];
     __syncthreads();
   }
 }

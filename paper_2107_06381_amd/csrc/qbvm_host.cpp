@@ -79,6 +79,8 @@ int build_fft(int n, FftTables& t) {
 
 std::mutex g_mu;
 std::map<std::pair<int, int>, std::unique_ptr<FftTables>> g_fft_cache;  // (device, n)
+// tuned variants: (device, role 0 rows / 1 cols / 2 time, N) -> variant
+std::map<std::tuple<int, int, int>, int> g_tuned;
 std::map<int, bool> g_roots_ready;
 
 int get_fft(int device, int n, const FftTables** out) {
@@ -238,6 +240,7 @@ struct qbvm_plan_s {
   const FftTables* tfft = nullptr;  // length N_t
   const FftTables* sfft = nullptr;  // length 2(m+1)
   int S_time = 1, S_dst = 1;
+  int var_rows = 1, var_cols = 1, var_time = 1;
   double* mu1d = nullptr;
   double* ghat = nullptr;
   double* yrow = nullptr;
@@ -355,6 +358,16 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
   if (rc) return rc;
   p->S_time = plan::signals_for(p->tfft->dev.nc);
   p->S_dst = plan::signals_for(p->sfft->dev.nc);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto pick = [&](int role, int N, int& var) {
+      auto it = g_tuned.find(std::make_tuple(p->device, role, N));
+      if (it != g_tuned.end()) var = it->second;
+    };
+    pick(0, p->sfft->dev.p2, p->var_rows);
+    pick(1, p->sfft->dev.p2, p->var_cols);
+    pick(2, p->tfft->dev.p2, p->var_time);
+  }
   // eigenvalues of the 1D three-point stencil: (4/h^2) sin^2(k pi/(2(m+1)))
   std::vector<double> mu(p->m);
   for (int k = 1; k <= p->m; ++k) {
@@ -369,7 +382,8 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
     HIP_TRY(dalloc(p, &p->s2, (size_t)p->Nt * p->m));
     HIP_TRY(dalloc(p, &p->cp, (size_t)p->Nt * p->m));
   }
-  p->wg_row = (int)std::max<long long>(1, std::min<long long>(1024, (p->nmodes + 255) / 256));
+  // four lanes per mode in the row kernel (64 modes per 256-lane workgroup)
+  p->wg_row = (int)std::max<long long>(1, std::min<long long>(4096, (p->nmodes + 63) / 64));
   HIP_TRY(dalloc(p, &p->partial, p->wg_row));
   HIP_TRY(dalloc(p, &p->counter, 1));
   HIP_TRY(hipMemset(p->counter, 0, sizeof(unsigned)));
@@ -403,6 +417,9 @@ sched::Geom geom(const qbvm_plan_s* p) {
   g.tfft = p->tfft->dev;
   g.sfft = p->sfft->dev;
   g.mu1d = p->mu1d;
+  g.var_rows = p->var_rows;
+  g.var_cols = p->var_cols;
+  g.var_time = p->var_time;
   return g;
 }
 
@@ -411,7 +428,7 @@ sched::Geom geom(const qbvm_plan_s* p) {
 int run_dst(const qbvm_plan_s* p, const double* in, double* out, long long batch, bool input_transform,
             NodeCtx* nc = nullptr, hipStream_t stream = nullptr) {
   hipStream_t s = nc ? stream : p->stream;
-  for (const auto& L : sched::dst_passes(geom(p), in, out, batch)) {
+  for (const auto& L : sched::dst_passes(geom(p), in, out, batch, input_transform)) {
     const double elems = (double)L.args.outer * L.args.inner * L.args.len;
     const int role = input_transform ? 0 : (L.args.inner == 1 ? 1 : 2);
     static const char* names[3] = {"dst_input", "dst_rows", "dst_cols"};
@@ -564,9 +581,9 @@ int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_d
 }
 
 static int enqueue_bisection(qbvm_plan_t p, int variant, int count, const double* ghat, const double* deltas,
-                             const qbvm_alpha_opts* o, double* bstate, double* alphas_out, int* hits_out,
-                             double* partial, unsigned* counter, int wpi) {
-  HIP_TRY(launch_bisect_init(bstate, count, deltas, o->tau_dp, o->log10_lo, o->log10_hi, p->stream));
+                             double delta_val, const qbvm_alpha_opts* o, double* bstate, double* alphas_out,
+                             int* hits_out, double* partial, unsigned* counter, int wpi) {
+  HIP_TRY(launch_bisect_init(bstate, count, deltas, delta_val, o->tau_dp, o->log10_lo, o->log10_hi, p->stream));
   int rc = enqueue_row(p, count, ghat, p->n, 0.0, nullptr, variant, nullptr, true, bstate, 2, nullptr, partial,
                        counter, wpi);
   if (rc) return rc;
@@ -598,13 +615,11 @@ int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double 
   if (variant != QBVM_PQ && variant != QBVM_PM) return set_error(QBVM_EINVAL, "invalid variant");
   if (o->use_learned && !p->has_model) return set_error(QBVM_ENOMODEL, "no model attached");
   qbvm_alpha_info inf{};
-  p->pinned[0] = delta;
-  HIP_TRY(hipMemcpyAsync(p->dscal, p->pinned, sizeof(double), hipMemcpyHostToDevice, p->stream));
   rc = run_dst(p, g_delta, p->ghat, 1, true);
   if (rc) return rc;
   if (o->use_learned) {
-    HIP_TRY(launch_features(1, p->nmodes, p->hd, p->ghat, p->dscal, p->bin_perm, p->bin_off, p->feats, p->stream));
-    HIP_TRY(launch_predict(p->model, p->feats, p->dscal + 1, p->stream));
+    HIP_TRY(launch_feat_predict(p->nmodes, p->hd, p->ghat, delta, p->bin_perm, p->bin_off, p->model, p->feats,
+                                p->dscal + 1, p->stream));
     rc = enqueue_row(p, 1, p->ghat, p->n, 0.0, p->dscal + 1, variant, nullptr, true, nullptr, 0, p->dscal + 3,
                      p->partial, p->counter, p->wg_row);
     if (rc) return rc;
@@ -622,7 +637,7 @@ int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double 
     }
     inf.used_fallback = 1;
   }
-  rc = enqueue_bisection(p, variant, 1, p->ghat, p->dscal, o, p->bstate, p->dscal + 4, nullptr, p->partial,
+  rc = enqueue_bisection(p, variant, 1, p->ghat, nullptr, delta, o, p->bstate, p->dscal + 4, nullptr, p->partial,
                          p->counter, p->wg_row);
   if (rc) return rc;
   rc = enqueue_row(p, 1, p->ghat, p->n, 0.0, p->dscal + 4, variant, nullptr, true, nullptr, 0, p->dscal + 3,
@@ -658,7 +673,7 @@ int qbvm_bisect_batched(qbvm_plan_t p, int variant, int count, const double* g_d
   if (rc) return rc;
   if (count < 1) return set_error(QBVM_EINVAL, "count must be >= 1");
   if (variant != QBVM_PQ && variant != QBVM_PM) return set_error(QBVM_EINVAL, "invalid variant");
-  const int wpi = (int)std::max<long long>(1, std::min<long long>(64, (p->nmodes + 1023) / 1024));
+  const int wpi = (int)std::max<long long>(1, std::min<long long>(64, (p->nmodes + 255) / 256));
   const size_t gh = (size_t)count * p->nmodes * sizeof(double);
   const size_t bs = (size_t)count * kBState * sizeof(double);
   const size_t pa = (size_t)count * wpi * sizeof(double);
@@ -673,7 +688,8 @@ int qbvm_bisect_batched(qbvm_plan_t p, int variant, int count, const double* g_d
   HIP_TRY(hipMemsetAsync(counter, 0, co, p->stream));
   rc = run_dst(p, g_deltas, ghat, count, true);
   if (rc) return rc;
-  return enqueue_bisection(p, variant, count, ghat, deltas, o, bstate, alphas_out, hits_out, partial, counter, wpi);
+  return enqueue_bisection(p, variant, count, ghat, deltas, 0.0, o, bstate, alphas_out, hits_out, partial, counter,
+                           wpi);
 }
 
 int qbvm_features(qbvm_plan_t p, int count, const double* g_deltas, const double* deltas, float* feats) {
@@ -743,6 +759,115 @@ int qbvm_adam_step(float* params, const float* grad, float* m, float* v, int n, 
 }
 
 }  // extern "C"
+
+
+// ------------------------------------------------------------- autotuner
+namespace {
+
+// median-free minimum of a few timed launches of one schedule step
+template <class F>
+int time_min_ms(hipStream_t s, F launch, double* out_ms) {
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  double best = 1e30;
+  for (int rep = 0; rep < 4; ++rep) {
+    HIP_TRY(hipEventRecord(a, s));
+    const int rc = launch();
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(b, s));
+    HIP_TRY(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, a, b));
+    if (rep > 0) best = std::min(best, (double)ms);  // first launch is a warm-up
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *out_ms = best;
+  return QBVM_OK;
+}
+
+}  // namespace
+
+extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
+  if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
+  double ms[12];
+  for (double& x : ms) x = -1.0;
+  const size_t ny = (size_t)p->Nt * p->nmodes;
+  double* scratch = nullptr;
+  HIP_TRY(hipMalloc((void**)&scratch, ny * sizeof(double)));
+  std::unique_ptr<double, void (*)(double*)> guard(scratch, [](double* q) { (void)hipFree(q); });
+  HIP_TRY(hipMemsetAsync(scratch, 0, ny * sizeof(double), p->stream));
+  const int Ns = p->sfft->dev.p2, Nt2 = p->tfft->dev.p2;
+  if (Ns && p->d >= 2) {
+    for (int role = 0; role < 2; ++role) {
+      double best = 1e30;
+      int bestv = -1;
+      for (int V : {0, 1, 3, 4}) {
+        if (!p2sz::dst_valid(Ns, V)) continue;
+        sched::Geom G = geom(p);
+        G.var_rows = G.var_cols = V;
+        const auto passes = sched::dst_passes(G, scratch, scratch, p->Nt, false);
+        const auto& L = passes[role == 0 ? 0 : 1];
+        double t = 0;
+        const int rc = time_min_ms(p->stream, [&]() -> int {
+          HIP_TRY(launch_dst(L.args, L.nwg, L.args.threads, L.lds, p->stream, nullptr, role + 1));
+          return QBVM_OK;
+        }, &t);
+        if (rc) return rc;
+        ms[role * 4 + (V < 2 ? V : V - 1)] = t;
+        if (t < best) {
+          best = t;
+          bestv = V;
+        }
+      }
+      if (bestv >= 0) (role == 0 ? p->var_rows : p->var_cols) = bestv;
+    }
+  }
+  if (Nt2 && p->d >= 2 && p2sz::time_valid(Nt2, 0)) {
+    double best = 1e30;
+    int bestv = -1;
+    for (int V = 0; V < p2sz::kTimeVariants2; ++V) {
+      if (!p2sz::time_valid(Nt2, V)) continue;
+      sched::Geom G = geom(p);
+      G.var_time = V;
+      const SolveScalars sc = sched::host_scalars(1e-3, QBVM_PQ, p->tau);
+      const auto t = sched::time_step(G, sc, nullptr, QBVM_PQ, scratch, scratch, 0, p->Nt);
+      double tm = 0;
+      const int rc = time_min_ms(p->stream, [&]() -> int {
+        HIP_TRY(launch_time(t.args, t.nwg, t.args.threads, t.lds, p->stream, nullptr));
+        return QBVM_OK;
+      }, &tm);
+      if (rc) return rc;
+      ms[8 + V] = tm;
+      if (tm < best) {
+        best = tm;
+        bestv = V;
+      }
+    }
+    if (bestv >= 0) p->var_time = bestv;
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (Ns && p->d >= 2) {
+      g_tuned[std::make_tuple(p->device, 0, Ns)] = p->var_rows;
+      g_tuned[std::make_tuple(p->device, 1, Ns)] = p->var_cols;
+    }
+    if (Nt2 && p->d >= 2) g_tuned[std::make_tuple(p->device, 2, Nt2)] = p->var_time;
+  }
+  if (ms_out)
+    for (int i = 0; i < 12; ++i) ms_out[i] = ms[i];
+  return QBVM_OK;
+}
+
+extern "C" int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var_time) {
+  if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
+  if (var_rows) *var_rows = p->var_rows;
+  if (var_cols) *var_cols = p->var_cols;
+  if (var_time) *var_time = p->var_time;
+  return QBVM_OK;
+}
 
 // ================================================================ batched
 namespace {

@@ -25,8 +25,11 @@ hipError_t launch_thomas(const ThomasArgs& a, hipStream_t s, NodeCtx* nc = nullp
 hipError_t launch_time1d(const Time1dArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,
                          NodeCtx* nc = nullptr);
 hipError_t launch_row(const RowArgs& a, long long nwg, int threads, size_t lds, hipStream_t s);
-hipError_t launch_bisect_init(double* bstate, int count, const double* deltas, double tau_dp,
-                              double lo, double hi, hipStream_t s);
+hipError_t launch_bisect_init(double* bstate, int count, const double* deltas, double delta_val,
+                              double tau_dp, double lo, double hi, hipStream_t s);
+hipError_t launch_feat_predict(long long nm, double hd, const double* ghat, double delta, const int* perm,
+                               const int* off, const float* model, float* feats, double* alpha_out,
+                               hipStream_t s);
 hipError_t launch_bisect_finish(const double* bstate, int count, double* alphas, int* hits,
                                 hipStream_t s);
 hipError_t launch_features(int count, long long nm, double hd, const double* ghat,

@@ -33,63 +33,79 @@ void upload_radix_roots(const c64* roots, int count) {
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_root), roots, sizeof(c64) * count, 0, hipMemcpyHostToDevice);
 }
 
-// Power-of-two kernels.  INPUT only separates the symbol of the transform of g_delta
-// from the passes over the solution levels, so per-kernel profiles stay apart.
-template <int N, bool INPUT>
-__global__ __launch_bounds__(kP2DstThreads) void k_dst_rows_p2(DstArgs a) {
+// Power-of-two kernels, one symbol per (N, variant); the input transform always
+// uses variant 2, the passes over the solution levels variants 0 or 1.
+template <int N, int V>
+__global__ __launch_bounds__(p2sz::dst_T(N, V)) void k_dst_rows_p2(DstArgs a) {
   extern __shared__ c64 lds[];
-  dst_rows_p2_body<N>(a, blockIdx.x, lds);
+  dst_rows_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V)>(a, blockIdx.x, lds);
 }
 
-template <int N, bool INPUT>
-__global__ __launch_bounds__(kP2DstThreads) void k_dst_cols_p2(DstArgs a) {
+template <int N, int V>
+__global__ __launch_bounds__(p2sz::dst_T(N, V)) void k_dst_cols_p2(DstArgs a) {
   extern __shared__ c64 lds[];
-  dst_cols_p2_body<N>(a, blockIdx.x, lds);
+  dst_cols_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V)>(a, blockIdx.x, lds);
 }
 
-template <int N, bool RADER>
-__global__ __launch_bounds__(kP2TimeThreads) void k_time_p2(TimeArgs a) {
+template <int N, int V, bool RADER>
+__global__ __launch_bounds__(p2sz::time_T(V)) void k_time_p2(TimeArgs a) {
   extern __shared__ c64 lds[];
-  time_p2_body<N, RADER>(a, blockIdx.x, lds);
+  time_p2_body<N, p2sz::time_E(V), p2sz::time_S(N, V), RADER, p2sz::time_pad(V)>(a, blockIdx.x, lds);
 }
 
-#define QBVM_P2_SWITCH(N, ...)     \
-  switch (N) {                      \
-    case 64: { constexpr int NN = 64; return __VA_ARGS__; }     \
-    case 128: { constexpr int NN = 128; return __VA_ARGS__; }   \
-    case 256: { constexpr int NN = 256; return __VA_ARGS__; }   \
-    case 512: { constexpr int NN = 512; return __VA_ARGS__; }   \
-    case 1024: { constexpr int NN = 1024; return __VA_ARGS__; } \
-    case 2048: { constexpr int NN = 2048; return __VA_ARGS__; } \
-    case 4096: { constexpr int NN = 4096; return __VA_ARGS__; } \
-    default: return nullptr;        \
+template <int N, int V>
+static const void* dst_fn_nv(bool cols) {
+  if constexpr (p2sz::dst_valid(N, V))
+    return cols ? (const void*)&k_dst_cols_p2<N, V> : (const void*)&k_dst_rows_p2<N, V>;
+  else
+    return nullptr;
+}
+
+template <int N>
+static const void* dst_fn_n(int V, bool cols) {
+  switch (V) {
+    case 0: return dst_fn_nv<N, 0>(cols);
+    case 1: return dst_fn_nv<N, 1>(cols);
+    case 2: return dst_fn_nv<N, 2>(cols);
+    case 3: return dst_fn_nv<N, 3>(cols);
+    case 4: return dst_fn_nv<N, 4>(cols);
+    default: return nullptr;
+  }
+}
+
+template <int N, int V>
+static const void* time_fn_nv(bool rader) {
+  if constexpr (p2sz::time_valid(N, V))
+    return rader ? (const void*)&k_time_p2<N, V, true> : (const void*)&k_time_p2<N, V, false>;
+  else
+    return nullptr;
+}
+
+template <int N>
+static const void* time_fn_n(int V, bool rader) {
+  switch (V) {
+    case 0: return time_fn_nv<N, 0>(rader);
+    case 1: return time_fn_nv<N, 1>(rader);
+    case 2: return time_fn_nv<N, 2>(rader);
+    case 3: return time_fn_nv<N, 3>(rader);
+    default: return nullptr;
+  }
+}
+
+#define QBVM_P2_SWITCH(N, F, ...)                      \
+  switch (N) {                                         \
+    case 64: return F<64>(__VA_ARGS__);                \
+    case 128: return F<128>(__VA_ARGS__);              \
+    case 256: return F<256>(__VA_ARGS__);              \
+    case 512: return F<512>(__VA_ARGS__);              \
+    case 1024: return F<1024>(__VA_ARGS__);            \
+    case 2048: return F<2048>(__VA_ARGS__);            \
+    case 4096: return F<4096>(__VA_ARGS__);            \
+    default: return nullptr;                           \
   }
 
-#define QBVM_P2_SWITCH_TIME(N, ...)     \
-  switch (N) {                      \
-    case 64: { constexpr int NN = 64; return __VA_ARGS__; }     \
-    case 128: { constexpr int NN = 128; return __VA_ARGS__; }   \
-    case 256: { constexpr int NN = 256; return __VA_ARGS__; }   \
-    case 512: { constexpr int NN = 512; return __VA_ARGS__; }   \
-    case 1024: { constexpr int NN = 1024; return __VA_ARGS__; } \
-    case 2048: { constexpr int NN = 2048; return __VA_ARGS__; } \
-    default: return nullptr;        \
-  }
-
-static const void* dst_p2_fn(int N, bool cols, bool input) {
-  if (cols) {
-    if (input) { QBVM_P2_SWITCH(N, (const void*)&k_dst_cols_p2<NN, true>) }
-    QBVM_P2_SWITCH(N, (const void*)&k_dst_cols_p2<NN, false>)
-  }
-  if (input) { QBVM_P2_SWITCH(N, (const void*)&k_dst_rows_p2<NN, true>) }
-  QBVM_P2_SWITCH(N, (const void*)&k_dst_rows_p2<NN, false>)
-}
-
-static const void* time_p2_fn(int N, bool rader) {
-  if (N > p2sz::kTimeMaxN) return nullptr;
-  if (rader) { QBVM_P2_SWITCH_TIME(N, (const void*)&k_time_p2<NN, true>) }
-  QBVM_P2_SWITCH_TIME(N, (const void*)&k_time_p2<NN, false>)
-}
+static const void* dst_p2_fn(int N, int V, bool cols) { QBVM_P2_SWITCH(N, dst_fn_n, V, cols) }
+static const void* time_p2_fn(int N, int V, bool rader) { QBVM_P2_SWITCH(N, time_fn_n, V, rader) }
 
 // ROLE only separates the kernel symbols (0: transform of g_delta, 1: rows of the
 // levels, 2: strided columns of the levels) so per-kernel profiles stay apart.
@@ -126,6 +142,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+
+constexpr int kRowLanes = 4;
 
 __global__ __launch_bounds__(256) void k_row(RowArgs a) {
   extern __shared__ c64 lds[];
@@ -166,26 +184,40 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a) {
   const c64 gi = inv_gamma(a.level, Nt, sc.logabsw, sc.f0s / (double)Nt);
   const double* gh = a.ghat + (size_t)inst * a.nmodes;
   double acc = 0.0;
+  // kRowLanes lanes share one mode, each summing every kRowLanes-th shift j
   const long long per = ((a.nmodes + a.wg_per_inst - 1) / a.wg_per_inst);
   const long long kb = wsub * per;
   const long long ke = kb + per < a.nmodes ? kb + per : a.nmodes;
-  for (long long k = kb + threadIdx.x; k < ke; k += blockDim.x) {
-    const double mu = mode_mu(k, a.d, a.m, a.mu1d);
-    double sr = 0.0, si = 0.0;
-    for (int j = 0; j < Nt; ++j) {
-      const c64 z = dt[j];
-      const double x = z.re + mu;
-      const double q = 1.0 / (x * x + z.im * z.im);
-      // w_j / (x + i z.im) = w_j (x - i z.im) q
-      const c64 ww = w[j];
-      sr += (ww.re * x + ww.im * z.im) * q;
-      si += (ww.im * x - ww.re * z.im) * q;
+  const int sub = threadIdx.x % kRowLanes;
+  const int mpb = blockDim.x / kRowLanes;
+  for (long long kbase = kb; kbase < ke; kbase += mpb) {
+    const long long k = kbase + threadIdx.x / kRowLanes;
+    const bool live = k < ke;
+    double sr = 0.0, si = 0.0, mu = 0.0;
+    if (live) {
+      mu = mode_mu(k, a.d, a.m, a.mu1d);
+      for (int j = sub; j < Nt; j += kRowLanes) {
+        const c64 z = dt[j];
+        const double x = z.re + mu;
+        const double q = 1.0 / (x * x + z.im * z.im);
+        // w_j / (x + i z.im) = w_j (x - i z.im) q
+        const c64 ww = w[j];
+        sr += (ww.re * x + ww.im * z.im) * q;
+        si += (ww.im * x - ww.re * z.im) * q;
+      }
     }
-    const double g = gh[k];
-    const double Y = (gi.re * sr - gi.im * si) * g;
-    if (a.yrow) a.yrow[(size_t)inst * a.nmodes + k] = Y;
-    const double r = Y - g;
-    acc += r * r;
+#pragma unroll
+    for (int off = kRowLanes / 2; off >= 1; off >>= 1) {
+      sr += __shfl_xor(sr, off, 64);
+      si += __shfl_xor(si, off, 64);
+    }
+    if (live && sub == 0) {
+      const double g = gh[k];
+      const double Y = (gi.re * sr - gi.im * si) * g;
+      if (a.yrow) a.yrow[(size_t)inst * a.nmodes + k] = Y;
+      const double r = Y - g;
+      acc += r * r;
+    }
   }
   if (!a.partial) return;
   acc = wave_sum(acc);
@@ -204,12 +236,20 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a) {
   }
   __syncthreads();
   if (!s_last) return;
+  __threadfence();
+  // the last workgroup of the instance sums the partials (fixed order per lane, then a fixed tree)
+  double t = 0.0;
+  for (int i = threadIdx.x; i < a.wg_per_inst; i += blockDim.x)
+    t += __hip_atomic_load(&a.partial[(size_t)inst * a.wg_per_inst + i], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  t = wave_sum(t);
+  __syncthreads();
+  if (lane == 0) red[wv] = t;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    double t = 0.0;
-    for (int i = 0; i < a.wg_per_inst; ++i) t += __hip_atomic_load(&a.partial[(size_t)inst * a.wg_per_inst + i], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    const double D = sqrt(a.hd * t);
+    double tot = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += red[i];
+    const double D = sqrt(a.hd * tot);
     __hip_atomic_store(&a.counter[inst], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (a.dout) a.dout[inst] = D;
     if (bs) {
@@ -232,14 +272,14 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a) {
   }
 }
 
-__global__ void k_bisect_init(double* bs, int count, const double* deltas, double tau_dp, double lo,
-                              double hi) {
+__global__ void k_bisect_init(double* bs, int count, const double* deltas, double delta_val, double tau_dp,
+                              double lo, double hi) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   double* b = bs + (size_t)i * kBState;
   b[0] = lo;
   b[1] = hi;
-  b[2] = tau_dp * deltas[i];
+  b[2] = tau_dp * (deltas ? deltas[i] : delta_val);
   b[3] = 0.0;
   b[4] = 0.0;
   b[5] = 0.0;
@@ -444,6 +484,63 @@ __global__ __launch_bounds__(64) void k_predict(const float* model, const float*
   }
 }
 
+// One instance: the 33 features (bins reduced in a fixed order, one wave per bin
+// group) followed by the network on them; writes alpha_out[0] = alpha, [1] = log10 alpha.
+__global__ __launch_bounds__(512) void k_feat_predict(long long nm, double hd, const double* ghat, double delta,
+                                                      const int* perm, const int* off, const float* model,
+                                                      float* feats, double* alpha_out) {
+  __shared__ double part[8][32];
+  __shared__ float x[33];
+  __shared__ float a1[64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  for (int b = wv; b < 32; b += nw) {
+    double t = 0.0;
+    for (int i = off[b] + lane; i < off[b + 1]; i += 64) {
+      const double v = ghat[perm[i]];
+      t += v * v;
+    }
+    t = wave_sum(t);
+    if (lane == 0) part[0][b] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 33) {
+    const int i = threadIdx.x;
+    const double f = i < 32 ? log10(part[0][i] * hd + 1e-300) : log10(delta);
+    feats[i] = (float)f;
+    x[i] = ((float)f - model[kNP + i]) / model[kNP + 33 + i];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int o = threadIdx.x;
+    float t = model[kB1 + o];
+    for (int i = 0; i < 33; ++i) t += model[kW1 + o * 33 + i] * x[i];
+    a1[o] = gelu_f(t);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int o = threadIdx.x;
+    float u = model[kB2 + o];
+    for (int i = 0; i < 64; ++i) u += model[kW2 + o * 64 + i] * a1[i];
+    float c = model[kW3 + o] * gelu_f(u);
+    for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s, 64);
+    if (o == 0) {
+      const float out = c + model[kB3];
+      const double l10 = (double)(out * model[kNP + 67] + model[kNP + 66]);
+      alpha_out[0] = exp10(l10);
+      alpha_out[1] = l10;
+    }
+  }
+}
+
+hipError_t launch_feat_predict(long long nm, double hd, const double* ghat, double delta, const int* perm,
+                               const int* off, const float* model, float* feats, double* alpha_out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_feat_predict, dim3(1), dim3(512), 0, s, nm, hd, ghat, delta, perm, off, model, feats,
+                     alpha_out);
+  return hipGetLastError();
+}
+
 __global__ void k_copy_scale(const double* in, double* out, long long n, double s) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = in[i] * s;
@@ -498,7 +595,7 @@ hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, 
       {(const void*)&k_dst<true, 0>, (const void*)&k_dst<true, 1>, (const void*)&k_dst<true, 2>}};
   const void* f = tab[a.fft.wide ? 1 : 0][role < 0 ? 0 : (role > 2 ? 2 : role)];
   if (a.fft.p2) {
-    f = dst_p2_fn(a.fft.p2, a.inner > 1, role == 0);
+    f = dst_p2_fn(a.fft.p2, a.var, a.inner > 1);
     if (!f) return hipErrorInvalidValue;
   }
   return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
@@ -507,7 +604,7 @@ hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, 
 hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds, hipStream_t s, NodeCtx* nc) {
   const void* f = a.fft.wide ? (const void*)&k_time<true> : (const void*)&k_time<false>;
   if (a.fft.p2) {
-    f = time_p2_fn(a.fft.p2, a.fft.kind == kRader);
+    f = time_p2_fn(a.fft.p2, a.var, a.fft.kind == kRader);
     if (!f) return hipErrorInvalidValue;
   }
   return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
@@ -528,10 +625,10 @@ hipError_t launch_row(const RowArgs& a, long long nwg, int threads, size_t lds, 
   return enqueue1((const void*)&k_row, dim3((unsigned)nwg), dim3(threads), lds, s, a, nullptr);
 }
 
-hipError_t launch_bisect_init(double* bstate, int count, const double* deltas, double tau_dp, double lo,
-                              double hi, hipStream_t s) {
+hipError_t launch_bisect_init(double* bstate, int count, const double* deltas, double delta_val, double tau_dp,
+                              double lo, double hi, hipStream_t s) {
   hipLaunchKernelGGL(k_bisect_init, dim3((count + 255) / 256), dim3(256), 0, s, bstate, count, deltas,
-                     tau_dp, lo, hi);
+                     delta_val, tau_dp, lo, hi);
   return hipGetLastError();
 }
 

@@ -1,4 +1,10 @@
-// Launch geometry of the power-of-two kernels (plain C++, mirrors qbvm_bodies_p2.hpp).
+// Launch geometry of the power-of-two kernels (plain C++, shared by the host,
+// the kernels and the CPU build).  Variants differ in the complex values per
+// lane E and the signals per workgroup S:
+//   sine passes: 0 = E16, 256 lanes; 1 = E8, 256 lanes; 2 = E8, one signal (input
+//                transform); 3 = E16, 512 lanes; 4 = E8, 512 lanes
+//   time kernel: 0 = E16, 128 lanes; 1 = E8, 256 lanes; 2, 3 = as 0, 1 without the
+//                bank-conflict pad (less LDS, more workgroups per CU)
 #pragma once
 
 #include <cstddef>
@@ -8,24 +14,45 @@
 namespace qbvm {
 namespace p2sz {
 
-constexpr int kDstThreads = 256;
-constexpr int kTimeThreads = 128;
-constexpr int kTimeMaxN = 2048;  // S = 2048/N >= 1
+constexpr int kDstVariants = 5;
+constexpr int kTimeVariants = 2;
+constexpr int kTimeMaxN = 2048;
 
-inline int dst_S(int N) { return kDstThreads * 16 / N; }
-inline int time_S(int N) { return kTimeThreads * 16 / N; }
-inline bool tw_in_lds(int N) { return N <= 1024; }
-
-// exchange buffer ([signal][position] padded for rows, [position][signal] for columns) + twiddles
-inline size_t dst_lds(int N, bool cols) {
-  const size_t S = (size_t)dst_S(N);
-  const size_t buf = cols ? (size_t)N * S : (size_t)(N + N / 16) * S;
-  return sizeof(c64) * (buf + (tw_in_lds(N) ? N : 0));
+constexpr int dst_E(int V) { return (V == 0 || V == 3) ? 16 : 8; }
+constexpr int dst_T(int N, int V) { return V == 2 ? N / 8 : (V >= 3 ? 512 : 256); }
+constexpr int dst_S(int N, int V) { return V == 2 ? 1 : dst_T(N, V) * dst_E(V) / N; }
+constexpr size_t dst_lds(int N, int V, bool cols);
+constexpr bool dst_valid(int N, int V) {
+  return V >= 0 && V < kDstVariants && N >= 64 && N <= 4096 && (N & (N - 1)) == 0 && dst_S(N, V) >= 1 &&
+         dst_T(N, V) <= 512 && dst_lds(N, V, false) <= 160 * 1024 && dst_lds(N, V, true) <= 160 * 1024;
 }
 
-inline size_t time_lds(int N, int Nt) {
-  const size_t S = (size_t)time_S(N);
-  return sizeof(c64) * ((size_t)N * S + (tw_in_lds(N) ? N : 0) + N + 2 * (size_t)Nt) + sizeof(int) * 2 * (size_t)N;
+constexpr int kTimeVariants2 = 4;
+constexpr int time_E(int V) { return (V % 2) == 0 ? 16 : 8; }
+constexpr int time_T(int V) { return (V % 2) == 0 ? 128 : 256; }
+constexpr bool time_pad(int V) { return V < 2; }
+constexpr int time_S(int N, int V) { return time_T(V) * time_E(V) / N; }
+constexpr bool time_valid(int N, int V) {
+  return V >= 0 && V < kTimeVariants2 && N >= 64 && N <= kTimeMaxN && (N & (N - 1)) == 0 && time_S(N, V) >= 1;
+}
+
+constexpr bool tw_in_lds(int N) { return N <= 1024; }
+
+// first radix of the (N, E) sequence (mirrors P2Radices, checked there by static_assert)
+constexpr int first_radix(int N, int E) { return (E == 16 && N >= 128 && N != 512) ? 16 : 8; }
+
+// exchange buffer ([signal][position] padded for rows, [position][signal] for columns) + twiddles
+constexpr size_t dst_lds(int N, int V, bool cols) {
+  return sizeof(c64) * ((cols ? (size_t)(N + N / first_radix(N, dst_E(V))) : (size_t)(N + N / 16)) * dst_S(N, V) +
+                        (tw_in_lds(N) ? N : 0));
+}
+
+// exchange buffer, twiddles, Rader kernel spectrum, d_j/tau and gamma_l^{-1}, two index maps
+constexpr size_t time_lds(int N, int V, int Nt) {
+  return sizeof(c64) * ((size_t)(N + (time_pad(V) ? N / first_radix(N, time_E(V)) : 0)) * time_S(N, V) +
+                        (tw_in_lds(N) ? N : 0) + N +
+                        2 * (size_t)Nt) +
+         sizeof(int) * 2 * (size_t)N;
 }
 
 }  // namespace p2sz

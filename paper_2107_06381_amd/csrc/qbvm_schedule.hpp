@@ -22,6 +22,7 @@ struct Geom {
   FftPlanDev tfft;  // length N_t
   FftPlanDev sfft;  // length 2(m+1)
   const double* mu1d;
+  int var_rows = 1, var_cols = 1, var_time = 1;  // power-of-two kernel variants (levels)
 };
 
 template <class A>
@@ -42,7 +43,9 @@ inline size_t lds_time1d(const Geom& g, int lev_count) {
 }
 
 // d passes of the orthonormal DST-I over a [batch][m]^d array (in -> out, then in place)
-inline std::vector<Launch<DstArgs>> dst_passes(const Geom& g, const double* in, double* out, long long batch) {
+// input_transform: g_delta (small batch) -> the one-signal variant; else the tuned ones
+inline std::vector<Launch<DstArgs>> dst_passes(const Geom& g, const double* in, double* out, long long batch,
+                                               bool input_transform = false) {
   std::vector<Launch<DstArgs>> v;
   const int m = g.m;
   long long inner = 1;
@@ -61,9 +64,13 @@ inline std::vector<Launch<DstArgs>> dst_passes(const Geom& g, const double* in, 
     a.threads = kThreads;
     size_t lds = lds_dst(g);
     if (g.sfft.p2) {  // compile-time power-of-two kernels
-      a.S = p2sz::dst_S(g.sfft.p2);
-      a.threads = p2sz::kDstThreads;
-      lds = p2sz::dst_lds(g.sfft.p2, inner > 1);
+      const int N = g.sfft.p2;
+      int V = input_transform ? 2 : (inner > 1 ? g.var_cols : g.var_rows);
+      if (!p2sz::dst_valid(N, V)) V = 0;
+      a.var = V;
+      a.S = p2sz::dst_S(N, V);
+      a.threads = p2sz::dst_T(N, V);
+      lds = p2sz::dst_lds(N, V, inner > 1);
     }
     long long nwg;
     if (inner == 1) {
@@ -102,10 +109,13 @@ inline Launch<TimeArgs> time_step(const Geom& g, SolveScalars sc, const double* 
   t.fft = g.tfft;
   t.threads = kThreads;
   size_t lds = lds_time(g, lev_count);
-  if (g.tfft.p2 && g.tfft.p2 <= p2sz::kTimeMaxN && lev_first == 0 && lev_count == g.Nt) {
-    t.S = p2sz::time_S(g.tfft.p2);
-    t.threads = p2sz::kTimeThreads;
-    lds = p2sz::time_lds(g.tfft.p2, g.Nt);
+  if (g.tfft.p2 && p2sz::time_valid(g.tfft.p2, 0) && lev_first == 0 && lev_count == g.Nt) {
+    const int N = g.tfft.p2;
+    const int V = p2sz::time_valid(N, g.var_time) ? g.var_time : 0;
+    t.var = V;
+    t.S = p2sz::time_S(N, V);
+    t.threads = p2sz::time_T(V);
+    lds = p2sz::time_lds(N, V, g.Nt);
   } else {
     t.fft.p2 = 0;  // generic kernel
   }

@@ -70,6 +70,7 @@ struct TimeArgs {
   const double* alpha_dev;  // if non-null, alpha is read from here (device-side choice)
   int variant;
   int threads;  // workgroup size of the launch
+  int var;      // power-of-two kernel variant
   FftPlanDev fft;
 };
 
@@ -84,6 +85,7 @@ struct DstArgs {
   long long tiles_per_outer;  // ceil(inner / (2S)) when inner > 1
   double scale;
   int threads;   // workgroup size of the launch
+  int var;       // power-of-two kernel variant
   FftPlanDev fft;
 };
 

@@ -31,7 +31,7 @@ EXPORTS = [
     "qbvm_choose_alpha", "qbvm_bisect_batched", "qbvm_features", "qbvm_set_alpha_model",
     "qbvm_mlp_forward", "qbvm_mlp_loss_grad", "qbvm_adam_step", "qbvm_strerror",
     "qbvm_last_error", "qbvm_version", "qbvm_profile_enable", "qbvm_profile_reset",
-    "qbvm_profile_count", "qbvm_profile_get",
+    "qbvm_profile_count", "qbvm_profile_get", "qbvm_plan_autotune", "qbvm_plan_get_variants",
 ]
 
 
@@ -93,6 +93,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qbvm_strerror": (ctypes.c_char_p, [i]),
         "qbvm_last_error": (ctypes.c_char_p, []),
         "qbvm_version": (i, []),
+        "qbvm_plan_autotune": (i, [vp, ctypes.POINTER(d)]),
+        "qbvm_plan_get_variants": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
         "qbvm_profile_enable": (None, [i]),
         "qbvm_profile_reset": (None, []),
         "qbvm_profile_count": (i, []),
@@ -166,6 +168,19 @@ class Plan:
     @property
     def workspace_bytes(self) -> int:
         return int(self.L_.qbvm_plan_workspace_bytes(self._h))
+
+    def autotune(self) -> dict:
+        """Time the kernel variants on this plan's shape and keep the fastest."""
+        ms = (ctypes.c_double * 12)()
+        _check(self.L_.qbvm_plan_autotune(self._h, ms))
+        v = [round(x, 5) for x in ms]
+        return {"ms_rows_v0134": v[0:4], "ms_cols_v0134": v[4:8], "ms_time_v0123": v[8:12],
+                "variants": self.variants()}
+
+    def variants(self):
+        r, c, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self.L_.qbvm_plan_get_variants(self._h, ctypes.byref(r), ctypes.byref(c), ctypes.byref(t)))
+        return {"rows": r.value, "cols": c.value, "time": t.value}
 
     def out_shape(self, output: int):
         sp = (self.m,) * self.d

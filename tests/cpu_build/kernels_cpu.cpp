@@ -2,8 +2,8 @@
 // host-side tests: indexing is checked by AddressSanitizer, results against the
 // oracle.  Usage:
 //   kernels_cpu fft   n S in.bin out.bin          (S signals, signal-major complex)
-//   kernels_cpu solve d m n L T alpha variant in.bin out.bin
-//   kernels_cpu dst   d m batch in.bin out.bin
+//   kernels_cpu solve d m n L T alpha variant in.bin out.bin [var_rows var_cols var_time]
+//   kernels_cpu dst   d m batch in.bin out.bin [var_rows var_cols input]
 #include "hip_cpu_shim.hpp"
 
 #include <cstdio>
@@ -21,6 +21,7 @@ namespace qbvm {
 c64 c_root[2080];
 }
 using namespace qbvm;
+using sched::Launch;
 
 template <class F>
 static void run_grid(long long nwg, int T, size_t lds_bytes, F body) {
@@ -138,27 +139,72 @@ static sched::Geom geom(int d, int m, int n, double L, double T, const Tables& t
     default: exit(9);                              \
   }
 
-#define P2_DISPATCH_T(N, CALL)                       \
-  switch (N) {                                    \
-    case 64: { constexpr int NN = 64; CALL; break; }     \
-    case 128: { constexpr int NN = 128; CALL; break; }   \
-    case 256: { constexpr int NN = 256; CALL; break; }   \
-    case 512: { constexpr int NN = 512; CALL; break; }   \
-    case 1024: { constexpr int NN = 1024; CALL; break; } \
-    case 2048: { constexpr int NN = 2048; CALL; break; } \
-    default: exit(9);                              \
+template <int N, int V>
+static void dst_p2_nv(const Launch<DstArgs>& Lz) {
+  if constexpr (p2sz::dst_valid(N, V)) {
+    const DstArgs& A = Lz.args;
+    constexpr int E = p2sz::dst_E(V), S = p2sz::dst_S(N, V);
+    if (A.inner > 1) run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_cols_p2_body<N, E, S>(A, wg, l); });
+    else run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_rows_p2_body<N, E, S>(A, wg, l); });
+  } else {
+    exit(11);
+  }
+}
+
+template <int N>
+static void dst_p2_n(const Launch<DstArgs>& Lz) {
+  switch (Lz.args.var) {
+    case 0: dst_p2_nv<N, 0>(Lz); break;
+    case 1: dst_p2_nv<N, 1>(Lz); break;
+    case 2: dst_p2_nv<N, 2>(Lz); break;
+    case 3: dst_p2_nv<N, 3>(Lz); break;
+    case 4: dst_p2_nv<N, 4>(Lz); break;
+    default: exit(12);
+  }
+}
+
+template <int N, int V>
+static void time_p2_nv(const Launch<TimeArgs>& t) {
+  if constexpr (p2sz::time_valid(N, V)) {
+    const TimeArgs& A = t.args;
+    constexpr int E = p2sz::time_E(V), S = p2sz::time_S(N, V);
+    constexpr bool PAD = p2sz::time_pad(V);
+    if (A.fft.kind == kRader) run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_p2_body<N, E, S, true, PAD>(A, wg, l); });
+    else run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_p2_body<N, E, S, false, PAD>(A, wg, l); });
+  } else {
+    exit(13);
+  }
+}
+
+template <int N>
+static void time_p2_n(const Launch<TimeArgs>& t) {
+  switch (t.args.var) {
+    case 0: time_p2_nv<N, 0>(t); break;
+    case 1: time_p2_nv<N, 1>(t); break;
+    case 2: time_p2_nv<N, 2>(t); break;
+    case 3: time_p2_nv<N, 3>(t); break;
+    default: exit(14);
+  }
+}
+
+#define P2_SWITCH(N, F, ARG)                         \
+  switch (N) {                                       \
+    case 64: F<64>(ARG); break;                      \
+    case 128: F<128>(ARG); break;                    \
+    case 256: F<256>(ARG); break;                    \
+    case 512: F<512>(ARG); break;                    \
+    case 1024: F<1024>(ARG); break;                  \
+    case 2048: F<2048>(ARG); break;                  \
+    case 4096: F<4096>(ARG); break;                  \
+    default: exit(9);                                \
   }
 
-static void run_dst(const sched::Geom& g, const double* in, double* out, long long batch) {
-  for (const auto& Lz : sched::dst_passes(g, in, out, batch)) {
+static void run_dst(const sched::Geom& g, const double* in, double* out, long long batch, bool input) {
+  for (const auto& Lz : sched::dst_passes(g, in, out, batch, input)) {
     const DstArgs& A = Lz.args;
     const int T = A.threads;
     if (A.fft.p2) {
-      if (A.inner > 1) {
-        P2_DISPATCH(A.fft.p2, run_grid(Lz.nwg, T, Lz.lds, [&](long long wg, c64* l) { dst_cols_p2_body<NN>(A, wg, l); }))
-      } else {
-        P2_DISPATCH(A.fft.p2, run_grid(Lz.nwg, T, Lz.lds, [&](long long wg, c64* l) { dst_rows_p2_body<NN>(A, wg, l); }))
-      }
+      P2_SWITCH(A.fft.p2, dst_p2_n, Lz)
     } else if (A.fft.wide) {
       run_grid(Lz.nwg, T, Lz.lds, [&](long long wg, c64* l) { dst_body<true>(A, wg, l); });
     } else {
@@ -186,25 +232,31 @@ int main(int argc, char** argv) {
     printf("kind=%d nc=%d wide=%d stages=%d\n", t.dev.kind, t.dev.nc, t.dev.wide, t.dev.nstages);
     return 0;
   }
-  if (cmd == "dst" && argc == 7) {
+  if (cmd == "dst" && (argc == 7 || argc == 10)) {
     const int d = atoi(argv[2]), m = atoi(argv[3]);
     const long long batch = atoll(argv[4]);
     Tables tt = make_tables(2), st = make_tables(2 * (m + 1));
     std::vector<double> mu(m, 0.0);
-    const sched::Geom g = geom(d, m, 1, 1.0, 1.0, tt, st, mu);
+    sched::Geom g = geom(d, m, 1, 1.0, 1.0, tt, st, mu);
+    bool input = batch == 1;
+    if (argc == 10) {
+      g.var_rows = atoi(argv[7]);
+      g.var_cols = atoi(argv[8]);
+      input = atoi(argv[9]) != 0;
+    }
     auto raw = read_file(argv[5]);
     const size_t N = (size_t)batch * g.nmodes;
     if (raw.size() != N * sizeof(double)) return 7;
     double* in = new double[N];
     double* out = new double[N];
     std::memcpy(in, raw.data(), raw.size());
-    run_dst(g, in, out, batch);
+    run_dst(g, in, out, batch, input);
     write_file(argv[6], out, N * sizeof(double));
     delete[] in;
     delete[] out;
     return 0;
   }
-  if (cmd == "solve" && argc == 11) {
+  if (cmd == "solve" && (argc == 11 || argc == 14)) {
     const int d = atoi(argv[2]), m = atoi(argv[3]), n = atoi(argv[4]);
     const double L = atof(argv[5]), T = atof(argv[6]), alpha = atof(argv[7]);
     const int variant = atoi(argv[8]);
@@ -215,7 +267,12 @@ int main(int argc, char** argv) {
       const long double s = sinl((long double)k * plan::kPiL / (2.0L * (m + 1)));
       mu[k - 1] = (double)(4.0L / ((long double)h * h) * s * s);
     }
-    const sched::Geom g = geom(d, m, n, L, T, tt, st, mu);
+    sched::Geom g = geom(d, m, n, L, T, tt, st, mu);
+    if (argc == 14) {
+      g.var_rows = atoi(argv[11]);
+      g.var_cols = atoi(argv[12]);
+      g.var_time = atoi(argv[13]);
+    }
     auto raw = read_file(argv[9]);
     if (raw.size() != (size_t)g.nmodes * sizeof(double)) return 7;
     double* gd = new double[g.nmodes];
@@ -234,22 +291,17 @@ int main(int argc, char** argv) {
       delete[] s2;
       delete[] cp;
     } else {
-      run_dst(g, gd, y, 1);
+      run_dst(g, gd, y, 1, true);
       const auto t = sched::time_step(g, sc, nullptr, variant, y, y, 0, g.Nt);
       const TimeArgs& A = t.args;
       if (A.fft.p2) {
-        if (A.fft.p2 > 2048) exit(10);
-        if (A.fft.kind == kRader) {
-          P2_DISPATCH_T(A.fft.p2, run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_p2_body<NN, true>(A, wg, l); }))
-        } else {
-          P2_DISPATCH_T(A.fft.p2, run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_p2_body<NN, false>(A, wg, l); }))
-        }
+        P2_SWITCH(A.fft.p2, time_p2_n, t)
       } else if (A.fft.wide) {
         run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_body<true>(A, wg, l); });
       } else {
         run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_body<false>(A, wg, l); });
       }
-      run_dst(g, y, y, g.Nt);
+      run_dst(g, y, y, g.Nt, false);
     }
     write_file(argv[10], y, ny * sizeof(double));
     delete[] gd;

@@ -50,16 +50,20 @@ def test_fft_engine(exe, tmp_path, n):
     assert np.linalg.norm(y - ref) <= 2e-15 * np.linalg.norm(ref) * max(1.0, np.log2(n)), info
 
 
-@pytest.mark.parametrize("d,m,batch", [(1, 9, 3), (2, 13, 2), (2, 100, 1), (3, 6, 2),
-                                       # power-of-two kernels: 2(m+1) = 64 .. 4096
-                                       (2, 31, 3), (3, 63, 1), (2, 127, 2), (2, 255, 1), (2, 511, 1),
-                                       (2, 1023, 1), (1, 2047, 5)])
-def test_dst_passes(exe, tmp_path, d, m, batch):
+DST_CASES = [(1, 9, 3), (2, 13, 2), (2, 100, 1), (3, 6, 2),
+             # power-of-two kernels: 2(m+1) = 64 .. 4096
+             (2, 31, 3), (3, 63, 1), (2, 127, 2), (2, 255, 1), (2, 511, 1), (2, 1023, 1), (1, 2047, 5)]
+
+
+@pytest.mark.parametrize("variants", [(0, 1, 0), (1, 0, 1), (3, 4, 0), (4, 3, 1)])
+@pytest.mark.parametrize("d,m,batch", DST_CASES)
+def test_dst_passes(exe, tmp_path, d, m, batch, variants):
+    """Every kernel variant of the sine passes (levels: E16 / E8; input transform: one signal)."""
     rng = np.random.default_rng(m)
     x = rng.standard_normal((batch,) + (m,) * d)
     fi, fo = tmp_path / "i.bin", tmp_path / "o.bin"
     x.tofile(fi)
-    _run(exe, ["dst", d, m, batch, fi, fo], tmp_path)
+    _run(exe, ["dst", d, m, batch, fi, fo, *variants], tmp_path)
     y = np.fromfile(fo).reshape(x.shape)
     ref = np.stack([O.dst_ortho(x[b]) for b in range(batch)])
     assert np.linalg.norm(y - ref) <= 1e-14 * np.linalg.norm(ref)
@@ -73,13 +77,15 @@ def test_dst_passes(exe, tmp_path, d, m, batch):
     (2, 63, 63, 1e-4, 0), (3, 15, 127, 1e-3, 1), (2, 20, 255, 1e-6, 0), (2, 33, 256, 1e-4, 0),
     (2, 255, 6, 1e-3, 0),
 ])
-def test_solve_schedule_vs_oracle(exe, tmp_path, d, m, n, alpha, variant):
-    """Full solve (1D Thomas path, 2D/3D sine-transform path) vs the closed form."""
+@pytest.mark.parametrize("kv", [(0, 4, 0), (4, 1, 1), (1, 3, 2), (3, 0, 3)])
+def test_solve_schedule_vs_oracle(exe, tmp_path, d, m, n, alpha, variant, kv):
+    """Full solve (1D Thomas path, 2D/3D sine-transform path) vs the closed form, both
+    power-of-two kernel variants."""
     L, T = 1.0, 0.9
     g = np.random.default_rng(d * 100 + m).standard_normal((m,) * d)
     fi, fo = tmp_path / "i.bin", tmp_path / "o.bin"
     g.tofile(fi)
-    _run(exe, ["solve", d, m, n, repr(L), repr(T), repr(alpha), variant, fi, fo], tmp_path)
+    _run(exe, ["solve", d, m, n, repr(L), repr(T), repr(alpha), variant, fi, fo, *kv], tmp_path)
     y = np.fromfile(fo).reshape((n + 1,) + (m,) * d)
     yc = O.closed_form(g, d, m, n, L, T, alpha, variant)
     rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)

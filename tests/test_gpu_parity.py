@@ -279,3 +279,19 @@ def test_batched_matches_single_and_oracle():
         yc = O.closed_form(ref[i], d, m, n, 1.0, 1.0, alphas2[i], variants[i])
         assert rel(ys[i].cpu().numpy(), yc) < TOL
     qbvm.batched_cache_clear()
+
+
+def test_autotune_then_solve():
+    """The autotuner times the power-of-two kernel variants and keeps parity."""
+    say("[case] autotune")
+    d, m, n = 2, 127, 256
+    g = np.random.default_rng(13).standard_normal((m, m))
+    p = qbvm.Plan(d, m, n)
+    rep = p.autotune()
+    assert rep["variants"]["time"] in (0, 1, 2, 3)
+    assert rep["variants"]["rows"] in (0, 1, 3, 4) and rep["variants"]["cols"] in (0, 1, 3, 4)
+    assert sum(1 for x in rep["ms_rows_v0134"] + rep["ms_cols_v0134"] + rep["ms_time_v0123"] if x > 0) >= 8
+    y = p.solve(1e-5, 0, to_dev(g))
+    torch.cuda.synchronize()
+    yc = O.closed_form(g, d, m, n, 1.0, 1.0, 1e-5, O.PQ)
+    assert rel(y.cpu().numpy(), yc) < TOL
