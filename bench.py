@@ -197,6 +197,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-alpha", action="store_true", help="skip the learned/bisection alpha-choice section")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched section")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference kernel for counter calibration)")
     ap.add_argument("--alpha-train", type=int, default=20000)
     ap.add_argument("--alpha-test", type=int, default=2000)
     args = ap.parse_args()
@@ -208,6 +210,14 @@ def main():
     import torch
 
     from paper_2107_06381_amd import qbvm, workloads as W
+
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     d, m, n, alpha = 2, 255, 256, 1e-4
     inst = W.config_2d()

@@ -47,6 +47,11 @@ __device__ __forceinline__ double mode_mu(long long k, int d, int m, const doubl
   return mu;
 }
 
+// column c of a columns pass holds data (see DstArgs)
+__device__ __forceinline__ bool dst_col_ok(const DstArgs& a, long long c) {
+  return c < a.inner && (a.colmod == 0 || (int)(c % a.colmod) < a.colvalid);
+}
+
 // ================================================================ k_dst ====
 // Orthonormal DST-I along the `len` axis of [outer][len][inner]: X_i = sqrt(2/(m+1)) *
 // sum_k x_k sin(pi i k/(m+1)).  Two real lines a, b are packed as a + i b into one
@@ -77,12 +82,12 @@ __device__ __forceinline__ void dst_body(const DstArgs& a, long long wg, c64* ld
       q = e / m;
       k = e - q * m;
       const long long line = i0 + q;
-      if (line < a.outer) x = a.in[line * m + k];
+      if (line < a.outer) x = a.in[line * a.in_pitch + k];
     } else {
       k = e / nl;
       q = e - k * nl;
       const long long i = i0 + q;
-      if (i < a.inner) x = a.in[(o * m + k) * a.inner + i];
+      if (dst_col_ok(a, i)) x = a.in[o * a.ostride + k * a.kstride + i];
     }
     const int s = q >> 1, comp = q & 1;
     const int p1 = fft_in_pos(a.fft, k + 1), p2 = fft_in_pos(a.fft, N - 1 - k);
@@ -101,13 +106,13 @@ __device__ __forceinline__ void dst_body(const DstArgs& a, long long wg, c64* ld
       k = e - q * m;
       const long long line = i0 + q;
       ok = line < a.outer;
-      dst = line * m + k;
+      dst = line * a.out_pitch + k;
     } else {
       k = e / nl;
       q = e - k * nl;
       const long long i = i0 + q;
-      ok = i < a.inner;
-      dst = (o * m + k) * a.inner + i;
+      ok = dst_col_ok(a, i);
+      dst = o * a.ostride + k * a.kstride + i;
     }
     const int s = q >> 1, comp = q & 1;
     const c64 V = fft_out(buf, S, a.fft, s, k + 1, side);

@@ -48,8 +48,8 @@ __device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long wg,
   const int m = a.len;
   const long long la = wg * 2LL * S + 2 * s, lb = la + 1;
   const bool oka = la < a.outer, okb = lb < a.outer;
-  const double* xa = a.in + la * m;
-  const double* xb = a.in + lb * m;
+  const double* xa = a.in + la * a.in_pitch;
+  const double* xb = a.in + lb * a.in_pitch;
   c64 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -63,8 +63,8 @@ __device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long wg,
     v[e] = {va, vb};
   }
   p2_fft<N, E, L>(v, s, u, buf, tw);
-  double* oa = a.out + la * m;
-  double* ob = a.out + lb * m;
+  double* oa = a.out + la * a.out_pitch;
+  double* ob = a.out + lb * a.out_pitch;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int i = p2_out_pos<N, E>(u, e);
@@ -86,8 +86,8 @@ __device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long wg,
   const int m = a.len;
   const long long o = wg / a.tiles_per_outer;
   const long long ca = (wg - o * a.tiles_per_outer) * 2LL * S + 2 * s, cb = ca + 1;
-  const bool oka = ca < a.inner, okb = cb < a.inner;
-  const double* base = a.in + o * m * a.inner;
+  const bool oka = dst_col_ok(a, ca), okb = dst_col_ok(a, cb);
+  const double* base = a.in + o * a.ostride;
   c64 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -95,19 +95,19 @@ __device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long wg,
     const int i = odd_ext_index(p2_in_pos<N, E, 0>(u, e), m, sg);
     double va = 0.0, vb = 0.0;
     if (i >= 0) {
-      const double* row = base + (long long)i * a.inner;
+      const double* row = base + (long long)i * a.kstride;
       if (oka) va = sg * row[ca];
       if (okb) vb = sg * row[cb];
     }
     v[e] = {va, vb};
   }
   p2_fft<N, E, L>(v, s, u, buf, tw);
-  double* obase = a.out + o * m * a.inner;
+  double* obase = a.out + o * a.ostride;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int i = p2_out_pos<N, E>(u, e);
     if (i >= 1 && i <= m) {
-      double* row = obase + (long long)(i - 1) * a.inner;
+      double* row = obase + (long long)(i - 1) * a.kstride;
       if (oka) row[ca] = -v[e].im * a.scale;
       if (okb) row[cb] = v[e].re * a.scale;
     }
@@ -148,8 +148,23 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
   const c64* tw = p2_twiddles<N>(a.fft, twl, t, L::T);
   __syncthreads();
 
-  const long long ka = wg * 2LL * S + 2 * s, kb = ka + 1;
-  const bool oka = ka < a.nmodes, okb = kb < a.nmodes;
+  // modes of this tile: flattened (pitch 0) or 2S consecutive x_1 of one padded row
+  long long ka, oa;
+  bool oka, okb;
+  if (a.pitch > 0) {
+    const long long row = wg / a.tiles_per_row;
+    const int c1 = (int)(wg - row * a.tiles_per_row) * 2 * S + 2 * s;
+    ka = row * a.m + c1;
+    oa = row * a.pitch + c1;
+    oka = c1 < a.m;
+    okb = c1 + 1 < a.m;
+  } else {
+    ka = wg * 2LL * S + 2 * s;
+    oa = ka;
+    oka = ka < a.nmodes;
+    okb = ka + 1 < a.nmodes;
+  }
+  const long long kb = ka + 1;
   const double ga = oka ? a.ghat[ka] : 0.0, gb = okb ? a.ghat[kb] : 0.0;
   const double mua = oka ? mode_mu(ka, a.d, a.m, a.mu1d) : 0.0;
   const double mub = okb ? mode_mu(kb, a.d, a.m, a.mu1d) : 0.0;
@@ -171,8 +186,8 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
   auto store = [&](int l, c64 X) {
     const c64 yv = cmul(gi[l], X);
     double* yl = a.y + (long long)l * a.ystride;
-    if (oka) yl[ka] = yv.re;
-    if (okb) yl[kb] = yv.im;
+    if (oka) yl[oa] = yv.re;
+    if (okb) yl[oa + 1] = yv.im;
   };
   if constexpr (RADER) {
     const c64 x0 = input(0);

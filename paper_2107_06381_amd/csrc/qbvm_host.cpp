@@ -20,6 +20,7 @@
 #include "qbvm_schedule.hpp"
 
 using namespace qbvm;
+using qbvm::sched::Launch;
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_last_error;
@@ -246,6 +247,7 @@ struct qbvm_plan_s {
   double* yrow = nullptr;
   c64* s2 = nullptr;
   c64* cp = nullptr;
+  double* W = nullptr;  // padded level workspace (d >= 2 power-of-two pipeline)
   double* partial = nullptr;
   unsigned* counter = nullptr;
   double* dscal = nullptr;   // [0] delta, [1] alpha_pred, [2] log10 alpha_pred, [3] D, [4] alpha_final, ...
@@ -332,6 +334,8 @@ void destroy_plan(qbvm_plan_s* p) {
   delete p;
 }
 
+sched::Geom geom(const qbvm_plan_s* p);
+
 int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
   *out = nullptr;
   int rc = validate_grid(grid);
@@ -382,6 +386,7 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
     HIP_TRY(dalloc(p, &p->s2, (size_t)p->Nt * p->m));
     HIP_TRY(dalloc(p, &p->cp, (size_t)p->Nt * p->m));
   }
+  if (sched::use_padded(geom(p))) HIP_TRY(dalloc(p, &p->W, (size_t)sched::padded_elems(geom(p))));
   // four lanes per mode in the row kernel (64 modes per 256-lane workgroup)
   p->wg_row = (int)std::max<long long>(1, std::min<long long>(4096, (p->nmodes + 63) / 64));
   HIP_TRY(dalloc(p, &p->partial, p->wg_row));
@@ -446,10 +451,32 @@ int check_alpha(double alpha, int variant) {
 }
 
 // Enqueue one full solve (every level).  alpha_dev (optional) overrides alpha.
+// W: padded workspace for the aligned pipeline (nullptr: in-place pipeline in y).
 int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, int variant, const double* g,
-                 double* y, c64* s2, c64* cp, NodeCtx* nc, hipStream_t stream) {
+                 double* y, c64* s2, c64* cp, NodeCtx* nc, hipStream_t stream, double* W = nullptr) {
   const sched::Geom G = geom(p);
   const SolveScalars sc = sched::host_scalars(alpha, variant, p->tau);
+  if (W && p->d >= 2 && sched::use_padded(G)) {
+    int rc = run_dst(p, g, p->ghat, 1, true, nc, stream);
+    if (rc) return rc;
+    const auto t = sched::time_step_padded(G, sc, alpha_dev, variant, p->ghat, W);
+    {
+      const double nm = (double)p->nmodes;
+      ProfScope ps("time_spectral", stream, 8.0 * nm * (1.0 + p->Nt),
+                   0.5 * nm * (fft_flops(p->tfft->dev) + 28.0 * p->Nt), nc);
+      HIP_TRY(launch_time(t.args, t.nwg, t.args.threads, t.lds, stream, nc));
+    }
+    const auto passes = sched::padded_passes(G, W, y);
+    for (size_t i = 0; i < passes.size(); ++i) {
+      const bool rows = i + 1 == passes.size();
+      const double elems = (double)p->Nt * p->nmodes;
+      ProfScope ps(rows ? "dst_rows" : "dst_cols", stream, 16.0 * elems,
+                   0.5 * (double)p->Nt * p->nmodes / p->m * fft_flops(p->sfft->dev), nc);
+      HIP_TRY(launch_dst(passes[i].args, passes[i].nwg, passes[i].args.threads, passes[i].lds, stream, nc,
+                         rows ? 1 : 2));
+    }
+    return QBVM_OK;
+  }
   if (p->d == 1) {
     const double cells = (double)p->Nt * p->m;
     {
@@ -555,7 +582,7 @@ int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta, 
   if (output != QBVM_OUT_ALL && output != QBVM_OUT_Y0 && output != QBVM_OUT_YN)
     return set_error(QBVM_EINVAL, "output must be QBVM_OUT_ALL, QBVM_OUT_Y0 or QBVM_OUT_YN");
   if (output == QBVM_OUT_ALL)
-    return enqueue_full(p, alpha, nullptr, variant, g_delta, y, p->s2, p->cp, nullptr, p->stream);
+    return enqueue_full(p, alpha, nullptr, variant, g_delta, y, p->s2, p->cp, nullptr, p->stream, p->W);
   rc = run_dst(p, g_delta, p->ghat, 1, true);
   if (rc) return rc;
   const int level = output == QBVM_OUT_Y0 ? 0 : p->n;
@@ -798,6 +825,8 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
   HIP_TRY(hipMalloc((void**)&scratch, ny * sizeof(double)));
   std::unique_ptr<double, void (*)(double*)> guard(scratch, [](double* q) { (void)hipFree(q); });
   HIP_TRY(hipMemsetAsync(scratch, 0, ny * sizeof(double), p->stream));
+  HIP_TRY(hipMemsetAsync(p->ghat, 0, p->nmodes * sizeof(double), p->stream));
+  if (p->W) HIP_TRY(hipMemsetAsync(p->W, 0, sched::padded_elems(geom(p)) * sizeof(double), p->stream));
   const int Ns = p->sfft->dev.p2, Nt2 = p->tfft->dev.p2;
   if (Ns && p->d >= 2) {
     for (int role = 0; role < 2; ++role) {
@@ -807,8 +836,9 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
         if (!p2sz::dst_valid(Ns, V)) continue;
         sched::Geom G = geom(p);
         G.var_rows = G.var_cols = V;
-        const auto passes = sched::dst_passes(G, scratch, scratch, p->Nt, false);
-        const auto& L = passes[role == 0 ? 0 : 1];
+        const bool pad = p->W != nullptr;
+        const auto passes = pad ? sched::padded_passes(G, p->W, scratch) : sched::dst_passes(G, scratch, scratch, p->Nt, false);
+        const auto& L = pad ? passes[role == 0 ? passes.size() - 1 : 0] : passes[role == 0 ? 0 : 1];
         double t = 0;
         const int rc = time_min_ms(p->stream, [&]() -> int {
           HIP_TRY(launch_dst(L.args, L.nwg, L.args.threads, L.lds, p->stream, nullptr, role + 1));
@@ -832,7 +862,8 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
       sched::Geom G = geom(p);
       G.var_time = V;
       const SolveScalars sc = sched::host_scalars(1e-3, QBVM_PQ, p->tau);
-      const auto t = sched::time_step(G, sc, nullptr, QBVM_PQ, scratch, scratch, 0, p->Nt);
+      const auto t = p->W ? sched::time_step_padded(G, sc, nullptr, QBVM_PQ, p->ghat, p->W)
+                          : sched::time_step(G, sc, nullptr, QBVM_PQ, scratch, scratch, 0, p->Nt);
       double tm = 0;
       const int rc = time_min_ms(p->stream, [&]() -> int {
         HIP_TRY(launch_time(t.args, t.nwg, t.args.threads, t.lds, p->stream, nullptr));

@@ -25,6 +25,16 @@ struct Geom {
   int var_rows = 1, var_cols = 1, var_time = 1;  // power-of-two kernel variants (levels)
 };
 
+// Padded pipeline (d >= 2, power-of-two sine and time kernels): the time kernel writes
+// levels into a workspace whose x_1 rows have pitch P1 (a multiple of 64 doubles, so
+// every column tile is aligned), the strided sine passes run in place there, and the
+// contiguous x_1 pass goes last and writes the unpadded output.
+inline long long padded_pitch(int m) { return ((long long)m + 63) / 64 * 64; }
+inline bool use_padded(const Geom& g) {
+  return g.d >= 2 && g.sfft.p2 && g.tfft.p2 && p2sz::time_valid(g.tfft.p2, 0);
+}
+inline long long padded_elems(const Geom& g) { return (long long)g.Nt * (g.nmodes / g.m) * padded_pitch(g.m); }
+
 template <class A>
 struct Launch {
   A args;
@@ -62,6 +72,11 @@ inline std::vector<Launch<DstArgs>> dst_passes(const Geom& g, const double* in, 
     a.scale = scale;
     a.fft = g.sfft;
     a.threads = kThreads;
+    a.in_pitch = a.out_pitch = m;
+    a.kstride = inner;
+    a.ostride = (long long)m * inner;
+    a.colmod = 0;
+    a.colvalid = 0;
     size_t lds = lds_dst(g);
     if (g.sfft.p2) {  // compile-time power-of-two kernels
       const int N = g.sfft.p2;
@@ -83,6 +98,58 @@ inline std::vector<Launch<DstArgs>> dst_passes(const Geom& g, const double* in, 
     v.push_back({a, nwg, lds});
     inner *= m;
   }
+  return v;
+}
+
+// geometry of one sine pass from its strides (shared by the padded passes)
+inline Launch<DstArgs> dst_pass_custom(const Geom& g, const double* in, double* out, long long outer,
+                                       long long inner, long long in_pitch, long long out_pitch, long long kstride,
+                                       long long ostride, int colmod, int colvalid, int V) {
+  DstArgs a{};
+  a.in = in;
+  a.out = out;
+  a.len = g.m;
+  a.outer = outer;
+  a.inner = inner;
+  a.scale = 0.5 * std::sqrt(2.0 / (g.m + 1));
+  a.fft = g.sfft;
+  a.in_pitch = in_pitch;
+  a.out_pitch = out_pitch;
+  a.kstride = kstride;
+  a.ostride = ostride;
+  a.colmod = colmod;
+  a.colvalid = colvalid;
+  const int N = g.sfft.p2;
+  if (!p2sz::dst_valid(N, V)) V = 0;
+  a.var = V;
+  a.S = p2sz::dst_S(N, V);
+  a.threads = p2sz::dst_T(N, V);
+  long long nwg;
+  if (inner == 1) {
+    nwg = (outer + 2 * a.S - 1) / (2 * a.S);
+    a.tiles_per_outer = 1;
+  } else {
+    a.tiles_per_outer = (inner + 2 * a.S - 1) / (2 * a.S);
+    nwg = outer * a.tiles_per_outer;
+  }
+  return {a, nwg, p2sz::dst_lds(N, V, inner > 1)};
+}
+
+// Padded-pipeline sine passes over all levels: strided axes in place on W, then
+// the x_1 pass W -> y.
+inline std::vector<Launch<DstArgs>> padded_passes(const Geom& g, double* W, double* y) {
+  std::vector<Launch<DstArgs>> v;
+  const int m = g.m;
+  const long long P1 = padded_pitch(m);
+  long long kstride = P1;  // axis 1 (x_2)
+  long long blocks = (long long)g.Nt * (g.nmodes / m / m);  // outer blocks for axis 1
+  for (int ax = 1; ax < g.d; ++ax) {
+    // columns of one block: all (x_ax-1 .. x_1) positions below this axis, padded rows
+    v.push_back(dst_pass_custom(g, W, W, blocks, kstride, 0, 0, kstride, kstride * m, (int)P1, m, g.var_cols));
+    kstride *= m;
+    blocks /= m;
+  }
+  v.push_back(dst_pass_custom(g, W, y, (long long)g.Nt * (g.nmodes / m), 1, P1, m, 0, 0, 0, 0, g.var_rows));
   return v;
 }
 
@@ -108,6 +175,8 @@ inline Launch<TimeArgs> time_step(const Geom& g, SolveScalars sc, const double* 
   t.variant = variant;
   t.fft = g.tfft;
   t.threads = kThreads;
+  t.pitch = 0;
+  t.tiles_per_row = 0;
   size_t lds = lds_time(g, lev_count);
   if (g.tfft.p2 && p2sz::time_valid(g.tfft.p2, 0) && lev_first == 0 && lev_count == g.Nt) {
     const int N = g.tfft.p2;
@@ -121,6 +190,19 @@ inline Launch<TimeArgs> time_step(const Geom& g, SolveScalars sc, const double* 
   }
   const long long nwg = (g.nmodes + 2LL * t.S - 1) / (2LL * t.S);
   return {t, nwg, lds};
+}
+
+// Time kernel of the padded pipeline: every level into W with x_1 pitch P1.
+inline Launch<TimeArgs> time_step_padded(const Geom& g, SolveScalars sc, const double* alpha_dev, int variant,
+                                         const double* ghat, double* W) {
+  Launch<TimeArgs> L = time_step(g, sc, alpha_dev, variant, ghat, W, 0, g.Nt);
+  const long long P1 = padded_pitch(g.m);
+  const long long rows = g.nmodes / g.m;
+  L.args.pitch = P1;
+  L.args.ystride = rows * P1;
+  L.args.tiles_per_row = (int)((g.m + 2LL * L.args.S - 1) / (2LL * L.args.S));
+  L.nwg = rows * L.args.tiles_per_row;
+  return L;
 }
 
 inline ThomasArgs thomas_step(const Geom& g, SolveScalars sc, const double* alpha_dev, int variant,

@@ -71,10 +71,16 @@ struct TimeArgs {
   int variant;
   int threads;  // workgroup size of the launch
   int var;      // power-of-two kernel variant
+  long long pitch;   // > 0: y rows of m modes padded to this pitch (tiles never straddle rows)
+  int tiles_per_row;
   FftPlanDev fft;
 };
 
 // Sine-transform pass: data viewed as [outer][len][inner]; transform along len.
+// Rows pass (inner == 1): line l is in[l*in_pitch + k], k < len, written to out[l*out_pitch + k].
+// Columns pass (inner > 1): point k of column c in block o is at o*ostride + k*kstride + c
+// (the same in input and output); column c is valid iff c < inner and, when colmod > 0,
+// c % colmod < colvalid (padded rows).
 struct DstArgs {
   const double* in;
   double* out;
@@ -86,6 +92,9 @@ struct DstArgs {
   double scale;
   int threads;   // workgroup size of the launch
   int var;       // power-of-two kernel variant
+  long long in_pitch, out_pitch;
+  long long kstride, ostride;
+  int colmod, colvalid;
   FftPlanDev fft;
 };
 

@@ -2,7 +2,7 @@
 // host-side tests: indexing is checked by AddressSanitizer, results against the
 // oracle.  Usage:
 //   kernels_cpu fft   n S in.bin out.bin          (S signals, signal-major complex)
-//   kernels_cpu solve d m n L T alpha variant in.bin out.bin [var_rows var_cols var_time]
+//   kernels_cpu solve d m n L T alpha variant in.bin out.bin [var_rows var_cols var_time [padded]]
 //   kernels_cpu dst   d m batch in.bin out.bin [var_rows var_cols input]
 #include "hip_cpu_shim.hpp"
 
@@ -256,7 +256,7 @@ int main(int argc, char** argv) {
     delete[] out;
     return 0;
   }
-  if (cmd == "solve" && (argc == 11 || argc == 14)) {
+  if (cmd == "solve" && (argc == 11 || argc == 14 || argc == 15)) {
     const int d = atoi(argv[2]), m = atoi(argv[3]), n = atoi(argv[4]);
     const double L = atof(argv[5]), T = atof(argv[6]), alpha = atof(argv[7]);
     const int variant = atoi(argv[8]);
@@ -280,7 +280,20 @@ int main(int argc, char** argv) {
     const size_t ny = (size_t)g.Nt * g.nmodes;
     double* y = new double[ny];
     const SolveScalars sc = sched::host_scalars(alpha, variant, g.tau);
-    if (d == 1) {
+    const bool padded = sched::use_padded(g) && !(argc == 15 && atoi(argv[14]) == 0);
+    if (padded) {
+      double* gh = new double[g.nmodes];
+      double* W = new double[sched::padded_elems(g)];
+      for (long long i = 0; i < sched::padded_elems(g); ++i) W[i] = 1e300;  // pad slots must not leak
+      run_dst(g, gd, gh, 1, true);
+      const auto t = sched::time_step_padded(g, sc, nullptr, variant, gh, W);
+      P2_SWITCH(t.args.fft.p2, time_p2_n, t)
+      for (const auto& Lz : sched::padded_passes(g, W, y)) {
+        P2_SWITCH(Lz.args.fft.p2, dst_p2_n, Lz)
+      }
+      delete[] gh;
+      delete[] W;
+    } else if (d == 1) {
       c64* s2 = new c64[(size_t)g.Nt * m];
       c64* cp = new c64[(size_t)g.Nt * m];
       const ThomasArgs ta = sched::thomas_step(g, sc, nullptr, variant, gd, s2, cp);

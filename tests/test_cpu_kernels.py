@@ -76,11 +76,13 @@ def test_dst_passes(exe, tmp_path, d, m, batch, variants):
     # power-of-two time kernels: N_t = 64, 128, 256 (Stockham) and 257 (Rader on 256)
     (2, 63, 63, 1e-4, 0), (3, 15, 127, 1e-3, 1), (2, 20, 255, 1e-6, 0), (2, 33, 256, 1e-4, 0),
     (2, 255, 6, 1e-3, 0),
+    # padded level pipeline (power-of-two sine and time kernels): 2D Rader-257, 2D 256, 3D 64
+    (2, 63, 256, 1e-4, 0), (2, 63, 255, 1e-5, 1), (3, 31, 63, 1e-3, 0),
 ])
-@pytest.mark.parametrize("kv", [(0, 4, 0), (4, 1, 1), (1, 3, 2), (3, 0, 3)])
+@pytest.mark.parametrize("kv", [(0, 4, 0, 1), (4, 1, 1, 1), (1, 3, 2, 0), (3, 0, 3, 0)])
 def test_solve_schedule_vs_oracle(exe, tmp_path, d, m, n, alpha, variant, kv):
-    """Full solve (1D Thomas path, 2D/3D sine-transform path) vs the closed form, both
-    power-of-two kernel variants."""
+    """Full solve (1D Thomas path, 2D/3D sine-transform path; padded and in-place
+    level pipelines) vs the closed form, for several power-of-two kernel variants."""
     L, T = 1.0, 0.9
     g = np.random.default_rng(d * 100 + m).standard_normal((m,) * d)
     fi, fo = tmp_path / "i.bin", tmp_path / "o.bin"

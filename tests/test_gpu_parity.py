@@ -58,6 +58,8 @@ CASES = [
     # power-of-two kernels: N_t = 64, 128, 256, 257 (Rader), sine lengths 64 .. 2048
     (2, 63, 63, 1e-4, 0), (3, 15, 127, 1e-3, 1), (2, 20, 255, 1e-6, 0), (2, 33, 256, 1e-4, 0),
     (2, 255, 6, 1e-3, 0), (2, 511, 3, 1e-2, 1), (2, 1023, 2, 1e-3, 0), (3, 63, 64, 1e-4, 0),
+    # padded level pipeline: 2D N_t = 256, 3D N_t = 64, 2D m = 511 with N_t = 128
+    (2, 63, 255, 1e-5, 1), (3, 31, 63, 1e-3, 0), (2, 511, 127, 1e-4, 0),
 ]
 
 
