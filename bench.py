@@ -68,6 +68,50 @@ def cpu_baseline(inst, alpha, budget_s: float):
                       f"(orthonormal DST-I via scipy, per-mode formula, all {n + 1} levels), {wall:.1f} s"}
 
 
+def solve_3d_bench(steps: int):
+    """3D m=127, n=128, T=0.5, alpha=1e-5 full solve (2.1 GB output): time and per-kernel rooflines."""
+    import torch
+
+    from paper_2107_06381_amd import qbvm, workloads as W
+
+    inst = W.config_3d()
+    dev = torch.device("cuda:0")
+    g = torch.from_numpy(inst.g_delta).to(dev)
+    plan = qbvm.Plan(3, 127, 128, 1.0, 0.5)
+    tune = plan.autotune()
+    y = torch.empty((129, 127, 127, 127), dtype=torch.float64, device=dev)
+    for _ in range(2):
+        plan.solve(1e-5, qbvm.QBVM_PQ, g, y)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.solve(1e-5, qbvm.QBVM_PQ, g, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    qbvm.profile_reset()
+    qbvm.profile_enable(True)
+    for _ in range(steps):
+        plan.solve(1e-5, qbvm.QBVM_PQ, g, y)
+    torch.cuda.synchronize()
+    rep = qbvm.profile_report()
+    qbvm.profile_enable(False)
+    kernels = {k: {"launches_per_step": r["launches"] / steps, "avg_us": round(r["total_ms"] / r["launches"] * 1e3, 1),
+                   "hbm_frac": round(r["bytes"] / (r["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+               for k, r in rep.items()}
+    step_bytes = sum(v["bytes"] for v in rep.values()) / steps
+    del y
+    plan.close()
+    torch.cuda.empty_cache()
+    unk = 128 * 127 ** 3
+    return {"workload": "3D PinT-QBVM, m=127 (7-point), n=128 (N_t=129), T=0.5, alpha=1e-5, Gaussian bump, 0.1% noise",
+            "ms_per_solve": round(ms, 4), "Munknowns_per_s": round(unk / (ms * 1e-3) / 1e6, 1),
+            "step_hbm_roofline_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernels": kernels, "autotune": tune}
+
+
 def alpha_choice_bench(train_count: int, test_count: int, lat_count: int, steps: int):
     """Learned vs bisection alpha choice on 2D m=127, n=128, T=1 (noise 0.1%..5%)."""
     import numpy as np
@@ -197,6 +241,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-alpha", action="store_true", help="skip the learned/bisection alpha-choice section")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched section")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D solve section")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for counter calibration)")
     ap.add_argument("--alpha-train", type=int, default=20000)
@@ -282,6 +327,7 @@ def main():
     step_bytes = sum(v["bytes"] for v in rep.values()) / args.steps
     del y
     torch.cuda.empty_cache()
+    solve3d = None if args.no_3d else solve_3d_bench(5)
     alpha = None if args.no_alpha else alpha_choice_bench(args.alpha_train, args.alpha_test, 200, 3000)
     batched = None if args.no_batched else batched_bench()
     line = {
@@ -304,6 +350,7 @@ def main():
         "step_hbm_roofline_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels": kernels,
         "autotune": tune,
+        "solve_3d": solve3d,
         "alpha_choice": alpha,
         "batched": batched,
         "parity_rel_err": parity,

@@ -27,9 +27,9 @@ __device__ __forceinline__ int odd_ext_index(int n, int m, double& sign) {
   return -1;
 }
 
-template <int N>
+template <int N, bool TWL = p2sz::tw_in_lds(N)>
 __device__ __forceinline__ const c64* p2_twiddles(const FftPlanDev& f, c64* tw_lds, int t, int T) {
-  if constexpr (p2_tw_in_lds<N>()) {
+  if constexpr (TWL) {
     for (int i = t; i < N; i += T) tw_lds[i] = f.tw[i];
     return tw_lds;
   } else {
@@ -38,12 +38,12 @@ __device__ __forceinline__ const c64* p2_twiddles(const FftPlanDev& f, c64* tw_l
 }
 
 // Rows of [outer][m] (inner == 1): lanes walk along lines, two lines per signal.
-template <int N, int E, int S>
+template <int N, int E, int S, bool TWL = p2sz::tw_in_lds(N)>
 __device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long wg, c64* lds) {
   using L = P2Layout<N, E, S, false>;
   c64* buf = lds;
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
-  const c64* tw = p2_twiddles<N>(a.fft, buf + L::lds_elems(), t, L::T);
+  const c64* tw = p2_twiddles<N, TWL>(a.fft, buf + L::lds_elems(), t, L::T);
   __syncthreads();
   const int m = a.len;
   const long long la = wg * 2LL * S + 2 * s, lb = la + 1;
@@ -76,12 +76,12 @@ __device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long wg,
 }
 
 // Columns of [outer][m][inner] (inner > 1): lanes of a wave take consecutive columns.
-template <int N, int E, int S>
+template <int N, int E, int S, bool TWL = p2sz::tw_in_lds(N)>
 __device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long wg, c64* lds) {
   using L = P2Layout<N, E, S, true>;
   c64* buf = lds;
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
-  const c64* tw = p2_twiddles<N>(a.fft, buf + L::lds_elems(), t, L::T);
+  const c64* tw = p2_twiddles<N, TWL>(a.fft, buf + L::lds_elems(), t, L::T);
   __syncthreads();
   const int m = a.len;
   const long long o = wg / a.tiles_per_outer;
@@ -134,9 +134,16 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
   const double croot = exp(sc.logabsw / (double)Nt);
   const double inv_tau = 1.0 / a.tau;
   const double gscale = sc.f0s / (double)Nt;
-  for (int j = t; j < Nt; j += L::T) {
-    dt[j] = shift_over_tau(j, Nt, croot, inv_tau);
-    gi[j] = inv_gamma(j, Nt, sc.logabsw, gscale);
+  if (a.tabs) {  // d_j/tau and gamma_l^{-1} f0s/N_t precomputed for this solve
+    for (int j = t; j < Nt; j += L::T) {
+      dt[j] = a.tabs[j];
+      gi[j] = a.tabs[Nt + j];
+    }
+  } else {
+    for (int j = t; j < Nt; j += L::T) {
+      dt[j] = shift_over_tau(j, Nt, croot, inv_tau);
+      gi[j] = inv_gamma(j, Nt, sc.logabsw, gscale);
+    }
   }
   if constexpr (RADER) {
     for (int i = t; i < N; i += L::T) {

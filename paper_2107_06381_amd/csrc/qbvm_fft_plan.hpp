@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "qbvm_types.hpp"
+#include "qbvm_p2_sizes.hpp"
 
 namespace qbvm {
 namespace plan {
@@ -206,6 +207,12 @@ inline bool build_tables(int n, HostFft& t, std::string& err) {
     t.kspec = dft_over_len(bb);
   }
   d.p2 = (d.kind != kBluestein && is_p2_core(nc)) ? nc : 0;
+  d.gtA = d.gtB = 0;
+  for (const auto& pr : p2sz::kGtPairs)
+    if (pr[0] * pr[1] == n) {
+      d.gtA = pr[0];
+      d.gtB = pr[1];
+    }
   return true;
 }
 

@@ -248,6 +248,7 @@ struct qbvm_plan_s {
   c64* s2 = nullptr;
   c64* cp = nullptr;
   double* W = nullptr;  // padded level workspace (d >= 2 power-of-two pipeline)
+  c64* tabs = nullptr;  // per-solve time-transform tables, 2 N_t
   double* partial = nullptr;
   unsigned* counter = nullptr;
   double* dscal = nullptr;   // [0] delta, [1] alpha_pred, [2] log10 alpha_pred, [3] D, [4] alpha_final, ...
@@ -371,6 +372,10 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
     pick(0, p->sfft->dev.p2, p->var_rows);
     pick(1, p->sfft->dev.p2, p->var_cols);
     pick(2, p->tfft->dev.p2, p->var_time);
+    if (p->tfft->dev.gtA) {
+      p->var_time = 0;
+      pick(3, p->Nt, p->var_time);
+    }
   }
   // eigenvalues of the 1D three-point stencil: (4/h^2) sin^2(k pi/(2(m+1)))
   std::vector<double> mu(p->m);
@@ -387,6 +392,7 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
     HIP_TRY(dalloc(p, &p->cp, (size_t)p->Nt * p->m));
   }
   if (sched::use_padded(geom(p))) HIP_TRY(dalloc(p, &p->W, (size_t)sched::padded_elems(geom(p))));
+  HIP_TRY(dalloc(p, &p->tabs, 2 * (size_t)p->Nt));
   // four lanes per mode in the row kernel (64 modes per 256-lane workgroup)
   p->wg_row = (int)std::max<long long>(1, std::min<long long>(4096, (p->nmodes + 63) / 64));
   HIP_TRY(dalloc(p, &p->partial, p->wg_row));
@@ -459,7 +465,9 @@ int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, in
   if (W && p->d >= 2 && sched::use_padded(G)) {
     int rc = run_dst(p, g, p->ghat, 1, true, nc, stream);
     if (rc) return rc;
-    const auto t = sched::time_step_padded(G, sc, alpha_dev, variant, p->ghat, W);
+    auto t = sched::time_step_padded(G, sc, alpha_dev, variant, p->ghat, W);
+    HIP_TRY(launch_alpha_tables(p->Nt, p->tau, variant, alpha, alpha_dev, p->tabs, stream, nc));
+    t.args.tabs = p->tabs;
     {
       const double nm = (double)p->nmodes;
       ProfScope ps("time_spectral", stream, 8.0 * nm * (1.0 + p->Nt),
@@ -818,7 +826,7 @@ int time_min_ms(hipStream_t s, F launch, double* out_ms) {
 
 extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
   if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
-  double ms[12];
+  double ms[16];
   for (double& x : ms) x = -1.0;
   const size_t ny = (size_t)p->Nt * p->nmodes;
   double* scratch = nullptr;
@@ -832,7 +840,7 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
     for (int role = 0; role < 2; ++role) {
       double best = 1e30;
       int bestv = -1;
-      for (int V : {0, 1, 3, 4}) {
+      for (int V : {0, 1, 3, 4, 5, 6}) {
         if (!p2sz::dst_valid(Ns, V)) continue;
         sched::Geom G = geom(p);
         G.var_rows = G.var_cols = V;
@@ -845,7 +853,7 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
           return QBVM_OK;
         }, &t);
         if (rc) return rc;
-        ms[role * 4 + (V < 2 ? V : V - 1)] = t;
+        ms[role * 6 + (V < 2 ? V : V - 1)] = t;
         if (t < best) {
           best = t;
           bestv = V;
@@ -854,11 +862,12 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
       if (bestv >= 0) (role == 0 ? p->var_rows : p->var_cols) = bestv;
     }
   }
-  if (Nt2 && p->d >= 2 && p2sz::time_valid(Nt2, 0)) {
+  const bool gt = p->tfft->dev.gtA != 0;
+  if ((Nt2 && p2sz::time_valid(Nt2, 0)) || gt) {
     double best = 1e30;
     int bestv = -1;
-    for (int V = 0; V < p2sz::kTimeVariants2; ++V) {
-      if (!p2sz::time_valid(Nt2, V)) continue;
+    for (int V = 0; V < (gt ? 2 : p2sz::kTimeVariants2); ++V) {
+      if (!gt && !p2sz::time_valid(Nt2, V)) continue;
       sched::Geom G = geom(p);
       G.var_time = V;
       const SolveScalars sc = sched::host_scalars(1e-3, QBVM_PQ, p->tau);
@@ -870,7 +879,7 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
         return QBVM_OK;
       }, &tm);
       if (rc) return rc;
-      ms[8 + V] = tm;
+      ms[12 + V] = tm;
       if (tm < best) {
         best = tm;
         bestv = V;
@@ -886,9 +895,10 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
       g_tuned[std::make_tuple(p->device, 1, Ns)] = p->var_cols;
     }
     if (Nt2 && p->d >= 2) g_tuned[std::make_tuple(p->device, 2, Nt2)] = p->var_time;
+    if (gt && p->d >= 2) g_tuned[std::make_tuple(p->device, 3, p->Nt)] = p->var_time;
   }
   if (ms_out)
-    for (int i = 0; i < 12; ++i) ms_out[i] = ms[i];
+    for (int i = 0; i < 16; ++i) ms_out[i] = ms[i];
   return QBVM_OK;
 }
 

@@ -19,6 +19,7 @@
 #include "qbvm_internal.hpp"
 #include "qbvm_bodies.hpp"
 #include "qbvm_bodies_p2.hpp"
+#include "qbvm_bodies_gt.hpp"
 #include "qbvm_p2_sizes.hpp"
 
 #include <cmath>
@@ -38,19 +39,30 @@ void upload_radix_roots(const c64* roots, int count) {
 template <int N, int V>
 __global__ __launch_bounds__(p2sz::dst_T(N, V)) void k_dst_rows_p2(DstArgs a) {
   extern __shared__ c64 lds[];
-  dst_rows_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V)>(a, blockIdx.x, lds);
+  dst_rows_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), p2sz::dst_tw_in_lds(N, V)>(a, blockIdx.x, lds);
 }
 
 template <int N, int V>
 __global__ __launch_bounds__(p2sz::dst_T(N, V)) void k_dst_cols_p2(DstArgs a) {
   extern __shared__ c64 lds[];
-  dst_cols_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V)>(a, blockIdx.x, lds);
+  dst_cols_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), p2sz::dst_tw_in_lds(N, V)>(a, blockIdx.x, lds);
 }
 
 template <int N, int V, bool RADER>
 __global__ __launch_bounds__(p2sz::time_T(V)) void k_time_p2(TimeArgs a) {
   extern __shared__ c64 lds[];
   time_p2_body<N, p2sz::time_E(V), p2sz::time_S(N, V), RADER, p2sz::time_pad(V)>(a, blockIdx.x, lds);
+}
+
+template <int A, int B, int V>
+__global__ __launch_bounds__(p2sz::gt_T(A, V)) void k_time_gt(TimeArgs a) {
+  extern __shared__ c64 lds[];
+  time_gt_body<A, B, p2sz::gt_S(V)>(a, blockIdx.x, lds);
+}
+
+static const void* time_gt_fn(int A, int B, int V) {
+  if (A == 3 && B == 43) return V == 0 ? (const void*)&k_time_gt<3, 43, 0> : (const void*)&k_time_gt<3, 43, 1>;
+  return nullptr;
 }
 
 template <int N, int V>
@@ -69,6 +81,8 @@ static const void* dst_fn_n(int V, bool cols) {
     case 2: return dst_fn_nv<N, 2>(cols);
     case 3: return dst_fn_nv<N, 3>(cols);
     case 4: return dst_fn_nv<N, 4>(cols);
+    case 5: return dst_fn_nv<N, 5>(cols);
+    case 6: return dst_fn_nv<N, 6>(cols);
     default: return nullptr;
   }
 }
@@ -541,6 +555,45 @@ hipError_t launch_feat_predict(long long nm, double hd, const double* ghat, doub
   return hipGetLastError();
 }
 
+// Per-solve tables of the time transform: d_j/tau and f0s/N_t gamma_l^{-1}, j, l < N_t.
+__global__ void k_alpha_tables(int Nt, double tau, int variant, double alpha, const double* alpha_dev, c64* tabs) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Nt) return;
+  const SolveScalars sc = scalars_from_alpha(alpha_dev ? *alpha_dev : alpha, variant, tau);
+  const double croot = exp(sc.logabsw / (double)Nt);
+  tabs[j] = shift_over_tau(j, Nt, croot, 1.0 / tau);
+  tabs[Nt + j] = inv_gamma(j, Nt, sc.logabsw, sc.f0s / (double)Nt);
+}
+
+hipError_t launch_alpha_tables(int Nt, double tau, int variant, double alpha, const double* alpha_dev, c64* tabs,
+                               hipStream_t s, NodeCtx* nc) {
+  struct Args {
+    int Nt;
+    double tau;
+    int variant;
+    double alpha;
+    const double* alpha_dev;
+    c64* tabs;
+  };
+  void* args[] = {&Nt, &tau, &variant, &alpha, &alpha_dev, &tabs};
+  const dim3 grid((Nt + 255) / 256), block(256);
+  if (!nc) return hipLaunchKernel((const void*)&k_alpha_tables, grid, block, args, 0, s);
+  hipKernelNodeParams p{};
+  p.func = (void*)&k_alpha_tables;
+  p.gridDim = grid;
+  p.blockDim = block;
+  p.sharedMemBytes = 0;
+  p.kernelParams = args;
+  hipGraphNode_t node;
+  const hipError_t e = hipGraphAddKernelNode(&node, nc->graph, nc->has_dep ? &nc->dep : nullptr,
+                                             nc->has_dep ? 1 : 0, &p);
+  if (e == hipSuccess) {
+    nc->dep = node;
+    nc->has_dep = true;
+  }
+  return e;
+}
+
 __global__ void k_copy_scale(const double* in, double* out, long long n, double s) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = in[i] * s;
@@ -605,6 +658,9 @@ hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds
   const void* f = a.fft.wide ? (const void*)&k_time<true> : (const void*)&k_time<false>;
   if (a.fft.p2) {
     f = time_p2_fn(a.fft.p2, a.var, a.fft.kind == kRader);
+    if (!f) return hipErrorInvalidValue;
+  } else if (a.fft.gtA) {
+    f = time_gt_fn(a.fft.gtA, a.fft.gtB, a.var);
     if (!f) return hipErrorInvalidValue;
   }
   return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);

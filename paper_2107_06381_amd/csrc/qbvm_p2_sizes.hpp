@@ -2,7 +2,8 @@
 // the kernels and the CPU build).  Variants differ in the complex values per
 // lane E and the signals per workgroup S:
 //   sine passes: 0 = E16, 256 lanes; 1 = E8, 256 lanes; 2 = E8, one signal (input
-//                transform); 3 = E16, 512 lanes; 4 = E8, 512 lanes
+//                transform); 3 = E16, 512 lanes; 4 = E8, 512 lanes; 5, 6 = as 3, 4 with the
+//                twiddles read from global memory (less LDS, two workgroups per CU)
 //   time kernel: 0 = E16, 128 lanes; 1 = E8, 256 lanes; 2, 3 = as 0, 1 without the
 //                bank-conflict pad (less LDS, more workgroups per CU)
 #pragma once
@@ -14,11 +15,11 @@
 namespace qbvm {
 namespace p2sz {
 
-constexpr int kDstVariants = 5;
+constexpr int kDstVariants = 7;
 constexpr int kTimeVariants = 2;
 constexpr int kTimeMaxN = 2048;
 
-constexpr int dst_E(int V) { return (V == 0 || V == 3) ? 16 : 8; }
+constexpr int dst_E(int V) { return (V == 0 || V == 3 || V == 5) ? 16 : 8; }
 constexpr int dst_T(int N, int V) { return V == 2 ? N / 8 : (V >= 3 ? 512 : 256); }
 constexpr int dst_S(int N, int V) { return V == 2 ? 1 : dst_T(N, V) * dst_E(V) / N; }
 constexpr size_t dst_lds(int N, int V, bool cols);
@@ -37,6 +38,7 @@ constexpr bool time_valid(int N, int V) {
 }
 
 constexpr bool tw_in_lds(int N) { return N <= 1024; }
+constexpr bool dst_tw_in_lds(int N, int V) { return tw_in_lds(N) && V < 5; }
 
 // first radix of the (N, E) sequence (mirrors P2Radices, checked there by static_assert)
 constexpr int first_radix(int N, int E) { return (E == 16 && N >= 128 && N != 512) ? 16 : 8; }
@@ -44,7 +46,7 @@ constexpr int first_radix(int N, int E) { return (E == 16 && N >= 128 && N != 51
 // exchange buffer ([signal][position] padded for rows, [position][signal] for columns) + twiddles
 constexpr size_t dst_lds(int N, int V, bool cols) {
   return sizeof(c64) * ((cols ? (size_t)(N + N / first_radix(N, dst_E(V))) : (size_t)(N + N / 16)) * dst_S(N, V) +
-                        (tw_in_lds(N) ? N : 0));
+                        (dst_tw_in_lds(N, V) ? N : 0));
 }
 
 // exchange buffer, twiddles, Rader kernel spectrum, d_j/tau and gamma_l^{-1}, two index maps
@@ -53,6 +55,19 @@ constexpr size_t time_lds(int N, int V, int Nt) {
                         (tw_in_lds(N) ? N : 0) + N +
                         2 * (size_t)Nt) +
          sizeof(int) * 2 * (size_t)N;
+}
+
+// Good-Thomas time kernels (N_t = A * B, gcd 1, B an odd prime); variant V: S = 32 (V=0) or 64
+constexpr int kGtPairs[][2] = {{3, 43}};
+constexpr bool gt_supported(int A, int B) {
+  for (const auto& p : kGtPairs)
+    if (p[0] == A && p[1] == B) return true;
+  return false;
+}
+constexpr int gt_S(int V) { return V == 0 ? 32 : 64; }
+constexpr int gt_T(int A, int V) { return A * gt_S(V); }
+constexpr size_t gt_lds(int A, int B, int V) {
+  return sizeof(c64) * ((size_t)A * B * gt_S(V) + 2 * (size_t)A * B);
 }
 
 }  // namespace p2sz

@@ -31,7 +31,7 @@ struct Geom {
 // contiguous x_1 pass goes last and writes the unpadded output.
 inline long long padded_pitch(int m) { return ((long long)m + 63) / 64 * 64; }
 inline bool use_padded(const Geom& g) {
-  return g.d >= 2 && g.sfft.p2 && g.tfft.p2 && p2sz::time_valid(g.tfft.p2, 0);
+  return g.d >= 2 && g.sfft.p2 && ((g.tfft.p2 && p2sz::time_valid(g.tfft.p2, 0)) || g.tfft.gtA);
 }
 inline long long padded_elems(const Geom& g) { return (long long)g.Nt * (g.nmodes / g.m) * padded_pitch(g.m); }
 
@@ -178,7 +178,14 @@ inline Launch<TimeArgs> time_step(const Geom& g, SolveScalars sc, const double* 
   t.pitch = 0;
   t.tiles_per_row = 0;
   size_t lds = lds_time(g, lev_count);
-  if (g.tfft.p2 && p2sz::time_valid(g.tfft.p2, 0) && lev_first == 0 && lev_count == g.Nt) {
+  if (g.tfft.gtA && lev_first == 0 && lev_count == g.Nt) {
+    const int V = (g.var_time == 0 || g.var_time == 1) ? g.var_time : 0;
+    t.var = V;
+    t.S = p2sz::gt_S(V);
+    t.threads = p2sz::gt_T(g.tfft.gtA, V);
+    t.fft.p2 = 0;
+    lds = p2sz::gt_lds(g.tfft.gtA, g.tfft.gtB, V);
+  } else if (g.tfft.p2 && p2sz::time_valid(g.tfft.p2, 0) && lev_first == 0 && lev_count == g.Nt) {
     const int N = g.tfft.p2;
     const int V = p2sz::time_valid(N, g.var_time) ? g.var_time : 0;
     t.var = V;
@@ -187,6 +194,7 @@ inline Launch<TimeArgs> time_step(const Geom& g, SolveScalars sc, const double* 
     lds = p2sz::time_lds(N, V, g.Nt);
   } else {
     t.fft.p2 = 0;  // generic kernel
+    t.fft.gtA = t.fft.gtB = 0;
   }
   const long long nwg = (g.nmodes + 2LL * t.S - 1) / (2LL * t.S);
   return {t, nwg, lds};

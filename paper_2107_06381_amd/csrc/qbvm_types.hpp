@@ -43,6 +43,7 @@ struct FftPlanDev {
   const int* gfwd;   // Rader: gfwd[q] = g^q mod n, q < n-1
   const int* ginvt;  // Rader: ginvt[p] = g^{-p} mod n, p < n-1
   int p2;            // core length if it has a compile-time power-of-two kernel (64..4096), else 0
+  int gtA, gtB;      // n = gtA * gtB handled by the compile-time Good-Thomas time kernel (else 0)
 };
 
 // Per-solve scalars derived from (alpha, variant, tau).
@@ -73,6 +74,7 @@ struct TimeArgs {
   int var;      // power-of-two kernel variant
   long long pitch;   // > 0: y rows of m modes padded to this pitch (tiles never straddle rows)
   int tiles_per_row;
+  const c64* tabs;   // optional: [N_t] d_j/tau then [N_t] f0s/N_t gamma_l^{-1} for this solve
   FftPlanDev fft;
 };
 

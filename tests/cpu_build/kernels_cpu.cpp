@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../paper_2107_06381_amd/csrc/qbvm_bodies_p2.hpp"
+#include "../../paper_2107_06381_amd/csrc/qbvm_bodies_gt.hpp"
 #include "../../paper_2107_06381_amd/csrc/qbvm_fft_plan.hpp"
 #include "../../paper_2107_06381_amd/csrc/qbvm_schedule.hpp"
 
@@ -144,8 +145,9 @@ static void dst_p2_nv(const Launch<DstArgs>& Lz) {
   if constexpr (p2sz::dst_valid(N, V)) {
     const DstArgs& A = Lz.args;
     constexpr int E = p2sz::dst_E(V), S = p2sz::dst_S(N, V);
-    if (A.inner > 1) run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_cols_p2_body<N, E, S>(A, wg, l); });
-    else run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_rows_p2_body<N, E, S>(A, wg, l); });
+    constexpr bool TWL = p2sz::dst_tw_in_lds(N, V);
+    if (A.inner > 1) run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_cols_p2_body<N, E, S, TWL>(A, wg, l); });
+    else run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_rows_p2_body<N, E, S, TWL>(A, wg, l); });
   } else {
     exit(11);
   }
@@ -159,6 +161,8 @@ static void dst_p2_n(const Launch<DstArgs>& Lz) {
     case 2: dst_p2_nv<N, 2>(Lz); break;
     case 3: dst_p2_nv<N, 3>(Lz); break;
     case 4: dst_p2_nv<N, 4>(Lz); break;
+    case 5: dst_p2_nv<N, 5>(Lz); break;
+    case 6: dst_p2_nv<N, 6>(Lz); break;
     default: exit(12);
   }
 }
@@ -198,6 +202,17 @@ static void time_p2_n(const Launch<TimeArgs>& t) {
     case 4096: F<4096>(ARG); break;                  \
     default: exit(9);                                \
   }
+
+static void run_time_fast(const Launch<TimeArgs>& t) {
+  const TimeArgs& A = t.args;
+  if (A.fft.gtA == 3 && A.fft.gtB == 43) {
+    if (A.var == 0) run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, 32>(A, wg, l); });
+    else run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, 64>(A, wg, l); });
+    return;
+  }
+  if (!A.fft.p2) exit(15);
+  P2_SWITCH(A.fft.p2, time_p2_n, t)
+}
 
 static void run_dst(const sched::Geom& g, const double* in, double* out, long long batch, bool input) {
   for (const auto& Lz : sched::dst_passes(g, in, out, batch, input)) {
@@ -286,8 +301,17 @@ int main(int argc, char** argv) {
       double* W = new double[sched::padded_elems(g)];
       for (long long i = 0; i < sched::padded_elems(g); ++i) W[i] = 1e300;  // pad slots must not leak
       run_dst(g, gd, gh, 1, true);
-      const auto t = sched::time_step_padded(g, sc, nullptr, variant, gh, W);
-      P2_SWITCH(t.args.fft.p2, time_p2_n, t)
+      auto t = sched::time_step_padded(g, sc, nullptr, variant, gh, W);
+      std::vector<c64> tabs(2 * (size_t)g.Nt);
+      {
+        const double croot = std::exp(sc.logabsw / (double)g.Nt);
+        for (int j = 0; j < g.Nt; ++j) {
+          tabs[j] = shift_over_tau(j, g.Nt, croot, 1.0 / g.tau);
+          tabs[g.Nt + j] = inv_gamma(j, g.Nt, sc.logabsw, sc.f0s / (double)g.Nt);
+        }
+      }
+      t.args.tabs = tabs.data();
+      run_time_fast(t);
       for (const auto& Lz : sched::padded_passes(g, W, y)) {
         P2_SWITCH(Lz.args.fft.p2, dst_p2_n, Lz)
       }
@@ -307,8 +331,8 @@ int main(int argc, char** argv) {
       run_dst(g, gd, y, 1, true);
       const auto t = sched::time_step(g, sc, nullptr, variant, y, y, 0, g.Nt);
       const TimeArgs& A = t.args;
-      if (A.fft.p2) {
-        P2_SWITCH(A.fft.p2, time_p2_n, t)
+      if (A.fft.p2 || A.fft.gtA) {
+        run_time_fast(t);
       } else if (A.fft.wide) {
         run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_body<true>(A, wg, l); });
       } else {

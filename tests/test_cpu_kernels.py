@@ -55,7 +55,7 @@ DST_CASES = [(1, 9, 3), (2, 13, 2), (2, 100, 1), (3, 6, 2),
              (2, 31, 3), (3, 63, 1), (2, 127, 2), (2, 255, 1), (2, 511, 1), (2, 1023, 1), (1, 2047, 5)]
 
 
-@pytest.mark.parametrize("variants", [(0, 1, 0), (1, 0, 1), (3, 4, 0), (4, 3, 1)])
+@pytest.mark.parametrize("variants", [(0, 1, 0), (1, 0, 1), (3, 4, 0), (4, 3, 1), (5, 6, 0), (6, 5, 0)])
 @pytest.mark.parametrize("d,m,batch", DST_CASES)
 def test_dst_passes(exe, tmp_path, d, m, batch, variants):
     """Every kernel variant of the sine passes (levels: E16 / E8; input transform: one signal)."""
@@ -78,8 +78,10 @@ def test_dst_passes(exe, tmp_path, d, m, batch, variants):
     (2, 255, 6, 1e-3, 0),
     # padded level pipeline (power-of-two sine and time kernels): 2D Rader-257, 2D 256, 3D 64
     (2, 63, 256, 1e-4, 0), (2, 63, 255, 1e-5, 1), (3, 31, 63, 1e-3, 0),
+    # Good-Thomas time kernel, N_t = 129 = 3 * 43 (padded: 2D m=63, 3D m=31; in place: 2D m=40)
+    (2, 63, 128, 1e-4, 0), (3, 31, 128, 1e-3, 1), (2, 40, 128, 1e-5, 0),
 ])
-@pytest.mark.parametrize("kv", [(0, 4, 0, 1), (4, 1, 1, 1), (1, 3, 2, 0), (3, 0, 3, 0)])
+@pytest.mark.parametrize("kv", [(0, 4, 0, 1), (4, 1, 1, 1), (1, 3, 2, 0), (3, 0, 3, 0), (6, 5, 3, 1)])
 def test_solve_schedule_vs_oracle(exe, tmp_path, d, m, n, alpha, variant, kv):
     """Full solve (1D Thomas path, 2D/3D sine-transform path; padded and in-place
     level pipelines) vs the closed form, for several power-of-two kernel variants."""
