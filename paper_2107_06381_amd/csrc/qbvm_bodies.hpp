@@ -36,6 +36,16 @@ __device__ __forceinline__ c64 inv_gamma(int l, int Nt, double logabsw, double s
   return {g * cs, -g * sn};
 }
 
+// 1/x for positive normal x: the hardware reciprocal estimate refined by two Newton
+// steps (a few ulp), in place of an IEEE division
+__device__ __forceinline__ double recip_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // eigenvalue of -Lap_h for flattened mode index k (x_1 fastest)
 __device__ __forceinline__ double mode_mu(long long k, int d, int m, const double* __restrict__ mu1d) {
   double mu = 0.0;

@@ -112,8 +112,8 @@ __device__ __forceinline__ void time_gt_body(const TimeArgs& a, long long wg, c6
     n = n >= N ? n - N : n;
     const c64 z = dt[n];
     const double xa = z.re + mua, xb = z.re + mub;
-    const double ia = ga / (xa * xa + z.im * z.im);
-    const double ib = gb / (xb * xb + z.im * z.im);
+    const double ia = ga * recip_nr(xa * xa + z.im * z.im);
+    const double ib = gb * recip_nr(xb * xb + z.im * z.im);
     v[b] = {ia * xa + ib * z.im, ib * xb - ia * z.im};
   }
   // length-B DFT over b -> Y[k2][ra][s]
@@ -130,8 +130,12 @@ __device__ __forceinline__ void time_gt_body(const TimeArgs& a, long long wg, c6
       const int l = (B * c1 * k1 + A * c2 * k2) % N;
       const c64 yv = cmul(gi[l], w[k1]);
       double* yl = a.y + (long long)l * a.ystride;
-      if (oka) yl[oa] = yv.re;
-      if (okb) yl[oa + 1] = yv.im;
+      if (a.pitch > 0) {  // aligned pair; a second mode past the row end lands in the padding
+        if (oka) *reinterpret_cast<c64*>(yl + oa) = yv;
+      } else {
+        if (oka) yl[oa] = yv.re;
+        if (okb) yl[oa + 1] = yv.im;
+      }
     }
   }
 }

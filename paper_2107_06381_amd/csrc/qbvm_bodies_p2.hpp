@@ -37,79 +37,129 @@ __device__ __forceinline__ const c64* p2_twiddles(const FftPlanDev& f, c64* tw_l
   }
 }
 
+// The sine passes are persistent: a workgroup takes the tiles first, first + step,
+// ... and loads the lines of its next tile into registers while the current tile
+// is transformed, so global-load latency overlaps the FFT.  Lines past the end are
+// read at a clamped, valid address and zeroed before the transform.
+
 // Rows of [outer][m] (inner == 1): lanes walk along lines, two lines per signal.
 template <int N, int E, int S, bool TWL = p2sz::tw_in_lds(N)>
-__device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long wg, c64* lds) {
+__device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long first, long long step, c64* lds) {
   using L = P2Layout<N, E, S, false>;
   c64* buf = lds;
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
   const c64* tw = p2_twiddles<N, TWL>(a.fft, buf + L::lds_elems(), t, L::T);
   __syncthreads();
   const int m = a.len;
-  const long long la = wg * 2LL * S + 2 * s, lb = la + 1;
-  const bool oka = la < a.outer, okb = lb < a.outer;
-  const double* xa = a.in + la * a.in_pitch;
-  const double* xb = a.in + lb * a.in_pitch;
-  c64 v[E];
+  const long long ntiles = (a.outer + 2LL * S - 1) / (2LL * S);
+  const long long last = a.outer - 1;
+  double ra[E], rb[E];
+  auto fetch = [&](long long tile) {
+    const long long la = tile * 2LL * S + 2 * s, lb = la + 1;
+    const double* xa = a.in + (la < last ? la : last) * a.in_pitch;
+    const double* xb = a.in + (lb < last ? lb : last) * a.in_pitch;
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    double sg;
-    const int i = odd_ext_index(p2_in_pos<N, E, 0>(u, e), m, sg);
-    double va = 0.0, vb = 0.0;
-    if (i >= 0) {
-      if (oka) va = sg * xa[i];
-      if (okb) vb = sg * xb[i];
+    for (int e = 0; e < E; ++e) {
+      double sg;
+      const int i = odd_ext_index(p2_in_pos<N, E, 0>(u, e), m, sg);
+      ra[e] = xa[i < 0 ? 0 : i];
+      rb[e] = xb[i < 0 ? 0 : i];
     }
-    v[e] = {va, vb};
-  }
-  p2_fft<N, E, L>(v, s, u, buf, tw);
-  double* oa = a.out + la * a.out_pitch;
-  double* ob = a.out + lb * a.out_pitch;
+  };
+  if (first < ntiles) fetch(first);
+  for (long long tile = first; tile < ntiles; tile += step) {
+    const long long la = tile * 2LL * S + 2 * s, lb = la + 1;
+    const bool oka = la < a.outer, okb = lb < a.outer;
+    c64 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = p2_out_pos<N, E>(u, e);
-    if (i >= 1 && i <= m) {
-      if (oka) oa[i - 1] = -v[e].im * a.scale;
-      if (okb) ob[i - 1] = v[e].re * a.scale;
+    for (int e = 0; e < E; ++e) {
+      double sg;
+      (void)odd_ext_index(p2_in_pos<N, E, 0>(u, e), m, sg);
+      v[e] = {oka ? sg * ra[e] : 0.0, okb ? sg * rb[e] : 0.0};
+    }
+    if (tile + step < ntiles) fetch(tile + step);
+    p2_fft<N, E, L>(v, s, u, buf, tw);
+    double* oa = a.out + la * a.out_pitch;
+    double* ob = a.out + lb * a.out_pitch;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = p2_out_pos<N, E>(u, e);
+      if (i >= 1 && i <= m) {
+        if (oka) oa[i - 1] = -v[e].im * a.scale;
+        if (okb) ob[i - 1] = v[e].re * a.scale;
+      }
     }
   }
 }
 
+// column c of a columns pass holds data (32-bit form: inner < 2^31 is checked on the host)
+__device__ __forceinline__ bool dst_col_ok32(const DstArgs& a, long long c) {
+  return c < a.inner && (a.colmod == 0 || ((int)c % a.colmod) < a.colvalid);
+}
+
 // Columns of [outer][m][inner] (inner > 1): lanes of a wave take consecutive columns.
-template <int N, int E, int S, bool TWL = p2sz::tw_in_lds(N)>
-__device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long wg, c64* lds) {
+// VEC2: the two columns of a signal are one aligned 16-byte pair (padded layout:
+// inner, kstride and ostride even); a pair with only its first column valid is
+// stored whole, its second value landing in a padding column.
+template <int N, int E, int S, bool VEC2, bool TWL = p2sz::tw_in_lds(N)>
+__device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long first, long long step, c64* lds) {
   using L = P2Layout<N, E, S, true>;
   c64* buf = lds;
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
   const c64* tw = p2_twiddles<N, TWL>(a.fft, buf + L::lds_elems(), t, L::T);
   __syncthreads();
   const int m = a.len;
-  const long long o = wg / a.tiles_per_outer;
-  const long long ca = (wg - o * a.tiles_per_outer) * 2LL * S + 2 * s, cb = ca + 1;
-  const bool oka = dst_col_ok(a, ca), okb = dst_col_ok(a, cb);
-  const double* base = a.in + o * a.ostride;
-  c64 v[E];
+  const long long tpo = a.tiles_per_outer;
+  const long long ntiles = a.outer * tpo;
+  const long long cmax = a.inner - (VEC2 ? 2 : 1);
+  double ra[E], rb[E];
+  auto fetch = [&](long long tile) {
+    const long long o = tile / tpo;
+    const long long ca = (tile - o * tpo) * 2LL * S + 2 * s;
+    const double* base = a.in + o * a.ostride;
+    const long long pa = ca < cmax ? ca : cmax;
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    double sg;
-    const int i = odd_ext_index(p2_in_pos<N, E, 0>(u, e), m, sg);
-    double va = 0.0, vb = 0.0;
-    if (i >= 0) {
-      const double* row = base + (long long)i * a.kstride;
-      if (oka) va = sg * row[ca];
-      if (okb) vb = sg * row[cb];
+    for (int e = 0; e < E; ++e) {
+      double sg;
+      const int i = odd_ext_index(p2_in_pos<N, E, 0>(u, e), m, sg);
+      const double* row = base + (long long)(i < 0 ? 0 : i) * a.kstride;
+      if constexpr (VEC2) {
+        const c64 w = *reinterpret_cast<const c64*>(row + pa);  // (column pa, column pa + 1)
+        ra[e] = w.re;
+        rb[e] = w.im;
+      } else {
+        ra[e] = row[pa];
+        rb[e] = row[ca + 1 < cmax ? ca + 1 : cmax];
+      }
     }
-    v[e] = {va, vb};
-  }
-  p2_fft<N, E, L>(v, s, u, buf, tw);
-  double* obase = a.out + o * a.ostride;
+  };
+  if (first < ntiles) fetch(first);
+  for (long long tile = first; tile < ntiles; tile += step) {
+    const long long o = tile / tpo;
+    const long long ca = (tile - o * tpo) * 2LL * S + 2 * s, cb = ca + 1;
+    const bool oka = dst_col_ok32(a, ca), okb = dst_col_ok32(a, cb);
+    c64 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = p2_out_pos<N, E>(u, e);
-    if (i >= 1 && i <= m) {
-      double* row = obase + (long long)(i - 1) * a.kstride;
-      if (oka) row[ca] = -v[e].im * a.scale;
-      if (okb) row[cb] = v[e].re * a.scale;
+    for (int e = 0; e < E; ++e) {
+      double sg;
+      (void)odd_ext_index(p2_in_pos<N, E, 0>(u, e), m, sg);
+      v[e] = {oka ? sg * ra[e] : 0.0, okb ? sg * rb[e] : 0.0};
+    }
+    if (tile + step < ntiles) fetch(tile + step);
+    p2_fft<N, E, L>(v, s, u, buf, tw);
+    double* obase = a.out + o * a.ostride;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = p2_out_pos<N, E>(u, e);
+      if (i >= 1 && i <= m) {
+        double* row = obase + (long long)(i - 1) * a.kstride;
+        if constexpr (VEC2) {
+          if (oka) *reinterpret_cast<c64*>(row + ca) = c64{-v[e].im * a.scale, v[e].re * a.scale};
+        } else {
+          if (oka) row[ca] = -v[e].im * a.scale;
+          if (okb) row[cb] = v[e].re * a.scale;
+        }
+      }
     }
   }
 }
@@ -179,8 +229,8 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
   auto input = [&](int j) -> c64 {
     const c64 z = dt[j];
     const double xa = z.re + mua, xb = z.re + mub;
-    const double ia = ga / (xa * xa + z.im * z.im);
-    const double ib = gb / (xb * xb + z.im * z.im);
+    const double ia = ga * recip_nr(xa * xa + z.im * z.im);
+    const double ib = gb * recip_nr(xb * xb + z.im * z.im);
     return {ia * xa + ib * z.im, ib * xb - ia * z.im};
   };
   c64 v[E];
@@ -190,11 +240,18 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
     v[e] = input(RADER ? gfw[q] : q);
   }
   p2_fft<N, E, L>(v, s, u, buf, tw);
+  // padded rows (pitch > 0): the pair is one aligned 16-byte store; a pair whose
+  // second mode is past the row end writes that value into the row padding
+  const bool pair = a.pitch > 0;
   auto store = [&](int l, c64 X) {
     const c64 yv = cmul(gi[l], X);
     double* yl = a.y + (long long)l * a.ystride;
-    if (oka) yl[oa] = yv.re;
-    if (okb) yl[oa + 1] = yv.im;
+    if (pair) {
+      if (oka) *reinterpret_cast<c64*>(yl + oa) = yv;
+    } else {
+      if (oka) yl[oa] = yv.re;
+      if (okb) yl[oa + 1] = yv.im;
+    }
   };
   if constexpr (RADER) {
     const c64 x0 = input(0);

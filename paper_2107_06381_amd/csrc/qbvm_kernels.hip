@@ -23,8 +23,10 @@
 #include "qbvm_p2_sizes.hpp"
 
 #include <cmath>
+#include <map>
 #include <mutex>
 #include <set>
+#include <tuple>
 
 namespace qbvm {
 
@@ -36,16 +38,20 @@ void upload_radix_roots(const c64* roots, int count) {
 
 // Power-of-two kernels, one symbol per (N, variant); the input transform always
 // uses variant 2, the passes over the solution levels variants 0 or 1.
+// The sine-pass kernels are persistent: the grid is sized to the resident capacity
+// and every workgroup strides over the tiles.
 template <int N, int V>
 __global__ __launch_bounds__(p2sz::dst_T(N, V)) void k_dst_rows_p2(DstArgs a) {
   extern __shared__ c64 lds[];
-  dst_rows_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), p2sz::dst_tw_in_lds(N, V)>(a, blockIdx.x, lds);
+  dst_rows_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), p2sz::dst_tw_in_lds(N, V)>(a, blockIdx.x, gridDim.x,
+                                                                                      lds);
 }
 
-template <int N, int V>
+template <int N, int V, bool VEC2>
 __global__ __launch_bounds__(p2sz::dst_T(N, V)) void k_dst_cols_p2(DstArgs a) {
   extern __shared__ c64 lds[];
-  dst_cols_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), p2sz::dst_tw_in_lds(N, V)>(a, blockIdx.x, lds);
+  dst_cols_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), VEC2, p2sz::dst_tw_in_lds(N, V)>(a, blockIdx.x,
+                                                                                            gridDim.x, lds);
 }
 
 template <int N, int V, bool RADER>
@@ -66,23 +72,25 @@ static const void* time_gt_fn(int A, int B, int V) {
 }
 
 template <int N, int V>
-static const void* dst_fn_nv(bool cols) {
-  if constexpr (p2sz::dst_valid(N, V))
-    return cols ? (const void*)&k_dst_cols_p2<N, V> : (const void*)&k_dst_rows_p2<N, V>;
-  else
+static const void* dst_fn_nv(bool cols, bool vec2) {
+  if constexpr (p2sz::dst_valid(N, V)) {
+    if (!cols) return (const void*)&k_dst_rows_p2<N, V>;
+    return vec2 ? (const void*)&k_dst_cols_p2<N, V, true> : (const void*)&k_dst_cols_p2<N, V, false>;
+  } else {
     return nullptr;
+  }
 }
 
 template <int N>
-static const void* dst_fn_n(int V, bool cols) {
+static const void* dst_fn_n(int V, bool cols, bool vec2) {
   switch (V) {
-    case 0: return dst_fn_nv<N, 0>(cols);
-    case 1: return dst_fn_nv<N, 1>(cols);
-    case 2: return dst_fn_nv<N, 2>(cols);
-    case 3: return dst_fn_nv<N, 3>(cols);
-    case 4: return dst_fn_nv<N, 4>(cols);
-    case 5: return dst_fn_nv<N, 5>(cols);
-    case 6: return dst_fn_nv<N, 6>(cols);
+    case 0: return dst_fn_nv<N, 0>(cols, vec2);
+    case 1: return dst_fn_nv<N, 1>(cols, vec2);
+    case 2: return dst_fn_nv<N, 2>(cols, vec2);
+    case 3: return dst_fn_nv<N, 3>(cols, vec2);
+    case 4: return dst_fn_nv<N, 4>(cols, vec2);
+    case 5: return dst_fn_nv<N, 5>(cols, vec2);
+    case 6: return dst_fn_nv<N, 6>(cols, vec2);
     default: return nullptr;
   }
 }
@@ -118,7 +126,7 @@ static const void* time_fn_n(int V, bool rader) {
     default: return nullptr;                           \
   }
 
-static const void* dst_p2_fn(int N, int V, bool cols) { QBVM_P2_SWITCH(N, dst_fn_n, V, cols) }
+static const void* dst_p2_fn(int N, int V, bool cols, bool vec2) { QBVM_P2_SWITCH(N, dst_fn_n, V, cols, vec2) }
 static const void* time_p2_fn(int N, int V, bool rader) { QBVM_P2_SWITCH(N, time_fn_n, V, rader) }
 
 // ROLE only separates the kernel symbols (0: transform of g_delta, 1: rows of the
@@ -618,6 +626,38 @@ static void allow_big_lds(const void* f) {
     (void)hipGetLastError();
 }
 
+// Workgroups of a persistent kernel over `tiles` tiles: the resident capacity of
+// the device (occupancy x compute units), lowered to even out the tiles per
+// workgroup.  Capacities are cached per (kernel, block, LDS, device).
+static long long persistent_grid(const void* f, int threads, size_t lds, long long tiles) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, int, size_t, int>, long long> cap_of;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return tiles;
+  }
+  long long cap;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_tuple(f, threads, lds, dev);
+    auto it = cap_of.find(key);
+    if (it == cap_of.end()) {
+      int cus = 0, per = 0;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, threads, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        cus = per = 0;
+      }
+      it = cap_of.emplace(key, (long long)(per < 1 ? 1 : per) * (cus < 1 ? 1 : cus)).first;
+    }
+    cap = it->second;
+  }
+  if (tiles <= cap) return tiles;
+  const long long rounds = (tiles + cap - 1) / cap;
+  return (tiles + rounds - 1) / rounds;
+}
+
 template <class A>
 static hipError_t enqueue1(const void* f, dim3 grid, dim3 block, size_t lds, hipStream_t s, const A& a,
                            NodeCtx* nc) {
@@ -648,8 +688,10 @@ hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, 
       {(const void*)&k_dst<true, 0>, (const void*)&k_dst<true, 1>, (const void*)&k_dst<true, 2>}};
   const void* f = tab[a.fft.wide ? 1 : 0][role < 0 ? 0 : (role > 2 ? 2 : role)];
   if (a.fft.p2) {
-    f = dst_p2_fn(a.fft.p2, a.var, a.inner > 1);
+    f = dst_p2_fn(a.fft.p2, a.var, a.inner > 1, a.inner > 1 && p2sz::dst_pairs_aligned(a));
     if (!f) return hipErrorInvalidValue;
+    allow_big_lds(f);
+    nwg = persistent_grid(f, threads, lds, nwg);
   }
   return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
 }

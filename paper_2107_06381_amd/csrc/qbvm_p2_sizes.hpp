@@ -9,6 +9,7 @@
 #pragma once
 
 #include <cstddef>
+#include <cstdint>
 
 #include "qbvm_types.hpp"
 
@@ -55,6 +56,13 @@ constexpr size_t time_lds(int N, int V, int Nt) {
                         (tw_in_lds(N) ? N : 0) + N +
                         2 * (size_t)Nt) +
          sizeof(int) * 2 * (size_t)N;
+}
+
+// Columns pass whose two columns per signal form aligned 16-byte pairs: padded
+// rows (colmod > 0) and even strides, 16-byte aligned buffers.
+inline bool dst_pairs_aligned(const DstArgs& a) {
+  return a.colmod > 0 && a.colmod % 2 == 0 && a.inner % 2 == 0 && a.kstride % 2 == 0 && a.ostride % 2 == 0 &&
+         (reinterpret_cast<std::uintptr_t>(a.in) % 16) == 0 && (reinterpret_cast<std::uintptr_t>(a.out) % 16) == 0;
 }
 
 // Good-Thomas time kernels (N_t = A * B, gcd 1, B an odd prime); variant V: S = 32 (V=0) or 64

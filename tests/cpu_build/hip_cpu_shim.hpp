@@ -29,3 +29,5 @@ inline void sincospi(double x, double* s, double* c) {
   *c = (double)cosl(a);
 }
 inline double exp10(double x) { return std::pow(10.0, x); }
+// the hardware reciprocal estimate, exact here (the bodies refine it by Newton steps)
+#define __builtin_amdgcn_rcp(x) (1.0 / (x))

@@ -146,8 +146,14 @@ static void dst_p2_nv(const Launch<DstArgs>& Lz) {
     const DstArgs& A = Lz.args;
     constexpr int E = p2sz::dst_E(V), S = p2sz::dst_S(N, V);
     constexpr bool TWL = p2sz::dst_tw_in_lds(N, V);
-    if (A.inner > 1) run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_cols_p2_body<N, E, S, TWL>(A, wg, l); });
-    else run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_rows_p2_body<N, E, S, TWL>(A, wg, l); });
+    // persistent bodies on a small grid, so every workgroup walks several tiles
+    const long long G = Lz.nwg < 3 ? Lz.nwg : 3;
+    if (A.inner > 1 && p2sz::dst_pairs_aligned(A))
+      run_grid(G, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_cols_p2_body<N, E, S, true, TWL>(A, wg, G, l); });
+    else if (A.inner > 1)
+      run_grid(G, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_cols_p2_body<N, E, S, false, TWL>(A, wg, G, l); });
+    else
+      run_grid(G, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_rows_p2_body<N, E, S, TWL>(A, wg, G, l); });
   } else {
     exit(11);
   }
@@ -299,7 +305,7 @@ int main(int argc, char** argv) {
     if (padded) {
       double* gh = new double[g.nmodes];
       double* W = new double[sched::padded_elems(g)];
-      for (long long i = 0; i < sched::padded_elems(g); ++i) W[i] = 1e300;  // pad slots must not leak
+      for (long long i = 0; i < sched::padded_elems(g); ++i) W[i] = std::nan("");  // pad slots must not leak
       run_dst(g, gd, gh, 1, true);
       auto t = sched::time_step_padded(g, sc, nullptr, variant, gh, W);
       std::vector<c64> tabs(2 * (size_t)g.Nt);
