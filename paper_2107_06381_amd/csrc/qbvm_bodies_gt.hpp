@@ -19,54 +19,70 @@ constexpr int gt_inv_mod(int x, int m) {
   return 0;
 }
 
-// Direct DFT of odd prime length B on registers v (destroyed), outputs to out[k * ostride].
+// cos and sin of 2 pi r / B as compile-time constants (Taylor series after reduction
+// to [0, pi/2]), so the DFT below takes its roots as scalar immediates.
+constexpr double gt_series(double x, bool sine) {
+  double term = sine ? x : 1.0, sum = term;
+  for (int n = sine ? 1 : 0; n < 40; n += 2) {
+    term *= -x * x / (double)((n + 1) * (n + 2));
+    sum += term;
+  }
+  return sum;
+}
+
 template <int B>
-__device__ __forceinline__ void gt_dft_odd_store(c64 (&v)[B], c64* out, int ostride) {
-  constexpr int H = (B - 1) / 2;
-  constexpr int base = B * (B - 1) / 2;
-  const c64 x0 = v[0];
-  c64 s0 = x0;
-#pragma unroll
-  for (int j = 1; j <= H; ++j) {
-    const c64 p = v[j], q = v[B - j];
-    v[j] = cadd(p, q);      // a_j
-    v[B - j] = csub(p, q);  // b_j
-    s0 = cadd(s0, v[j]);
-  }
-  out[0] = s0;
-#pragma unroll
-  for (int k = 1; k <= H; ++k) {
-    c64 Ak = x0, Bk = {0.0, 0.0};
-#pragma unroll
-    for (int j = 1; j <= H; ++j) {
-      const c64 w = c_root[base + (j * k) % B];
-      Ak.re += v[j].re * w.re;
-      Ak.im += v[j].im * w.re;
-      Bk.re -= v[B - j].re * w.im;
-      Bk.im -= v[B - j].im * w.im;
+struct GtRoots {
+  double c[B], s[B];
+  constexpr GtRoots() : c(), s() {
+    constexpr double pi = 3.141592653589793238462643383279502884;
+    for (int r = 0; r < B; ++r) {
+      const int q = r <= B / 2 ? r : B - r;  // angle 2 pi q / B in [0, pi]; sin flips for r > B/2
+      double th = 2.0 * pi * (double)q / (double)B;
+      double sg_c = 1.0;
+      if (th > pi / 2) {
+        th = pi - th;
+        sg_c = -1.0;
+      }
+      c[r] = sg_c * gt_series(th, false);
+      s[r] = (r <= B / 2 ? 1.0 : -1.0) * gt_series(th, true);
     }
-    out[k * ostride] = {Ak.re + Bk.im, Ak.im - Bk.re};
-    out[(B - k) * ostride] = {Ak.re - Bk.im, Ak.im + Bk.re};
   }
+};
+
+template <int B>
+constexpr int gt_pairs() { return (B - 1) / 2; }
+
+// Output slots of chunk ch (KC symmetric pairs per chunk; chunk 0 also holds k = 0).
+template <int B, int KC>
+constexpr int gt_chunk_first(int ch) { return 1 + ch * KC; }
+template <int B, int KC>
+constexpr int gt_chunk_last(int ch) {
+  return gt_chunk_first<B, KC>(ch) + KC - 1 < gt_pairs<B>() ? gt_chunk_first<B, KC>(ch) + KC - 1 : gt_pairs<B>();
+}
+template <int B, int KC>
+constexpr int gt_chunk_slots(int ch) {
+  return (ch == 0 ? 1 : 0) + 2 * (gt_chunk_last<B, KC>(ch) - gt_chunk_first<B, KC>(ch) + 1);
 }
 
-template <int A, int B, int S>
-constexpr size_t gt_lds_bytes(int Nt) {
-  return sizeof(c64) * ((size_t)A * B * S + 2 * (size_t)Nt);
-}
-
-template <int A, int B, int S>
+// PAIR: levels in padded rows (pitch > 0), each lane's two modes stored as one
+// aligned 16-byte pair (a second mode past the row end lands in the padding).
+template <int A, int B, int S, int KC, bool PAIR>
 __device__ __forceinline__ void time_gt_body(const TimeArgs& a, long long wg, c64* lds) {
   constexpr int N = A * B;
+  constexpr int H = gt_pairs<B>();
+  constexpr int NCH = (H + KC - 1) / KC;
   constexpr int c1 = gt_inv_mod(B % A, A);
   constexpr int c2 = gt_inv_mod(A % B, B);
   static_assert(A >= 2 && c1 > 0, "A and B must be coprime");
   static_assert(c2 > 0, "A and B must be coprime");
   constexpr int T = A * S;
-  c64* Y = lds;            // [k2][a][s]
-  c64* dt = lds + (size_t)N * S;
+  constexpr GtRoots<B> R{};
+  c64* dt = lds;
   c64* gi = dt + N;
-  const int t = threadIdx.x, s = t % S, ra = t / S;
+  c64* Y = gi + N;  // [slot][a][s] for one chunk of outputs
+  static_assert(S % 64 == 0, "one row index per wave");
+  const int t = threadIdx.x, s = t % S;
+  const int ra = __builtin_amdgcn_readfirstlane(t / S);  // uniform across the wave
 
   SolveScalars sc = a.sc;
   if (a.alpha_dev) sc = scalars_from_alpha(*a.alpha_dev, a.variant, a.tau);
@@ -86,7 +102,7 @@ __device__ __forceinline__ void time_gt_body(const TimeArgs& a, long long wg, c6
 
   long long ka, oa;
   bool oka, okb;
-  if (a.pitch > 0) {
+  if (PAIR) {
     const long long row = wg / a.tiles_per_row;
     const int cc = (int)(wg - row * a.tiles_per_row) * 2 * S + 2 * s;
     ka = row * a.m + cc;
@@ -116,27 +132,63 @@ __device__ __forceinline__ void time_gt_body(const TimeArgs& a, long long wg, c6
     const double ib = gb * recip_nr(xb * xb + z.im * z.im);
     v[b] = {ia * xa + ib * z.im, ib * xb - ia * z.im};
   }
-  // length-B DFT over b -> Y[k2][ra][s]
-  gt_dft_odd_store<B>(v, Y + (size_t)ra * S + s, A * S);
-  __syncthreads();
-  // length-A DFTs over a for k2 = ra, ra + A, ...; Step (c) scaling and store
-  for (int k2 = ra; k2 < B; k2 += A) {
-    c64 w[A];
+  // length-B DFT over b in symmetric form: a_j = x_j + x_{B-j}, b_j = x_j - x_{B-j}
+  const c64 x0 = v[0];
+  c64 s0 = x0;
 #pragma unroll
-    for (int q = 0; q < A; ++q) w[q] = Y[((size_t)k2 * A + q) * S + s];
-    Bfly<A>::run(w);
+  for (int j = 1; j <= H; ++j) {
+    const c64 p = v[j], q = v[B - j];
+    v[j] = cadd(p, q);
+    v[B - j] = csub(p, q);
+    s0 = cadd(s0, v[j]);
+  }
 #pragma unroll
-    for (int k1 = 0; k1 < A; ++k1) {
-      const int l = (B * c1 * k1 + A * c2 * k2) % N;
-      const c64 yv = cmul(gi[l], w[k1]);
-      double* yl = a.y + (long long)l * a.ystride;
-      if (a.pitch > 0) {  // aligned pair; a second mode past the row end lands in the padding
-        if (oka) *reinterpret_cast<c64*>(yl + oa) = yv;
-      } else {
-        if (oka) yl[oa] = yv.re;
-        if (okb) yl[oa + 1] = yv.im;
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int klo = gt_chunk_first<B, KC>(ch), khi = gt_chunk_last<B, KC>(ch);
+    const int base = ch == 0 ? 1 : 0;
+    if (ch == 0) Y[(size_t)ra * S + s] = s0;
+#pragma unroll
+    for (int k = klo; k <= khi; ++k) {
+      c64 Ak = x0, Bk = {0.0, 0.0};
+#pragma unroll
+      for (int j = 1; j <= H; ++j) {
+        const int r = (j * k) % B;
+        Ak.re += v[j].re * R.c[r];
+        Ak.im += v[j].im * R.c[r];
+        Bk.re += v[B - j].re * R.s[r];  // X_k = A_k - i B_k, B_k = sum_j b_j sin(2 pi jk/B)
+        Bk.im += v[B - j].im * R.s[r];
+      }
+      const int sl = base + 2 * (k - klo);
+      Y[((size_t)sl * A + ra) * S + s] = {Ak.re + Bk.im, Ak.im - Bk.re};        // X_k
+      Y[((size_t)(sl + 1) * A + ra) * S + s] = {Ak.re - Bk.im, Ak.im + Bk.re};  // X_{B-k}
+    }
+    __syncthreads();
+    // length-A DFTs over a for this chunk's k2; Step (c) scaling and store
+    const int nsl = gt_chunk_slots<B, KC>(ch);
+#pragma unroll
+    for (int q0 = 0; q0 < (2 * KC + 1 + A - 1) / A; ++q0) {
+      const int sl = ra + q0 * A;
+      if (sl < nsl) {
+        const int k2 = (ch == 0 && sl == 0) ? 0 : (((sl - base) & 1) ? B - (klo + (sl - base) / 2) : klo + (sl - base) / 2);
+        c64 w[A];
+#pragma unroll
+        for (int q = 0; q < A; ++q) w[q] = Y[((size_t)sl * A + q) * S + s];
+        Bfly<A>::run(w);
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+          const int l = (B * c1 * k1 + A * c2 * k2) % N;
+          const c64 yv = cmul(gi[l], w[k1]);
+          double* yl = a.y + (long long)l * a.ystride;
+          if constexpr (PAIR) {
+            if (oka) *reinterpret_cast<c64*>(yl + (unsigned)oa) = yv;  // offset within a level < 2^31
+          } else {
+            if (oka) yl[oa] = yv.re;
+            if (okb) yl[oa + 1] = yv.im;
+          }
+        }
       }
     }
+    __syncthreads();
   }
 }
 

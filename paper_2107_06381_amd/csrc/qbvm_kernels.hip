@@ -60,14 +60,18 @@ __global__ __launch_bounds__(p2sz::time_T(V)) void k_time_p2(TimeArgs a) {
   time_p2_body<N, p2sz::time_E(V), p2sz::time_S(N, V), RADER, p2sz::time_pad(V)>(a, blockIdx.x, lds);
 }
 
-template <int A, int B, int V>
-__global__ __launch_bounds__(p2sz::gt_T(A, V)) void k_time_gt(TimeArgs a) {
+// two waves per SIMD: the lane's B-point row stays in registers
+template <int A, int B, int V, bool PAIR>
+__global__ __launch_bounds__(p2sz::gt_T(A, V), 2) void k_time_gt(TimeArgs a) {
   extern __shared__ c64 lds[];
-  time_gt_body<A, B, p2sz::gt_S(V)>(a, blockIdx.x, lds);
+  time_gt_body<A, B, p2sz::gt_S(V), p2sz::gt_KC(V), PAIR>(a, blockIdx.x, lds);
 }
 
-static const void* time_gt_fn(int A, int B, int V) {
-  if (A == 3 && B == 43) return V == 0 ? (const void*)&k_time_gt<3, 43, 0> : (const void*)&k_time_gt<3, 43, 1>;
+static const void* time_gt_fn(int A, int B, int V, bool pair) {
+  if (A == 3 && B == 43) {
+    if (pair) return V == 0 ? (const void*)&k_time_gt<3, 43, 0, true> : (const void*)&k_time_gt<3, 43, 1, true>;
+    return V == 0 ? (const void*)&k_time_gt<3, 43, 0, false> : (const void*)&k_time_gt<3, 43, 1, false>;
+  }
   return nullptr;
 }
 
@@ -702,7 +706,7 @@ hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds
     f = time_p2_fn(a.fft.p2, a.var, a.fft.kind == kRader);
     if (!f) return hipErrorInvalidValue;
   } else if (a.fft.gtA) {
-    f = time_gt_fn(a.fft.gtA, a.fft.gtB, a.var);
+    f = time_gt_fn(a.fft.gtA, a.fft.gtB, a.var, a.pitch > 0);
     if (!f) return hipErrorInvalidValue;
   }
   return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);

@@ -65,17 +65,20 @@ inline bool dst_pairs_aligned(const DstArgs& a) {
          (reinterpret_cast<std::uintptr_t>(a.in) % 16) == 0 && (reinterpret_cast<std::uintptr_t>(a.out) % 16) == 0;
 }
 
-// Good-Thomas time kernels (N_t = A * B, gcd 1, B an odd prime); variant V: S = 32 (V=0) or 64
+// Good-Thomas time kernels (N_t = A * B, gcd 1, B an odd prime): S = 64 signals per
+// workgroup (A waves); the B-point outputs are exchanged in chunks of KC symmetric
+// pairs, variant 0: KC = 7, variant 1: KC = 11.
 constexpr int kGtPairs[][2] = {{3, 43}};
 constexpr bool gt_supported(int A, int B) {
   for (const auto& p : kGtPairs)
     if (p[0] == A && p[1] == B) return true;
   return false;
 }
-constexpr int gt_S(int V) { return V == 0 ? 32 : 64; }
+constexpr int gt_S(int) { return 64; }
+constexpr int gt_KC(int V) { return V == 0 ? 7 : 5; }
 constexpr int gt_T(int A, int V) { return A * gt_S(V); }
 constexpr size_t gt_lds(int A, int B, int V) {
-  return sizeof(c64) * ((size_t)A * B * gt_S(V) + 2 * (size_t)A * B);
+  return sizeof(c64) * ((size_t)(2 * gt_KC(V) + 1) * A * gt_S(V) + 2 * (size_t)A * B);
 }
 
 }  // namespace p2sz

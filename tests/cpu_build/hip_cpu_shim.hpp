@@ -31,3 +31,5 @@ inline void sincospi(double x, double* s, double* c) {
 inline double exp10(double x) { return std::pow(10.0, x); }
 // the hardware reciprocal estimate, exact here (the bodies refine it by Newton steps)
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))
+// every lane of the emulated wave holds the same value where the bodies use this
+#define __builtin_amdgcn_readfirstlane(x) (x)

@@ -212,8 +212,10 @@ static void time_p2_n(const Launch<TimeArgs>& t) {
 static void run_time_fast(const Launch<TimeArgs>& t) {
   const TimeArgs& A = t.args;
   if (A.fft.gtA == 3 && A.fft.gtB == 43) {
-    if (A.var == 0) run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, 32>(A, wg, l); });
-    else run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, 64>(A, wg, l); });
+    if (A.var == 0 && A.pitch > 0) run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, p2sz::gt_S(0), p2sz::gt_KC(0), true>(A, wg, l); });
+    else if (A.var == 0) run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, p2sz::gt_S(0), p2sz::gt_KC(0), false>(A, wg, l); });
+    else if (A.pitch > 0) run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, p2sz::gt_S(1), p2sz::gt_KC(1), true>(A, wg, l); });
+    else run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, p2sz::gt_S(1), p2sz::gt_KC(1), false>(A, wg, l); });
     return;
   }
   if (!A.fft.p2) exit(15);
