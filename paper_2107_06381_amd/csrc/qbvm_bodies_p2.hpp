@@ -9,8 +9,6 @@
 
 namespace qbvm {
 
-template <int N>
-constexpr bool p2_tw_in_lds() { return p2sz::tw_in_lds(N); }
 
 // value of the odd extension v_n = [0, x_1..x_m, 0, -x_m..-x_1] at n (0 <= n < 2(m+1)), or -1
 __device__ __forceinline__ int odd_ext_index(int n, int m, double& sign) {
@@ -27,13 +25,23 @@ __device__ __forceinline__ int odd_ext_index(int n, int m, double& sign) {
   return -1;
 }
 
-template <int N, bool TWL = p2sz::tw_in_lds(N)>
-__device__ __forceinline__ const c64* p2_twiddles(const FftPlanDev& f, c64* tw_lds, int t, int T) {
-  if constexpr (TWL) {
+// Twiddle accessor of the given table mode; modes 1 and 2 copy the table into LDS
+// at tw_lds (the caller synchronises before the first use).
+template <int N, int TWM = (p2sz::tw_in_lds(N) ? 1 : 0), int E = 8>
+__device__ __forceinline__ auto p2_twiddles(const FftPlanDev& f, c64* tw_lds, int t, int T, int u = 0) {
+  if constexpr (TWM == 3) {  // per-lane registers, loaded once
+    (void)tw_lds;
+    (void)t;
+    (void)T;
+    return p2_tw_regs<N, E>(f.tw, u);
+  } else if constexpr (TWM == 2) {
+    for (int i = t; i < 64 + N / 64; i += T) tw_lds[i] = i < 64 ? f.tw[i] : f.tw[(i - 64) * 64];
+    return TwSplit{tw_lds, tw_lds + 64};
+  } else if constexpr (TWM == 1) {
     for (int i = t; i < N; i += T) tw_lds[i] = f.tw[i];
-    return tw_lds;
+    return TwFull{tw_lds};
   } else {
-    return f.tw;
+    return TwFull{f.tw};
   }
 }
 
@@ -43,12 +51,12 @@ __device__ __forceinline__ const c64* p2_twiddles(const FftPlanDev& f, c64* tw_l
 // read at a clamped, valid address and zeroed before the transform.
 
 // Rows of [outer][m] (inner == 1): lanes walk along lines, two lines per signal.
-template <int N, int E, int S, bool TWL = p2sz::tw_in_lds(N)>
+template <int N, int E, int S, int TWM, int PM = 1>
 __device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long first, long long step, c64* lds) {
-  using L = P2Layout<N, E, S, false>;
+  using L = P2Layout<N, E, S, false, true, PM>;
   c64* buf = lds;
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
-  const c64* tw = p2_twiddles<N, TWL>(a.fft, buf + L::lds_elems(), t, L::T);
+  const auto tw = p2_twiddles<N, TWM, E>(a.fft, buf + L::lds_elems(), t, L::T, u);
   __syncthreads();
   const int m = a.len;
   const long long ntiles = (a.outer + 2LL * S - 1) / (2LL * S);
@@ -101,12 +109,12 @@ __device__ __forceinline__ bool dst_col_ok32(const DstArgs& a, long long c) {
 // VEC2: the two columns of a signal are one aligned 16-byte pair (padded layout:
 // inner, kstride and ostride even); a pair with only its first column valid is
 // stored whole, its second value landing in a padding column.
-template <int N, int E, int S, bool VEC2, bool TWL = p2sz::tw_in_lds(N)>
+template <int N, int E, int S, bool VEC2, int TWM>
 __device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long first, long long step, c64* lds) {
   using L = P2Layout<N, E, S, true>;
   c64* buf = lds;
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
-  const c64* tw = p2_twiddles<N, TWL>(a.fft, buf + L::lds_elems(), t, L::T);
+  const auto tw = p2_twiddles<N, TWM, E>(a.fft, buf + L::lds_elems(), t, L::T, u);
   __syncthreads();
   const int m = a.len;
   const long long tpo = a.tiles_per_outer;
@@ -171,8 +179,9 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
   using L = P2Layout<N, E, S, true, PAD>;
   const int Nt = a.Nt;
   c64* buf = lds;
+  constexpr int TWM = p2sz::time_tw_mode(N, E);
   c64* twl = buf + L::lds_elems();
-  c64* ks = twl + (p2_tw_in_lds<N>() ? N : 0);
+  c64* ks = twl + p2sz::tw_elems(N, TWM);
   c64* dt = ks + N;
   c64* gi = dt + Nt;
   int* gfw = reinterpret_cast<int*>(gi + Nt);
@@ -202,7 +211,7 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
       gbw[i] = a.fft.ginvt[i];
     }
   }
-  const c64* tw = p2_twiddles<N>(a.fft, twl, t, L::T);
+  const auto tw = p2_twiddles<N, TWM, E>(a.fft, twl, t, L::T, u);
   __syncthreads();
 
   // modes of this tile: flattened (pitch 0) or 2S consecutive x_1 of one padded row

@@ -57,19 +57,27 @@ constexpr int p2_log2(int x) { return x <= 1 ? 0 : 1 + p2_log2(x / 2); }
 // SigFast pads one slot per R0 positions (R0 = first radix): the stage-0 writes of
 // consecutive lane groups are R0 apart, and the pad makes their LDS bank groups
 // alternate.  PosFast pads one slot per 16 positions.
-template <int N, int E, int S, bool SIGFAST, bool SPAD = true>
+// PosFast position maps (PM): 0 = one pad slot per 16 positions; 1 = XOR of the
+// low four position bits with the next four (no pad, fewer bank conflicts in the
+// exchanges measured on gfx950); 2 = one pad slot per 8.
+template <int N, int E, int S, bool SIGFAST, bool SPAD = true, int PM = 1>
 struct P2Layout {
   static constexpr int P = N / E;
   static constexpr int T = S * P;
   static constexpr int R0 = P2Radices<N, E>::R[0];
   static constexpr int LR0 = SPAD ? p2_log2(R0) : 30;  // no pad: pos >> 30 == 0
-  static constexpr int NPAD = N + N / 16;
+  static constexpr int NPAD = PM == 1 ? N : (PM == 2 ? N + N / 8 : N + N / 16);
   static constexpr int NPADS = SPAD ? N + N / R0 : N;
   static constexpr size_t lds_elems() { return SIGFAST ? (size_t)NPADS * S : (size_t)NPAD * S; }
   static __device__ __forceinline__ int sig(int t) { return SIGFAST ? (t % S) : (t / P); }
   static __device__ __forceinline__ int lane(int t) { return SIGFAST ? (t / S) : (t % P); }
+  static __device__ __forceinline__ int pmap(int pos) {
+    if constexpr (PM == 1) return pos ^ ((pos >> 4) & 15);
+    else if constexpr (PM == 2) return pos + (pos >> 3);
+    else return pos + (pos >> 4);
+  }
   static __device__ __forceinline__ int at(int s, int pos) {
-    return SIGFAST ? (pos + (pos >> LR0)) * S + s : s * NPAD + pos + (pos >> 4);
+    return SIGFAST ? (pos + (pos >> LR0)) * S + s : s * NPAD + pmap(pos);
   }
 };
 
@@ -86,22 +94,86 @@ __device__ __forceinline__ int p2_out_pos(int u, int e) {
   return p2_in_pos<N, E, P2Radices<N, E>::K - 1>(u, e);
 }
 
-// Twiddle and butterflies of stage STAGE on the lane's E registers.
+// Twiddle sources, w(i) = exp(-2 pi i idx / N): a full table, or a two-level one
+// with w(i) = hi[i / 64] * lo[i % 64] (64 + N/64 entries, one extra product).
+struct TwFull {
+  const c64* t;
+  __device__ __forceinline__ c64 operator()(int i) const { return t[i]; }
+};
+struct TwSplit {
+  const c64* lo;
+  const c64* hi;
+  __device__ __forceinline__ c64 operator()(int i) const { return cmul(hi[i >> 6], lo[i & 63]); }
+};
+
+// Per-lane twiddles kept in registers for a whole persistent kernel: every stage
+// after the first multiplies input r of butterfly b by exp(-2 pi i k r/(NS R)) with
+// k = (u + b N/E) mod NS, which depends on the lane only.
+template <int N, int E>
+constexpr int p2_tw_off(int stage) {
+  int off = 0;
+  for (int st = 1; st < stage; ++st) off += (E / P2Radices<N, E>::R[st]) * (P2Radices<N, E>::R[st] - 1);
+  return off;
+}
+template <int N, int E>
+constexpr int p2_tw_count() { return p2_tw_off<N, E>(P2Radices<N, E>::K); }
+
+template <int N, int E>
+struct TwReg {
+  c64 w[p2_tw_count<N, E>() > 0 ? p2_tw_count<N, E>() : 1];
+};
+
 template <int N, int E, int STAGE>
-__device__ __forceinline__ void p2_compute(c64 (&v)[E], int u, const c64* __restrict__ tw) {
+__device__ __forceinline__ void p2_tw_fill_stage(TwReg<N, E>& T, const c64* __restrict__ tw, int u) {
+  if constexpr (STAGE < P2Radices<N, E>::K) {
+    constexpr int R = P2Radices<N, E>::R[STAGE];
+    constexpr int NS = p2_ns<N, E>(STAGE);
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+      const int k = (u + b * (N / E)) & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) T.w[p2_tw_off<N, E>(STAGE) + b * (R - 1) + r - 1] = tw[k * r * (N / (NS * R))];
+    }
+    p2_tw_fill_stage<N, E, STAGE + 1>(T, tw, u);
+  }
+}
+
+// Load the lane's register twiddles from the full table (global memory).
+template <int N, int E>
+__device__ __forceinline__ TwReg<N, E> p2_tw_regs(const c64* __restrict__ tw, int u) {
+  TwReg<N, E> T;
+  p2_tw_fill_stage<N, E, 1>(T, tw, u);
+  return T;
+}
+
+template <int N, int E, int STAGE>
+__device__ __forceinline__ void p2_twiddle_group(c64* v, int b, int u, const TwReg<N, E>& tw) {
+  constexpr int R = P2Radices<N, E>::R[STAGE];
+  (void)u;
+#pragma unroll
+  for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw.w[p2_tw_off<N, E>(STAGE) + b * (R - 1) + r - 1]);
+}
+
+template <int N, int E, int STAGE, class TW>
+__device__ __forceinline__ void p2_twiddle_group(c64* v, int b, int u, const TW& tw) {
+  constexpr int R = P2Radices<N, E>::R[STAGE];
+  constexpr int NS = p2_ns<N, E>(STAGE);
+  const int k = (u + b * (N / E)) & (NS - 1);
+  if (k != 0) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw(k * r * (N / (NS * R))));
+  }
+}
+
+// Twiddle and butterflies of stage STAGE on the lane's E registers.
+template <int N, int E, int STAGE, class TW>
+__device__ __forceinline__ void p2_compute(c64 (&v)[E], int u, const TW& tw) {
   constexpr int R = P2Radices<N, E>::R[STAGE];
   constexpr int NS = p2_ns<N, E>(STAGE);
   constexpr int B = E / R;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    if constexpr (NS > 1) {
-      const int j = u + b * (N / E);
-      const int k = j & (NS - 1);
-      if (k != 0) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], tw[k * r * (N / (NS * R))]);
-      }
-    }
+    if constexpr (NS > 1) p2_twiddle_group<N, E, STAGE>(&v[b * R], b, u, tw);
     Bfly<R>::run(&v[b * R]);
   }
 }
@@ -125,8 +197,8 @@ __device__ __forceinline__ void p2_exchange(c64 (&v)[E], int s, int u, c64* __re
   __syncthreads();
 }
 
-template <int N, int E, int STAGE, class L>
-__device__ __forceinline__ void p2_stages(c64 (&v)[E], int s, int u, c64* buf, const c64* tw) {
+template <int N, int E, int STAGE, class L, class TW>
+__device__ __forceinline__ void p2_stages(c64 (&v)[E], int s, int u, c64* buf, const TW& tw) {
   p2_compute<N, E, STAGE>(v, u, tw);
   if constexpr (STAGE + 1 < P2Radices<N, E>::K) {
     p2_exchange<N, E, STAGE, L>(v, s, u, buf);
@@ -135,8 +207,8 @@ __device__ __forceinline__ void p2_stages(c64 (&v)[E], int s, int u, c64* buf, c
 }
 
 // Whole forward DFT on registers loaded in stage-0 order (slot e = position p2_in_pos<N,E,0>).
-template <int N, int E, class L>
-__device__ __forceinline__ void p2_fft(c64 (&v)[E], int s, int u, c64* buf, const c64* tw) {
+template <int N, int E, class L, class TW>
+__device__ __forceinline__ void p2_fft(c64 (&v)[E], int s, int u, c64* buf, const TW& tw) {
   p2_stages<N, E, 0, L>(v, s, u, buf, tw);
 }
 

@@ -43,14 +43,14 @@ void upload_radix_roots(const c64* roots, int count) {
 template <int N, int V>
 __global__ __launch_bounds__(p2sz::dst_T(N, V)) void k_dst_rows_p2(DstArgs a) {
   extern __shared__ c64 lds[];
-  dst_rows_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), p2sz::dst_tw_in_lds(N, V)>(a, blockIdx.x, gridDim.x,
+  dst_rows_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), p2sz::dst_tw_mode(N, V)>(a, blockIdx.x, gridDim.x,
                                                                                       lds);
 }
 
 template <int N, int V, bool VEC2>
 __global__ __launch_bounds__(p2sz::dst_T(N, V)) void k_dst_cols_p2(DstArgs a) {
   extern __shared__ c64 lds[];
-  dst_cols_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), VEC2, p2sz::dst_tw_in_lds(N, V)>(a, blockIdx.x,
+  dst_cols_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), VEC2, p2sz::dst_tw_mode(N, V)>(a, blockIdx.x,
                                                                                             gridDim.x, lds);
 }
 

@@ -2,8 +2,9 @@
 // the kernels and the CPU build).  Variants differ in the complex values per
 // lane E and the signals per workgroup S:
 //   sine passes: 0 = E16, 256 lanes; 1 = E8, 256 lanes; 2 = E8, one signal (input
-//                transform); 3 = E16, 512 lanes; 4 = E8, 512 lanes; 5, 6 = as 3, 4 with the
-//                twiddles read from global memory (less LDS, two workgroups per CU)
+//                transform); 3 = E16, 512 lanes; 4 = E8, 512 lanes; 5, 6 = as 1, 4 with
+//                the lane's twiddles in registers (no LDS table, a third fewer LDS
+//                accesses per tile)
 //   time kernel: 0 = E16, 128 lanes; 1 = E8, 256 lanes; 2, 3 = as 0, 1 without the
 //                bank-conflict pad (less LDS, more workgroups per CU)
 #pragma once
@@ -20,8 +21,8 @@ constexpr int kDstVariants = 7;
 constexpr int kTimeVariants = 2;
 constexpr int kTimeMaxN = 2048;
 
-constexpr int dst_E(int V) { return (V == 0 || V == 3 || V == 5) ? 16 : 8; }
-constexpr int dst_T(int N, int V) { return V == 2 ? N / 8 : (V >= 3 ? 512 : 256); }
+constexpr int dst_E(int V) { return (V == 0 || V == 3) ? 16 : 8; }
+constexpr int dst_T(int N, int V) { return V == 2 ? N / 8 : ((V == 3 || V == 4 || V == 6) ? 512 : 256); }
 constexpr int dst_S(int N, int V) { return V == 2 ? 1 : dst_T(N, V) * dst_E(V) / N; }
 constexpr size_t dst_lds(int N, int V, bool cols);
 constexpr bool dst_valid(int N, int V) {
@@ -39,21 +40,28 @@ constexpr bool time_valid(int N, int V) {
 }
 
 constexpr bool tw_in_lds(int N) { return N <= 1024; }
-constexpr bool dst_tw_in_lds(int N, int V) { return tw_in_lds(N) && V < 5; }
+// twiddles: 0 = full table, global; 1 = full table, LDS; 2 = two-level table, LDS;
+// 3 = per-lane registers
+constexpr int dst_tw_mode(int N, int V) { return V >= 5 ? 3 : (tw_in_lds(N) ? 1 : 0); }
+constexpr int tw_elems(int N, int mode) { return mode == 1 ? N : (mode == 2 ? 64 + N / 64 : 0); }
 
 // first radix of the (N, E) sequence (mirrors P2Radices, checked there by static_assert)
 constexpr int first_radix(int N, int E) { return (E == 16 && N >= 128 && N != 512) ? 16 : 8; }
 
-// exchange buffer ([signal][position] padded for rows, [position][signal] for columns) + twiddles
+// exchange buffer ([signal][position] XOR-mapped for rows, [position][signal] padded for
+// columns) + twiddles
 constexpr size_t dst_lds(int N, int V, bool cols) {
-  return sizeof(c64) * ((cols ? (size_t)(N + N / first_radix(N, dst_E(V))) : (size_t)(N + N / 16)) * dst_S(N, V) +
-                        (dst_tw_in_lds(N, V) ? N : 0));
+  return sizeof(c64) * ((cols ? (size_t)(N + N / first_radix(N, dst_E(V))) : (size_t)N) * dst_S(N, V) +
+                        tw_elems(N, dst_tw_mode(N, V)));
 }
+
+// time kernels: E = 8 keeps the lane's twiddles in registers, E = 16 a table
+constexpr int time_tw_mode(int N, int E) { return E == 8 ? 3 : (tw_in_lds(N) ? 1 : 0); }
 
 // exchange buffer, twiddles, Rader kernel spectrum, d_j/tau and gamma_l^{-1}, two index maps
 constexpr size_t time_lds(int N, int V, int Nt) {
   return sizeof(c64) * ((size_t)(N + (time_pad(V) ? N / first_radix(N, time_E(V)) : 0)) * time_S(N, V) +
-                        (tw_in_lds(N) ? N : 0) + N +
+                        tw_elems(N, time_tw_mode(N, time_E(V))) + N +
                         2 * (size_t)Nt) +
          sizeof(int) * 2 * (size_t)N;
 }

@@ -145,7 +145,7 @@ static void dst_p2_nv(const Launch<DstArgs>& Lz) {
   if constexpr (p2sz::dst_valid(N, V)) {
     const DstArgs& A = Lz.args;
     constexpr int E = p2sz::dst_E(V), S = p2sz::dst_S(N, V);
-    constexpr bool TWL = p2sz::dst_tw_in_lds(N, V);
+    constexpr int TWL = p2sz::dst_tw_mode(N, V);
     // persistent bodies on a small grid, so every workgroup walks several tiles
     const long long G = Lz.nwg < 3 ? Lz.nwg : 3;
     if (A.inner > 1 && p2sz::dst_pairs_aligned(A))

@@ -50,15 +50,28 @@ def test_fft_engine(exe, tmp_path, n):
     assert np.linalg.norm(y - ref) <= 2e-15 * np.linalg.norm(ref) * max(1.0, np.log2(n)), info
 
 
+# The CPU build runs every lane as a thread, so the full kernel-variant matrix takes
+# tens of minutes; by default a subset runs in which every variant and every
+# pipeline (generic, power-of-two, padded, Rader, Good-Thomas) still appears.
+# QBVM_FULL_EMU=1 runs the full matrix.
+FULL = os.environ.get("QBVM_FULL_EMU") == "1"
+
 DST_CASES = [(1, 9, 3), (2, 13, 2), (2, 100, 1), (3, 6, 2),
              # power-of-two kernels: 2(m+1) = 64 .. 4096
              (2, 31, 3), (3, 63, 1), (2, 127, 2), (2, 255, 1), (2, 511, 1), (2, 1023, 1), (1, 2047, 5)]
+DST_VARIANTS = [(0, 1, 0), (1, 0, 1), (3, 4, 0), (4, 3, 1), (5, 6, 0), (6, 5, 0)]
+DST_QUICK = [((1, 9, 3), (0, 1, 0)), ((2, 13, 2), (1, 0, 1)), ((3, 6, 2), (3, 4, 0)), ((2, 31, 3), (5, 6, 0)),
+             ((2, 127, 2), (6, 5, 0)), ((2, 255, 1), (3, 4, 0)), ((2, 511, 1), (4, 3, 1)), ((2, 1023, 1), (1, 0, 1)),
+             ((1, 2047, 5), (0, 1, 0)), ((2, 100, 1), (1, 0, 0))]
+DST_PARAMS = [(c, v) for c in DST_CASES for v in DST_VARIANTS] if FULL else DST_QUICK
 
 
-@pytest.mark.parametrize("variants", [(0, 1, 0), (1, 0, 1), (3, 4, 0), (4, 3, 1), (5, 6, 0), (6, 5, 0)])
-@pytest.mark.parametrize("d,m,batch", DST_CASES)
-def test_dst_passes(exe, tmp_path, d, m, batch, variants):
-    """Every kernel variant of the sine passes (levels: E16 / E8; input transform: one signal)."""
+@pytest.mark.parametrize("case,variants", DST_PARAMS,
+                         ids=[f"{c[0]}d-m{c[1]}-b{c[2]}-v{v[0]}{v[1]}{v[2]}" for c, v in DST_PARAMS])
+def test_dst_passes(exe, tmp_path, case, variants):
+    """Kernel variants of the sine passes (levels: E16 / E8, table / register
+    twiddles; input transform: one signal) vs the oracle's orthonormal DST-I."""
+    d, m, batch = case
     rng = np.random.default_rng(m)
     x = rng.standard_normal((batch,) + (m,) * d)
     fi, fo = tmp_path / "i.bin", tmp_path / "o.bin"
@@ -69,7 +82,7 @@ def test_dst_passes(exe, tmp_path, d, m, batch, variants):
     assert np.linalg.norm(y - ref) <= 1e-14 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("d,m,n,alpha,variant", [
+SOLVE_CASES = [
     (1, 7, 6, 1e-2, 0), (1, 127, 128, 1e-3, 0), (1, 33, 40, 1e-6, 1), (1, 64, 63, 1e-6, 0),
     (2, 5, 4, 1e-3, 0), (2, 15, 16, 1e-4, 1), (2, 20, 11, 1e-2, 0), (2, 31, 100, 1e-8, 0),
     (3, 4, 5, 1e-3, 0), (3, 9, 8, 1e-5, 1), (2, 1, 1, 0.5, 0), (1, 1, 3, 0.1, 1),
@@ -78,13 +91,24 @@ def test_dst_passes(exe, tmp_path, d, m, batch, variants):
     (2, 255, 6, 1e-3, 0),
     # padded level pipeline (power-of-two sine and time kernels): 2D Rader-257, 2D 256, 3D 64
     (2, 63, 256, 1e-4, 0), (2, 63, 255, 1e-5, 1), (3, 31, 63, 1e-3, 0),
-    # Good-Thomas time kernel, N_t = 129 = 3 * 43 (padded: 2D m=63, 3D m=31; in place: 2D m=40)
-    (2, 63, 128, 1e-4, 0), (3, 31, 128, 1e-3, 1), (2, 40, 128, 1e-5, 0),
-])
-@pytest.mark.parametrize("kv", [(0, 4, 0, 1), (4, 1, 1, 1), (1, 3, 2, 0), (3, 0, 3, 0), (6, 5, 3, 1)])
-def test_solve_schedule_vs_oracle(exe, tmp_path, d, m, n, alpha, variant, kv):
+    # Good-Thomas time kernel, N_t = 129 = 3 * 43 (padded: 2D m=63, 3D m=31; in place: 2D m=40, 3D m=7)
+    (2, 63, 128, 1e-4, 0), (3, 31, 128, 1e-3, 1), (2, 40, 128, 1e-5, 0), (3, 7, 128, 1e-3, 0),
+]
+SOLVE_KV = [(0, 4, 0, 1), (4, 1, 1, 1), (1, 3, 2, 0), (3, 0, 3, 0), (6, 5, 3, 1), (5, 6, 1, 1)]
+# subset: the cheap cases, each with one variant set, every set used
+_QUICK_SKIP = {(3, 15, 127, 1e-3, 1), (3, 31, 63, 1e-3, 0), (3, 31, 128, 1e-3, 1), (2, 255, 6, 1e-3, 0),
+               (2, 63, 255, 1e-5, 1)}
+SOLVE_PARAMS = ([(c, kv) for c in SOLVE_CASES for kv in SOLVE_KV] if FULL else
+                [(c, SOLVE_KV[i % len(SOLVE_KV)]) for i, c in enumerate(c for c in SOLVE_CASES if c not in _QUICK_SKIP)])
+
+
+@pytest.mark.parametrize("case,kv", SOLVE_PARAMS,
+                         ids=[f"{c[0]}d-m{c[1]}-n{c[2]}-a{c[3]:g}-{'PM' if c[4] else 'PQ'}-kv{''.join(map(str, k))}"
+                              for c, k in SOLVE_PARAMS])
+def test_solve_schedule_vs_oracle(exe, tmp_path, case, kv):
     """Full solve (1D Thomas path, 2D/3D sine-transform path; padded and in-place
     level pipelines) vs the closed form, for several power-of-two kernel variants."""
+    d, m, n, alpha, variant = case
     L, T = 1.0, 0.9
     g = np.random.default_rng(d * 100 + m).standard_normal((m,) * d)
     fi, fo = tmp_path / "i.bin", tmp_path / "o.bin"
