@@ -156,7 +156,9 @@ void qbvm_batched_cache_clear(void);
 
 /* D(alpha) = ||y^N(alpha) - g_delta||_h, ||v||_h = h^{d/2} ||v||_2 (the discrete
  * L2 norm of Section 5), with y^N computed by Step (c) at the last level only.
- * g_delta: DEVICE.  *D_out: HOST.  Synchronous. */
+ * g_delta: DEVICE.  *D_out: HOST.  Returns once the result is on the host (the
+ * last kernel posts it to host memory the plan owns; g_delta has been read by
+ * then); later work on the plan's stream stays ordered after it. */
 int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_delta,
                      double* D_out);
 
@@ -166,7 +168,8 @@ int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_d
  * spectrum of g_delta and delta; the prediction is accepted if
  * win_lo <= D/delta <= win_hi, otherwise the device-side bisection on log10 alpha
  * runs and its result is returned.  g_delta: DEVICE; delta > 0 (weighted norm).
- * alpha_out, info: HOST (info may be NULL).  Synchronous.  Returns QBVM_ENOROOT
+ * alpha_out, info: HOST (info may be NULL).  Returns once the result is on the
+ * host, as qbvm_discrepancy.  Returns QBVM_ENOROOT
  * (with *alpha_out = the nearer bracket end and info->bracket_hit = 1) when the
  * root is outside the bracket. */
 int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double delta,

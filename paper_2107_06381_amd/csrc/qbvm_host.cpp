@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -258,7 +260,10 @@ struct qbvm_plan_s {
   bool has_model = false;
   int* bin_perm = nullptr;
   int* bin_off = nullptr;
-  double* pinned = nullptr;  // host, 64 doubles
+  // result mailbox: coherent mapped host memory the final row kernel writes into
+  double* mbox = nullptr;      // host view, 8 doubles
+  double* mbox_dev = nullptr;  // device view
+  double mbox_seq = 0.0;
   int wg_row = 1;
   // grow-only batch workspace
   double* bws = nullptr;
@@ -330,7 +335,7 @@ void destroy_plan(qbvm_plan_s* p) {
   (void)hipStreamSynchronize(p->stream);
   for (void* q : p->allocs) (void)hipFree(q);
   if (p->bws) (void)hipFree(p->bws);
-  if (p->pinned) (void)hipHostFree(p->pinned);
+  if (p->mbox) (void)hipHostFree(p->mbox);
   (void)hipSetDevice(cur);
   delete p;
 }
@@ -395,7 +400,7 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
   HIP_TRY(dalloc(p, &p->tabs, 2 * (size_t)p->Nt));
   // four lanes per mode in the row kernel (64 modes per 256-lane workgroup)
   p->wg_row = (int)std::max<long long>(1, std::min<long long>(4096, (p->nmodes + 63) / 64));
-  HIP_TRY(dalloc(p, &p->partial, p->wg_row));
+  HIP_TRY(dalloc(p, &p->partial, std::max<long long>(p->wg_row, 32)));  // row reduction; 32 feature bins
   HIP_TRY(dalloc(p, &p->counter, 1));
   HIP_TRY(hipMemset(p->counter, 0, sizeof(unsigned)));
   HIP_TRY(dalloc(p, &p->dscal, 16));
@@ -408,7 +413,9 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
   HIP_TRY(dalloc(p, &p->bin_off, off.size()));
   HIP_TRY(hipMemcpy(p->bin_perm, perm.data(), sizeof(int) * perm.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->bin_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
-  HIP_TRY(hipHostMalloc((void**)&p->pinned, 64 * sizeof(double), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&p->mbox, 8 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+  for (int i = 0; i < 8; ++i) p->mbox[i] = 0.0;
+  HIP_TRY(hipHostGetDevicePointer((void**)&p->mbox_dev, p->mbox, 0));
   guard.release();
   *out = p;
   return QBVM_OK;
@@ -512,7 +519,8 @@ int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, in
 // one level of Step (c) per mode; optional mode output and discrepancy reduction
 int enqueue_row(const qbvm_plan_s* p, int count, const double* ghat, int level, double alpha,
                 const double* alpha_dev, int variant, double* yrow, bool reduce, double* bstate, int mode,
-                double* dout, double* partial, unsigned* counter, int wg_per_inst) {
+                double* dout, double* partial, unsigned* counter, int wg_per_inst, double* host_out = nullptr,
+                const double* report_bs = nullptr, double host_seq = 0.0) {
   RowArgs r{};
   r.Nt = p->Nt;
   r.d = p->d;
@@ -534,10 +542,31 @@ int enqueue_row(const qbvm_plan_s* p, int count, const double* ghat, int level, 
   r.bstate = bstate;
   r.mode = mode;
   r.dout = dout;
+  r.host_out = host_out;
+  r.report_bs = report_bs;
+  r.host_seq = host_seq;
   const size_t lds = sizeof(c64) * 2 * p->Nt;
   ProfScope ps("dft_row", p->stream, 8.0 * count * p->nmodes * (yrow ? 2.0 : 1.0),
                14.0 * count * (double)p->nmodes * p->Nt, nullptr);
   HIP_TRY(launch_row(r, (long long)count * wg_per_inst, kThreads, lds, p->stream));
+  return QBVM_OK;
+}
+
+// Wait until the final row kernel has posted sequence number seq in the mailbox
+// (polling coherent host memory instead of a copy and a stream synchronisation);
+// after 0.2 s of polling fall back to synchronising the stream.
+int wait_mailbox(qbvm_plan_s* p, double seq) {
+  volatile double* box = p->mbox;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (unsigned spin = 0;; ++spin) {
+    if (box[0] == seq) break;
+    if ((spin & 1023u) == 1023u && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(200)) {
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      if (box[0] != seq) return set_error(QBVM_EHIP, "result mailbox not written");
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
   return QBVM_OK;
 }
 
@@ -606,12 +635,13 @@ int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_d
   if (rc) return rc;
   rc = run_dst(p, g_delta, p->ghat, 1, true);
   if (rc) return rc;
+  const double seq = (p->mbox_seq += 1.0);
   rc = enqueue_row(p, 1, p->ghat, p->n, alpha, nullptr, variant, nullptr, true, nullptr, 0, p->dscal + 3,
-                   p->partial, p->counter, p->wg_row);
+                   p->partial, p->counter, p->wg_row, p->mbox_dev, nullptr, seq);
   if (rc) return rc;
-  HIP_TRY(hipMemcpyAsync(p->pinned, p->dscal + 3, sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  *D_out = p->pinned[0];
+  rc = wait_mailbox(p, seq);
+  if (rc) return rc;
+  *D_out = p->mbox[2];
   return QBVM_OK;
 }
 
@@ -653,14 +683,15 @@ int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double 
   rc = run_dst(p, g_delta, p->ghat, 1, true);
   if (rc) return rc;
   if (o->use_learned) {
-    HIP_TRY(launch_feat_predict(p->nmodes, p->hd, p->ghat, delta, p->bin_perm, p->bin_off, p->model, p->feats,
-                                p->dscal + 1, p->stream));
+    HIP_TRY(launch_feat_predict(p->hd, p->ghat, delta, p->bin_perm, p->bin_off, p->model, p->feats, p->dscal + 1,
+                                p->partial, p->counter, p->stream));
+    const double seq = (p->mbox_seq += 1.0);
     rc = enqueue_row(p, 1, p->ghat, p->n, 0.0, p->dscal + 1, variant, nullptr, true, nullptr, 0, p->dscal + 3,
-                     p->partial, p->counter, p->wg_row);
+                     p->partial, p->counter, p->wg_row, p->mbox_dev, nullptr, seq);
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(p->pinned + 8, p->dscal, 4 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    const double a_hat = p->pinned[9], D = p->pinned[11];
+    rc = wait_mailbox(p, seq);
+    if (rc) return rc;
+    const double a_hat = p->mbox[1], D = p->mbox[2];
     inf.alpha_learned = a_hat;
     inf.iterations = 1;
     inf.discrepancy = D;
@@ -675,17 +706,16 @@ int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double 
   rc = enqueue_bisection(p, variant, 1, p->ghat, nullptr, delta, o, p->bstate, p->dscal + 4, nullptr, p->partial,
                          p->counter, p->wg_row);
   if (rc) return rc;
+  const double seq = (p->mbox_seq += 1.0);
   rc = enqueue_row(p, 1, p->ghat, p->n, 0.0, p->dscal + 4, variant, nullptr, true, nullptr, 0, p->dscal + 3,
-                   p->partial, p->counter, p->wg_row);
+                   p->partial, p->counter, p->wg_row, p->mbox_dev, p->bstate, seq);
   if (rc) return rc;
-  HIP_TRY(hipMemcpyAsync(p->pinned + 16, p->bstate, kBState * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->pinned + 24, p->dscal, 8 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  const double* bs = p->pinned + 16;
-  *alpha_out = p->pinned[24 + 4];
-  inf.discrepancy = p->pinned[24 + 3];
-  inf.iterations += (int)bs[5] + 1;
-  inf.bracket_hit = bs[6] != 0.0 ? 1 : 0;
+  rc = wait_mailbox(p, seq);
+  if (rc) return rc;
+  *alpha_out = p->mbox[1];
+  inf.discrepancy = p->mbox[2];
+  inf.iterations += (int)p->mbox[3] + 1;
+  inf.bracket_hit = p->mbox[4] != 0.0 ? 1 : 0;
   if (info) *info = inf;
   return inf.bracket_hit ? set_error(QBVM_ENOROOT, "discrepancy root outside the bracket") : QBVM_OK;
 }

@@ -29,9 +29,10 @@ hipError_t launch_alpha_tables(int Nt, double tau, int variant, double alpha, co
 hipError_t launch_row(const RowArgs& a, long long nwg, int threads, size_t lds, hipStream_t s);
 hipError_t launch_bisect_init(double* bstate, int count, const double* deltas, double delta_val,
                               double tau_dp, double lo, double hi, hipStream_t s);
-hipError_t launch_feat_predict(long long nm, double hd, const double* ghat, double delta, const int* perm,
-                               const int* off, const float* model, float* feats, double* alpha_out,
-                               hipStream_t s);
+// 32 workgroups; partial holds >= 32 doubles; counter[0] is zero on entry and exit
+hipError_t launch_feat_predict(double hd, const double* ghat, double delta, const int* perm, const int* off,
+                               const float* model, float* feats, double* alpha_out, double* partial,
+                               unsigned* counter, hipStream_t s);
 hipError_t launch_bisect_finish(const double* bstate, int count, double* alphas, int* hits,
                                 hipStream_t s);
 hipError_t launch_features(int count, long long nm, double hd, const double* ghat,

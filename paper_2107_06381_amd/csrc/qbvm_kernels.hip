@@ -169,6 +169,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Cross-workgroup hand-off of reduction partials.  Partials and counters are only
+// written and read with device-scope atomic stores/loads, which are coherent across
+// the XCDs' L2 caches, so publishing needs no L2 write-back or invalidation (a
+// device-scope fence would issue both, once per workgroup): wait for the partial's
+// store to complete, then count the workgroup in.  The last workgroup's loads
+// depend on the value the count returned.
+__device__ __forceinline__ unsigned publish_and_count(double* slot, double v, unsigned* counter) {
+  __hip_atomic_store(slot, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);
+  return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int kRowLanes = 4;
 
 __global__ __launch_bounds__(256) void k_row(RowArgs a) {
@@ -225,7 +237,7 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a) {
       for (int j = sub; j < Nt; j += kRowLanes) {
         const c64 z = dt[j];
         const double x = z.re + mu;
-        const double q = 1.0 / (x * x + z.im * z.im);
+        const double q = recip_nr(x * x + z.im * z.im);
         // w_j / (x + i z.im) = w_j (x - i z.im) q
         const c64 ww = w[j];
         sr += (ww.re * x + ww.im * z.im) * q;
@@ -254,15 +266,11 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a) {
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
-    __hip_atomic_store(&a.partial[blockIdx.x], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned prev = __hip_atomic_fetch_add(&a.counter[inst], 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned prev = publish_and_count(&a.partial[blockIdx.x], t, &a.counter[inst]);
     s_last = (prev == (unsigned)(a.wg_per_inst - 1));
   }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
   // the last workgroup of the instance sums the partials (fixed order per lane, then a fixed tree)
   double t = 0.0;
   for (int i = threadIdx.x; i < a.wg_per_inst; i += blockDim.x)
@@ -294,6 +302,16 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a) {
       }
       bs[3] = D;
       bs[4] = s_alpha;
+    }
+    if (a.host_out && inst == 0) {  // system-scope vector stores; the sequence number last
+      __hip_atomic_store(&a.host_out[1], s_alpha, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&a.host_out[2], D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      if (a.report_bs) {
+        __hip_atomic_store(&a.host_out[3], a.report_bs[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&a.host_out[4], a.report_bs[6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_store(&a.host_out[0], a.host_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }
@@ -510,38 +528,50 @@ __global__ __launch_bounds__(64) void k_predict(const float* model, const float*
   }
 }
 
-// One instance: the 33 features (bins reduced in a fixed order, one wave per bin
-// group) followed by the network on them; writes alpha_out[0] = alpha, [1] = log10 alpha.
-__global__ __launch_bounds__(512) void k_feat_predict(long long nm, double hd, const double* ghat, double delta,
-                                                      const int* perm, const int* off, const float* model,
-                                                      float* feats, double* alpha_out) {
-  __shared__ double part[8][32];
+// One instance on 32 workgroups, one per bin: each reduces its bin in a fixed order
+// and publishes the sum; the last workgroup to finish forms the 33 features and
+// runs the network.  Writes alpha_out[0] = alpha, [1] = log10 alpha.  counter[0]
+// must be zero on entry and is zero again on exit.
+__global__ __launch_bounds__(256) void k_feat_predict(double hd, const double* ghat, double delta, const int* perm,
+                                                      const int* off, const float* model, float* feats,
+                                                      double* alpha_out, double* partial, unsigned* counter) {
+  __shared__ double red[4];
   __shared__ float x[33];
   __shared__ float a1[64];
+  __shared__ bool s_last;
+  const int b = blockIdx.x;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nw = blockDim.x >> 6;
-  for (int b = wv; b < 32; b += nw) {
-    double t = 0.0;
-    for (int i = off[b] + lane; i < off[b + 1]; i += 64) {
-      const double v = ghat[perm[i]];
-      t += v * v;
-    }
-    t = wave_sum(t);
-    if (lane == 0) part[0][b] = t;
+  double t = 0.0;
+  for (int i = off[b] + (int)threadIdx.x; i < off[b + 1]; i += (int)blockDim.x) {
+    const double v = ghat[perm[i]];
+    t += v * v;
+  }
+  t = wave_sum(t);
+  if (lane == 0) red[wv] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) sum += red[i];
+    const unsigned prev = publish_and_count(&partial[b], sum, counter);
+    s_last = (prev == gridDim.x - 1);
   }
   __syncthreads();
+  if (!s_last) return;
   if (threadIdx.x < 33) {
     const int i = threadIdx.x;
-    const double f = i < 32 ? log10(part[0][i] * hd + 1e-300) : log10(delta);
+    const double f = i < 32 ? log10(__hip_atomic_load(&partial[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * hd +
+                                    1e-300)
+                            : log10(delta);
     feats[i] = (float)f;
     x[i] = ((float)f - model[kNP + i]) / model[kNP + 33 + i];
   }
+  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   if (threadIdx.x < 64) {
     const int o = threadIdx.x;
-    float t = model[kB1 + o];
-    for (int i = 0; i < 33; ++i) t += model[kW1 + o * 33 + i] * x[i];
-    a1[o] = gelu_f(t);
+    float u = model[kB1 + o];
+    for (int i = 0; i < 33; ++i) u += model[kW1 + o * 33 + i] * x[i];
+    a1[o] = gelu_f(u);
   }
   __syncthreads();
   if (threadIdx.x < 64) {
@@ -549,7 +579,7 @@ __global__ __launch_bounds__(512) void k_feat_predict(long long nm, double hd, c
     float u = model[kB2 + o];
     for (int i = 0; i < 64; ++i) u += model[kW2 + o * 64 + i] * a1[i];
     float c = model[kW3 + o] * gelu_f(u);
-    for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s, 64);
+    for (int sft = 32; sft >= 1; sft >>= 1) c += __shfl_xor(c, sft, 64);
     if (o == 0) {
       const float out = c + model[kB3];
       const double l10 = (double)(out * model[kNP + 67] + model[kNP + 66]);
@@ -559,11 +589,11 @@ __global__ __launch_bounds__(512) void k_feat_predict(long long nm, double hd, c
   }
 }
 
-hipError_t launch_feat_predict(long long nm, double hd, const double* ghat, double delta, const int* perm,
-                               const int* off, const float* model, float* feats, double* alpha_out,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_feat_predict, dim3(1), dim3(512), 0, s, nm, hd, ghat, delta, perm, off, model, feats,
-                     alpha_out);
+hipError_t launch_feat_predict(double hd, const double* ghat, double delta, const int* perm, const int* off,
+                               const float* model, float* feats, double* alpha_out, double* partial,
+                               unsigned* counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_feat_predict, dim3(32), dim3(256), 0, s, hd, ghat, delta, perm, off, model, feats,
+                     alpha_out, partial, counter);
   return hipGetLastError();
 }
 

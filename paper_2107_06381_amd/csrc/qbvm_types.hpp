@@ -154,6 +154,11 @@ struct RowArgs {
   double* bstate;         // if non-null: per instance {lo, hi, target, D, alpha, it, hit, pad}
   int mode;               // 0: fixed alpha (D to dout); 1: bisection step; 2: endpoint check
   double* dout;           // per-instance D (device)
+  // optional result mailbox in mapped host memory (instance 0 only): [1] alpha, [2] D,
+  // [3] iterations and [4] bracket flag of report_bs (if set), then [0] = host_seq
+  double* host_out;
+  const double* report_bs;
+  double host_seq;
 };
 
 // Bisection state layout (doubles per instance).
