@@ -854,9 +854,12 @@ int time_min_ms(hipStream_t s, F launch, double* out_ms) {
 
 }  // namespace
 
+// rows variants 0, 1, 3, 4, 5, 6; columns the same; time variants 0 .. kTimeVariants2 - 1
+constexpr int kAutotuneTimings = 12 + p2sz::kTimeVariants2;
+
 extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
   if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
-  double ms[16];
+  double ms[kAutotuneTimings];
   for (double& x : ms) x = -1.0;
   const size_t ny = (size_t)p->Nt * p->nmodes;
   double* scratch = nullptr;
@@ -928,7 +931,7 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
     if (gt && p->d >= 2) g_tuned[std::make_tuple(p->device, 3, p->Nt)] = p->var_time;
   }
   if (ms_out)
-    for (int i = 0; i < 16; ++i) ms_out[i] = ms[i];
+    for (int i = 0; i < kAutotuneTimings; ++i) ms_out[i] = ms[i];
   return QBVM_OK;
 }
 

@@ -114,6 +114,8 @@ static const void* time_fn_n(int V, bool rader) {
     case 1: return time_fn_nv<N, 1>(rader);
     case 2: return time_fn_nv<N, 2>(rader);
     case 3: return time_fn_nv<N, 3>(rader);
+    case 4: return time_fn_nv<N, 4>(rader);
+    case 5: return time_fn_nv<N, 5>(rader);
     default: return nullptr;
   }
 }

@@ -6,7 +6,9 @@
 //                the lane's twiddles in registers (no LDS table, a third fewer LDS
 //                accesses per tile)
 //   time kernel: 0 = E16, 128 lanes; 1 = E8, 256 lanes; 2, 3 = as 0, 1 without the
-//                bank-conflict pad (less LDS, more workgroups per CU)
+//                bank-conflict pad (less LDS, more workgroups per CU); 4 = E8, 512
+//                lanes; 5 = E16, 256 lanes (both unpadded: twice the signals per
+//                workgroup, which changes how evenly the tiles fill the CUs)
 #pragma once
 
 #include <cstddef>
@@ -30,13 +32,15 @@ constexpr bool dst_valid(int N, int V) {
          dst_T(N, V) <= 512 && dst_lds(N, V, false) <= 160 * 1024 && dst_lds(N, V, true) <= 160 * 1024;
 }
 
-constexpr int kTimeVariants2 = 4;
-constexpr int time_E(int V) { return (V % 2) == 0 ? 16 : 8; }
-constexpr int time_T(int V) { return (V % 2) == 0 ? 128 : 256; }
+constexpr int kTimeVariants2 = 6;
+constexpr int time_E(int V) { return (V == 0 || V == 2 || V == 5) ? 16 : 8; }
+constexpr int time_T(int V) { return V == 4 ? 512 : (V == 5 ? 256 : ((V % 2) == 0 ? 128 : 256)); }
 constexpr bool time_pad(int V) { return V < 2; }
 constexpr int time_S(int N, int V) { return time_T(V) * time_E(V) / N; }
+constexpr size_t time_lds(int N, int V, int Nt);
 constexpr bool time_valid(int N, int V) {
-  return V >= 0 && V < kTimeVariants2 && N >= 64 && N <= kTimeMaxN && (N & (N - 1)) == 0 && time_S(N, V) >= 1;
+  return V >= 0 && V < kTimeVariants2 && N >= 64 && N <= kTimeMaxN && (N & (N - 1)) == 0 && time_S(N, V) >= 1 &&
+         time_lds(N, V, N + 1) <= 160 * 1024;
 }
 
 constexpr bool tw_in_lds(int N) { return N <= 1024; }

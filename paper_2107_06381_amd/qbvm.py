@@ -171,10 +171,10 @@ class Plan:
 
     def autotune(self) -> dict:
         """Time the kernel variants on this plan's shape and keep the fastest."""
-        ms = (ctypes.c_double * 16)()
+        ms = (ctypes.c_double * 18)()
         _check(self.L_.qbvm_plan_autotune(self._h, ms))
         v = [round(x, 5) for x in ms]
-        return {"ms_rows_v013456": v[0:6], "ms_cols_v013456": v[6:12], "ms_time_v0123": v[12:16],
+        return {"ms_rows_v013456": v[0:6], "ms_cols_v013456": v[6:12], "ms_time_v012345": v[12:18],
                 "variants": self.variants()}
 
     def variants(self):

@@ -193,6 +193,8 @@ static void time_p2_n(const Launch<TimeArgs>& t) {
     case 1: time_p2_nv<N, 1>(t); break;
     case 2: time_p2_nv<N, 2>(t); break;
     case 3: time_p2_nv<N, 3>(t); break;
+    case 4: time_p2_nv<N, 4>(t); break;
+    case 5: time_p2_nv<N, 5>(t); break;
     default: exit(14);
   }
 }

@@ -94,7 +94,8 @@ SOLVE_CASES = [
     # Good-Thomas time kernel, N_t = 129 = 3 * 43 (padded: 2D m=63, 3D m=31; in place: 2D m=40, 3D m=7)
     (2, 63, 128, 1e-4, 0), (3, 31, 128, 1e-3, 1), (2, 40, 128, 1e-5, 0), (3, 7, 128, 1e-3, 0),
 ]
-SOLVE_KV = [(0, 4, 0, 1), (4, 1, 1, 1), (1, 3, 2, 0), (3, 0, 3, 0), (6, 5, 3, 1), (5, 6, 1, 1)]
+SOLVE_KV = [(0, 4, 0, 1), (4, 1, 1, 1), (1, 3, 2, 0), (3, 0, 3, 0), (6, 5, 3, 1), (5, 6, 1, 1), (5, 6, 4, 1),
+            (1, 4, 5, 0)]
 # subset: the cheap cases, each with one variant set, every set used
 _QUICK_SKIP = {(3, 15, 127, 1e-3, 1), (3, 31, 63, 1e-3, 0), (3, 31, 128, 1e-3, 1), (2, 255, 6, 1e-3, 0),
                (2, 63, 255, 1e-5, 1)}
