@@ -243,7 +243,8 @@ struct qbvm_plan_s {
   const FftTables* tfft = nullptr;  // length N_t
   const FftTables* sfft = nullptr;  // length 2(m+1)
   int S_time = 1, S_dst = 1;
-  int var_rows = 1, var_cols = 1, var_time = 1;
+  // kernel variants before any autotuning: the ones it keeps on the 2D and 3D workloads
+  int var_rows = 5, var_cols = 6, var_time = 4;
   double* mu1d = nullptr;
   double* ghat = nullptr;
   double* yrow = nullptr;
@@ -378,7 +379,7 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
     pick(1, p->sfft->dev.p2, p->var_cols);
     pick(2, p->tfft->dev.p2, p->var_time);
     if (p->tfft->dev.gtA) {
-      p->var_time = 0;
+      p->var_time = 1;
       pick(3, p->Nt, p->var_time);
     }
   }

@@ -98,10 +98,16 @@ def test_config_1d_full():
 
 
 def test_config_2d_full():
-    """2D, m=255, n=256 (N_t = 257, prime), alpha=1e-4: every level against the closed form."""
+    """2D, m=255, n=256 (N_t = 257, prime), alpha=1e-4, in the kernel variants the autotuner
+    keeps (the bench's launch configuration): every level against the closed form."""
     say("[case] config 2d")
     inst = W.config_2d()
-    y = gpu_solve(2, 255, 256, 1.0, 1.0, 1e-4, 0, inst.g_delta)
+    p = qbvm.Plan(2, 255, 256, 1.0, 1.0)
+    say("variants", p.autotune()["variants"])
+    y = p.solve(1e-4, 0, to_dev(inst.g_delta))
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    p.close()
     yc = O.closed_form(inst.g_delta, 2, 255, 256, 1.0, 1.0, 1e-4, O.PQ)
     assert rel(y, yc) < TOL and rel(y[0], yc[0]) < TOL and rel(y[-1], yc[-1]) < TOL
     # sampled levels against the all-at-once rows (residual of levels 1..n)
@@ -109,11 +115,13 @@ def test_config_2d_full():
 
 
 def test_config_3d_sampled_levels():
-    """3D, m=127, n=128, T=0.5, alpha=1e-5 (2.1 GB output): levels 0, 1, 64, n against the closed form."""
+    """3D, m=127, n=128, T=0.5, alpha=1e-5 (2.1 GB output), autotuned variants: levels 0, 1, 64, n
+    against the closed form."""
     say("[case] config 3d")
     inst = W.config_3d()
     m, n = 127, 128
     p = qbvm.Plan(3, m, n, 1.0, 0.5)
+    say("variants", p.autotune()["variants"])
     y = p.solve(1e-5, 0, to_dev(inst.g_delta))
     torch.cuda.synchronize()
     levels = [0, 1, 64, n]
