@@ -123,9 +123,9 @@ long long qbvm_plan_workspace_bytes(qbvm_plan_t p);
  * the full solution size, and keep the fastest in the plan.  Results are also
  * cached per (device, kernel role, transform length) and used as the defaults of
  * later plans.  Synchronous; allocates and frees (n+1) m^d doubles of scratch.
- * ms_out (HOST, may be NULL) receives 18 timings in milliseconds (-1 where not
- * applicable): rows variants 0, 1, 3, 4, 5, 6; columns variants 0, 1, 3, 4, 5, 6;
- * time variants 0..5. */
+ * ms_out (HOST, may be NULL) receives 20 timings in milliseconds (-1 where not
+ * applicable): rows variants 0, 1, 3, 4, 5, 6, 7; columns variants 0, 1, 3, 4, 5,
+ * 6, 7; time variants 0..5. */
 int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out);
 
 /* The kernel variants a plan uses (HOST outputs): sine rows, sine columns, time. */

@@ -855,8 +855,8 @@ int time_min_ms(hipStream_t s, F launch, double* out_ms) {
 
 }  // namespace
 
-// rows variants 0, 1, 3, 4, 5, 6; columns the same; time variants 0 .. kTimeVariants2 - 1
-constexpr int kAutotuneTimings = 12 + p2sz::kTimeVariants2;
+// rows variants 0, 1, 3 .. 7; columns the same; time variants 0 .. kTimeVariants2 - 1
+constexpr int kAutotuneTimings = 14 + p2sz::kTimeVariants2;
 
 extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
   if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
@@ -874,7 +874,7 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
     for (int role = 0; role < 2; ++role) {
       double best = 1e30;
       int bestv = -1;
-      for (int V : {0, 1, 3, 4, 5, 6}) {
+      for (int V : {0, 1, 3, 4, 5, 6, 7}) {
         if (!p2sz::dst_valid(Ns, V)) continue;
         sched::Geom G = geom(p);
         G.var_rows = G.var_cols = V;
@@ -887,7 +887,7 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
           return QBVM_OK;
         }, &t);
         if (rc) return rc;
-        ms[role * 6 + (V < 2 ? V : V - 1)] = t;
+        ms[role * 7 + (V < 2 ? V : V - 1)] = t;
         if (t < best) {
           best = t;
           bestv = V;
@@ -913,7 +913,7 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
         return QBVM_OK;
       }, &tm);
       if (rc) return rc;
-      ms[12 + V] = tm;
+      ms[14 + V] = tm;
       if (tm < best) {
         best = tm;
         bestv = V;

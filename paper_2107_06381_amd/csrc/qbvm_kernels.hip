@@ -95,6 +95,7 @@ static const void* dst_fn_n(int V, bool cols, bool vec2) {
     case 4: return dst_fn_nv<N, 4>(cols, vec2);
     case 5: return dst_fn_nv<N, 5>(cols, vec2);
     case 6: return dst_fn_nv<N, 6>(cols, vec2);
+    case 7: return dst_fn_nv<N, 7>(cols, vec2);
     default: return nullptr;
   }
 }

@@ -171,10 +171,10 @@ class Plan:
 
     def autotune(self) -> dict:
         """Time the kernel variants on this plan's shape and keep the fastest."""
-        ms = (ctypes.c_double * 18)()
+        ms = (ctypes.c_double * 20)()
         _check(self.L_.qbvm_plan_autotune(self._h, ms))
         v = [round(x, 5) for x in ms]
-        return {"ms_rows_v013456": v[0:6], "ms_cols_v013456": v[6:12], "ms_time_v012345": v[12:18],
+        return {"ms_rows_v0134567": v[0:7], "ms_cols_v0134567": v[7:14], "ms_time_v012345": v[14:20],
                 "variants": self.variants()}
 
     def variants(self):

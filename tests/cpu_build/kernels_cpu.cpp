@@ -169,6 +169,7 @@ static void dst_p2_n(const Launch<DstArgs>& Lz) {
     case 4: dst_p2_nv<N, 4>(Lz); break;
     case 5: dst_p2_nv<N, 5>(Lz); break;
     case 6: dst_p2_nv<N, 6>(Lz); break;
+    case 7: dst_p2_nv<N, 7>(Lz); break;
     default: exit(12);
   }
 }

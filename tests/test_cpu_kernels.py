@@ -59,10 +59,10 @@ FULL = os.environ.get("QBVM_FULL_EMU") == "1"
 DST_CASES = [(1, 9, 3), (2, 13, 2), (2, 100, 1), (3, 6, 2),
              # power-of-two kernels: 2(m+1) = 64 .. 4096
              (2, 31, 3), (3, 63, 1), (2, 127, 2), (2, 255, 1), (2, 511, 1), (2, 1023, 1), (1, 2047, 5)]
-DST_VARIANTS = [(0, 1, 0), (1, 0, 1), (3, 4, 0), (4, 3, 1), (5, 6, 0), (6, 5, 0)]
+DST_VARIANTS = [(0, 1, 0), (1, 0, 1), (3, 4, 0), (4, 3, 1), (5, 6, 0), (6, 5, 0), (7, 7, 1)]
 DST_QUICK = [((1, 9, 3), (0, 1, 0)), ((2, 13, 2), (1, 0, 1)), ((3, 6, 2), (3, 4, 0)), ((2, 31, 3), (5, 6, 0)),
              ((2, 127, 2), (6, 5, 0)), ((2, 255, 1), (3, 4, 0)), ((2, 511, 1), (4, 3, 1)), ((2, 1023, 1), (1, 0, 1)),
-             ((1, 2047, 5), (0, 1, 0)), ((2, 100, 1), (1, 0, 0))]
+             ((1, 2047, 5), (0, 1, 0)), ((2, 100, 1), (1, 0, 0)), ((3, 63, 1), (7, 7, 1))]
 DST_PARAMS = [(c, v) for c in DST_CASES for v in DST_VARIANTS] if FULL else DST_QUICK
 
 
