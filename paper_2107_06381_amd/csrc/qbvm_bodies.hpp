@@ -46,6 +46,18 @@ __device__ __forceinline__ double recip_nr(double x) {
   return fma(r, e, r);
 }
 
+// entries j = gid, gid + gstride, ... of a TabJob (Sections 3.1-3.3: omega from alpha,
+// then the shifts d_j and the inverse scaling gamma_l^{-1})
+__device__ __forceinline__ void tab_job_run(const TabJob& t, long long gid, long long gstride) {
+  if (!t.out || gid >= t.Nt) return;
+  const SolveScalars sc = scalars_from_alpha(t.alpha_dev ? *t.alpha_dev : t.alpha, t.variant, t.tau);
+  const double croot = exp(sc.logabsw / (double)t.Nt);
+  for (long long j = gid; j < t.Nt; j += gstride) {
+    t.out[j] = shift_over_tau((int)j, t.Nt, croot, 1.0 / t.tau);
+    t.out[t.Nt + j] = inv_gamma((int)j, t.Nt, sc.logabsw, sc.f0s / (double)t.Nt);
+  }
+}
+
 // eigenvalue of -Lap_h for flattened mode index k (x_1 fastest)
 __device__ __forceinline__ double mode_mu(long long k, int d, int m, const double* __restrict__ mu1d) {
   double mu = 0.0;

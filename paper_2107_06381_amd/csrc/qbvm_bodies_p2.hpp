@@ -56,6 +56,7 @@ __device__ __forceinline__ void dst_rows_p2_body(const DstArgs& a, long long fir
   using L = P2Layout<N, E, S, false, true, PM>;
   c64* buf = lds;
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
+  tab_job_run(a.tab, first * L::T + t, step * L::T);
   const auto tw = p2_twiddles<N, TWM, E>(a.fft, buf + L::lds_elems(), t, L::T, u);
   __syncthreads();
   const int m = a.len;
@@ -114,6 +115,7 @@ __device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long fir
   using L = P2Layout<N, E, S, true>;
   c64* buf = lds;
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
+  tab_job_run(a.tab, first * L::T + t, step * L::T);
   const auto tw = p2_twiddles<N, TWM, E>(a.fft, buf + L::lds_elems(), t, L::T, u);
   __syncthreads();
   const int m = a.len;

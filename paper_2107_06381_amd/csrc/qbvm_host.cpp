@@ -444,10 +444,17 @@ sched::Geom geom(const qbvm_plan_s* p) {
 
 // d passes of the orthonormal DST-I over a [batch][m]^d array
 // input_transform: the data are g_delta (one or a batch of instances), else solution levels
+// tab (optional): per-solve time tables computed as side work of the last pass
+// (power-of-two passes only; returns QBVM_EUNSUPPORTED before enqueueing otherwise)
 int run_dst(const qbvm_plan_s* p, const double* in, double* out, long long batch, bool input_transform,
-            NodeCtx* nc = nullptr, hipStream_t stream = nullptr) {
+            NodeCtx* nc = nullptr, hipStream_t stream = nullptr, const TabJob* tab = nullptr) {
   hipStream_t s = nc ? stream : p->stream;
-  for (const auto& L : sched::dst_passes(geom(p), in, out, batch, input_transform)) {
+  auto passes = sched::dst_passes(geom(p), in, out, batch, input_transform);
+  if (tab) {
+    if (!passes.back().args.fft.p2) return QBVM_EUNSUPPORTED;
+    passes.back().args.tab = *tab;
+  }
+  for (const auto& L : passes) {
     const double elems = (double)L.args.outer * L.args.inner * L.args.len;
     const int role = input_transform ? 0 : (L.args.inner == 1 ? 1 : 2);
     static const char* names[3] = {"dst_input", "dst_rows", "dst_cols"};
@@ -471,10 +478,11 @@ int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, in
   const sched::Geom G = geom(p);
   const SolveScalars sc = sched::host_scalars(alpha, variant, p->tau);
   if (W && p->d >= 2 && sched::use_padded(G)) {
-    int rc = run_dst(p, g, p->ghat, 1, true, nc, stream);
+    // the last input pass also fills the per-solve time tables (one launch fewer)
+    const TabJob job{p->tabs, p->Nt, variant, p->tau, alpha, alpha_dev};
+    int rc = run_dst(p, g, p->ghat, 1, true, nc, stream, &job);
     if (rc) return rc;
     auto t = sched::time_step_padded(G, sc, alpha_dev, variant, p->ghat, W);
-    HIP_TRY(launch_alpha_tables(p->Nt, p->tau, variant, alpha, alpha_dev, p->tabs, stream, nc));
     t.args.tabs = p->tabs;
     {
       const double nm = (double)p->nmodes;

@@ -602,12 +602,8 @@ hipError_t launch_feat_predict(double hd, const double* ghat, double delta, cons
 
 // Per-solve tables of the time transform: d_j/tau and f0s/N_t gamma_l^{-1}, j, l < N_t.
 __global__ void k_alpha_tables(int Nt, double tau, int variant, double alpha, const double* alpha_dev, c64* tabs) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= Nt) return;
-  const SolveScalars sc = scalars_from_alpha(alpha_dev ? *alpha_dev : alpha, variant, tau);
-  const double croot = exp(sc.logabsw / (double)Nt);
-  tabs[j] = shift_over_tau(j, Nt, croot, 1.0 / tau);
-  tabs[Nt + j] = inv_gamma(j, Nt, sc.logabsw, sc.f0s / (double)Nt);
+  const TabJob job{tabs, Nt, variant, tau, alpha, alpha_dev};
+  tab_job_run(job, (long long)blockIdx.x * blockDim.x + threadIdx.x, (long long)gridDim.x * blockDim.x);
 }
 
 hipError_t launch_alpha_tables(int Nt, double tau, int variant, double alpha, const double* alpha_dev, c64* tabs,

@@ -1,8 +1,8 @@
 // Launch geometry of the power-of-two kernels (plain C++, shared by the host,
 // the kernels and the CPU build).  Variants differ in the complex values per
 // lane E and the signals per workgroup S:
-//   sine passes: 0 = E16, 256 lanes; 1 = E8, 256 lanes; 2 = E8, one signal (input
-//                transform); 3 = E16, 512 lanes; 4 = E8, 512 lanes; 5, 6 = as 1, 4 with
+//   sine passes: 0 = E16, 256 lanes; 1 = E8, 256 lanes; 2 = E8, one signal, register
+//                twiddles (input transform); 3 = E16, 512 lanes; 4 = E8, 512 lanes; 5, 6 = as 1, 4 with
 //                the lane's twiddles in registers (no LDS table, a third fewer LDS
 //                accesses per tile); 7 = E8, one signal (one wave at N = 512) per
 //                workgroup with register twiddles: barriers stay inside one wave
@@ -47,7 +47,7 @@ constexpr bool time_valid(int N, int V) {
 constexpr bool tw_in_lds(int N) { return N <= 1024; }
 // twiddles: 0 = full table, global; 1 = full table, LDS; 2 = two-level table, LDS;
 // 3 = per-lane registers
-constexpr int dst_tw_mode(int N, int V) { return V >= 5 ? 3 : (tw_in_lds(N) ? 1 : 0); }
+constexpr int dst_tw_mode(int N, int V) { return (V >= 5 || V == 2) ? 3 : (tw_in_lds(N) ? 1 : 0); }
 constexpr int tw_elems(int N, int mode) { return mode == 1 ? N : (mode == 2 ? 64 + N / 64 : 0); }
 
 // first radix of the (N, E) sequence (mirrors P2Radices, checked there by static_assert)

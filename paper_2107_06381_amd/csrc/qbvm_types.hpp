@@ -78,6 +78,17 @@ struct TimeArgs {
   FftPlanDev fft;
 };
 
+// Per-solve time tables d_j/tau and f0s/N_t gamma_l^{-1} (j, l < N_t), computed as side
+// work by the workgroups of a kernel that runs before the time transform.
+struct TabJob {
+  c64* out;                 // [N_t] d_j/tau then [N_t] f0s/N_t gamma_l^{-1}; nullptr: no job
+  int Nt;
+  int variant;
+  double tau;
+  double alpha;
+  const double* alpha_dev;  // if non-null, alpha is read from here
+};
+
 // Sine-transform pass: data viewed as [outer][len][inner]; transform along len.
 // Rows pass (inner == 1): line l is in[l*in_pitch + k], k < len, written to out[l*out_pitch + k].
 // Columns pass (inner > 1): point k of column c in block o is at o*ostride + k*kstride + c
@@ -97,6 +108,7 @@ struct DstArgs {
   long long in_pitch, out_pitch;
   long long kstride, ostride;
   int colmod, colvalid;
+  TabJob tab;  // optional side work (power-of-two kernels)
   FftPlanDev fft;
 };
 

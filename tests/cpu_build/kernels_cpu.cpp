@@ -225,8 +225,14 @@ static void run_time_fast(const Launch<TimeArgs>& t) {
   P2_SWITCH(A.fft.p2, time_p2_n, t)
 }
 
-static void run_dst(const sched::Geom& g, const double* in, double* out, long long batch, bool input) {
-  for (const auto& Lz : sched::dst_passes(g, in, out, batch, input)) {
+static void run_dst(const sched::Geom& g, const double* in, double* out, long long batch, bool input,
+                    const TabJob* tab = nullptr) {
+  auto passes = sched::dst_passes(g, in, out, batch, input);
+  if (tab) {
+    if (!passes.back().args.fft.p2) exit(15);
+    passes.back().args.tab = *tab;
+  }
+  for (const auto& Lz : passes) {
     const DstArgs& A = Lz.args;
     const int T = A.threads;
     if (A.fft.p2) {
@@ -311,16 +317,11 @@ int main(int argc, char** argv) {
       double* gh = new double[g.nmodes];
       double* W = new double[sched::padded_elems(g)];
       for (long long i = 0; i < sched::padded_elems(g); ++i) W[i] = std::nan("");  // pad slots must not leak
-      run_dst(g, gd, gh, 1, true);
+      // the last input pass fills the time tables as side work, as on the device
+      std::vector<c64> tabs(2 * (size_t)g.Nt, c64{std::nan(""), std::nan("")});
+      const TabJob job{tabs.data(), g.Nt, variant, g.tau, alpha, nullptr};
+      run_dst(g, gd, gh, 1, true, &job);
       auto t = sched::time_step_padded(g, sc, nullptr, variant, gh, W);
-      std::vector<c64> tabs(2 * (size_t)g.Nt);
-      {
-        const double croot = std::exp(sc.logabsw / (double)g.Nt);
-        for (int j = 0; j < g.Nt; ++j) {
-          tabs[j] = shift_over_tau(j, g.Nt, croot, 1.0 / g.tau);
-          tabs[g.Nt + j] = inv_gamma(j, g.Nt, sc.logabsw, sc.f0s / (double)g.Nt);
-        }
-      }
       t.args.tabs = tabs.data();
       run_time_fast(t);
       for (const auto& Lz : sched::padded_passes(g, W, y)) {
