@@ -47,7 +47,10 @@ constexpr bool time_valid(int N, int V) {
 constexpr bool tw_in_lds(int N) { return N <= 1024; }
 // twiddles: 0 = full table, global; 1 = full table, LDS; 2 = two-level table, LDS;
 // 3 = per-lane registers
-constexpr int dst_tw_mode(int N, int V) { return (V >= 5 || V == 2) ? 3 : (tw_in_lds(N) ? 1 : 0); }
+// (E = 16 keeps at most 15 twiddles per lane for N <= 256, more above)
+constexpr int dst_tw_mode(int N, int V) {
+  return (V >= 5 || V == 2 || (dst_E(V) == 16 && N <= 256)) ? 3 : (tw_in_lds(N) ? 1 : 0);
+}
 constexpr int tw_elems(int N, int mode) { return mode == 1 ? N : (mode == 2 ? 64 + N / 64 : 0); }
 
 // first radix of the (N, E) sequence (mirrors P2Radices, checked there by static_assert)
@@ -60,8 +63,8 @@ constexpr size_t dst_lds(int N, int V, bool cols) {
                         tw_elems(N, dst_tw_mode(N, V)));
 }
 
-// time kernels: E = 8 keeps the lane's twiddles in registers, E = 16 a table
-constexpr int time_tw_mode(int N, int E) { return E == 8 ? 3 : (tw_in_lds(N) ? 1 : 0); }
+// time kernels: the lane's twiddles in registers for E = 8, and for E = 16 up to N = 256
+constexpr int time_tw_mode(int N, int E) { return (E == 8 || N <= 256) ? 3 : (tw_in_lds(N) ? 1 : 0); }
 
 // exchange buffer, twiddles, Rader kernel spectrum, d_j/tau and gamma_l^{-1}, two index maps
 constexpr size_t time_lds(int N, int V, int Nt) {
