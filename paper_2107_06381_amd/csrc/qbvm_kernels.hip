@@ -38,20 +38,30 @@ void upload_radix_roots(const c64* roots, int count) {
 
 // Power-of-two kernels, one symbol per (N, variant); the input transform always
 // uses variant 2, the passes over the solution levels variants 0 or 1.
+// Workgroups are dispatched to the 8 XCDs round-robin (block b on XCD b mod 8), each
+// XCD with its own L2.  The persistent kernels renumber the blocks so that every XCD
+// holds a contiguous range of logical workgroups: tiles in flight on one XCD are then
+// neighbours, and a cache line shared by two tiles is fetched into one L2 only.
+__device__ __forceinline__ long long xcd_contiguous(unsigned b, unsigned G) {
+  constexpr unsigned X = 8;
+  const unsigned per = G / X, rem = G % X, x = b % X, i = b / X;
+  return x < rem ? (long long)x * (per + 1) + i : (long long)rem * (per + 1) + (long long)(x - rem) * per + i;
+}
+
 // The sine-pass kernels are persistent: the grid is sized to the resident capacity
 // and every workgroup strides over the tiles.
 template <int N, int V>
 __global__ __launch_bounds__(p2sz::dst_T(N, V)) void k_dst_rows_p2(DstArgs a) {
   extern __shared__ c64 lds[];
-  dst_rows_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), p2sz::dst_tw_mode(N, V)>(a, blockIdx.x, gridDim.x,
-                                                                                      lds);
+  dst_rows_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), p2sz::dst_tw_mode(N, V)>(
+      a, xcd_contiguous(blockIdx.x, gridDim.x), gridDim.x, lds);
 }
 
 template <int N, int V, bool VEC2>
 __global__ __launch_bounds__(p2sz::dst_T(N, V)) void k_dst_cols_p2(DstArgs a) {
   extern __shared__ c64 lds[];
-  dst_cols_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), VEC2, p2sz::dst_tw_mode(N, V)>(a, blockIdx.x,
-                                                                                            gridDim.x, lds);
+  dst_cols_p2_body<N, p2sz::dst_E(V), p2sz::dst_S(N, V), VEC2, p2sz::dst_tw_mode(N, V)>(
+      a, xcd_contiguous(blockIdx.x, gridDim.x), gridDim.x, lds);
 }
 
 template <int N, int V, bool RADER>
