@@ -34,9 +34,9 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str, workload: str, per_launch_units: float):
-    """HBM bytes per launch from the committed counter summary, if it was taken on
-    the current kernel sources; else None."""
+def read_traffic(kernel: str, workload: str, variant: int):
+    """HBM bytes per launch of this kernel variant from the committed counter summary,
+    if it was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -44,7 +44,8 @@ def read_traffic(kernel: str, workload: str, per_launch_units: float):
         rec = json.load(f)
     if rec.get("source_hash") != source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    entry = rec.get("per_variant", {}).get(str(variant))
+    return entry.get("hbm_bytes_per_launch") if entry else None
 
 
 def cpu_baseline(inst, alpha, budget_s: float):
@@ -320,7 +321,8 @@ def main():
     bytes_per_launch = r["bytes"] / r["launches"]
     achieved = bytes_per_launch / avg_s / 1e9
     workload = "2d_m255_n256"
-    traffic = read_traffic(dom, workload, bytes_per_launch)
+    role_variant = {"dst_rows": "rows", "dst_cols": "cols", "time_spectral": "time"}.get(dom)
+    traffic = read_traffic(dom, workload, tune["variants"][role_variant]) if role_variant else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}

@@ -122,7 +122,8 @@ long long qbvm_plan_workspace_bytes(qbvm_plan_t p);
  * sine passes over the levels and of the time transform on a scratch array of
  * the full solution size, and keep the fastest in the plan.  Results are also
  * cached per (device, kernel role, transform length) and used as the defaults of
- * later plans.  Synchronous; allocates and frees (n+1) m^d doubles of scratch.
+ * later plans.  The plan's current variant is kept unless another is more than 3%
+ * faster.  Synchronous; allocates and frees (n+1) m^d doubles of scratch.
  * ms_out (HOST, may be NULL) receives 20 timings in milliseconds (-1 where not
  * applicable): rows variants 0, 1, 3, 4, 5, 6, 7; columns variants 0, 1, 3, 4, 5,
  * 6, 7; time variants 0..5. */

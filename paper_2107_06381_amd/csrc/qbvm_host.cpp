@@ -243,8 +243,7 @@ struct qbvm_plan_s {
   const FftTables* tfft = nullptr;  // length N_t
   const FftTables* sfft = nullptr;  // length 2(m+1)
   int S_time = 1, S_dst = 1;
-  // kernel variants before any autotuning: the ones it keeps on the 2D and 3D workloads
-  int var_rows = 5, var_cols = 6, var_time = 4;
+  int var_rows = 5, var_cols = 6, var_time = 4;  // set per transform length in create_plan
   double* mu1d = nullptr;
   double* ghat = nullptr;
   double* yrow = nullptr;
@@ -375,6 +374,11 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
       auto it = g_tuned.find(std::make_tuple(p->device, role, N));
       if (it != g_tuned.end()) var = it->second;
     };
+    // untuned defaults: the variants the autotuner keeps for these lengths on MI355X
+    const int Ns = p->sfft->dev.p2, Nt2 = p->tfft->dev.p2;
+    p->var_rows = Ns >= 512 ? 7 : 5;
+    p->var_cols = Ns >= 512 ? 6 : 1;
+    p->var_time = (Nt2 && Nt2 <= 256) ? 5 : 4;
     pick(0, p->sfft->dev.p2, p->var_rows);
     pick(1, p->sfft->dev.p2, p->var_cols);
     pick(2, p->tfft->dev.p2, p->var_time);
@@ -865,6 +869,7 @@ int time_min_ms(hipStream_t s, F launch, double* out_ms) {
 
 // rows variants 0, 1, 3 .. 7; columns the same; time variants 0 .. kTimeVariants2 - 1
 constexpr int kAutotuneTimings = 14 + p2sz::kTimeVariants2;
+constexpr double kKeepMargin = 1.03;
 
 extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
   if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
@@ -901,7 +906,11 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
           bestv = V;
         }
       }
-      if (bestv >= 0) (role == 0 ? p->var_rows : p->var_cols) = bestv;
+      // keep the current variant unless another is clearly faster (timings of close
+      // variants jitter by a few percent from run to run)
+      int& cur = role == 0 ? p->var_rows : p->var_cols;
+      const double tc = p2sz::dst_valid(Ns, cur) ? ms[role * 7 + (cur < 2 ? cur : cur - 1)] : -1.0;
+      if (bestv >= 0 && !(tc > 0 && tc <= kKeepMargin * best)) cur = bestv;
     }
   }
   const bool gt = p->tfft->dev.gtA != 0;
@@ -927,7 +936,8 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
         bestv = V;
       }
     }
-    if (bestv >= 0) p->var_time = bestv;
+    const double tcur = (p->var_time >= 0 && p->var_time < p2sz::kTimeVariants2) ? ms[14 + p->var_time] : -1.0;
+    if (bestv >= 0 && !(tcur > 0 && tcur <= kKeepMargin * best)) p->var_time = bestv;
   }
   HIP_TRY(hipStreamSynchronize(p->stream));
   {
