@@ -58,8 +58,9 @@ extern "C" {
 #define QBVM_OUT_YN  2 /* the final level y^N only: m^d doubles              */
 
 /* Size limits of this build. */
-#define QBVM_MAX_NT      4096  /* n + 1 */
-#define QBVM_MAX_M_1D    4095
+#define QBVM_MAX_NT      4096  /* n + 1, d = 1 */
+#define QBVM_MAX_NT_MD   2048  /* n + 1, d = 2, 3 (one time signal and its tables fit in LDS) */
+#define QBVM_MAX_M_1D    2047  /* the sine transform of g (length 2(m+1)) serves 1D too */
 #define QBVM_MAX_M_2D    2047
 #define QBVM_MAX_M_3D    511
 

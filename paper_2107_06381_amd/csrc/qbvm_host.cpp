@@ -293,7 +293,8 @@ int validate_grid(const qbvm_grid* g) {
   if (!(g->L > 0) || !(g->T > 0) || !std::isfinite(g->L) || !std::isfinite(g->T))
     return set_error(QBVM_EINVAL, "L and T must be positive and finite");
   const int mmax = g->d == 1 ? QBVM_MAX_M_1D : (g->d == 2 ? QBVM_MAX_M_2D : QBVM_MAX_M_3D);
-  if (g->m > mmax || g->n + 1 > QBVM_MAX_NT) return set_error(QBVM_EUNSUPPORTED, "grid exceeds the size limits");
+  const int ntmax = g->d == 1 ? QBVM_MAX_NT : QBVM_MAX_NT_MD;
+  if (g->m > mmax || g->n + 1 > ntmax) return set_error(QBVM_EUNSUPPORTED, "grid exceeds the size limits");
   return QBVM_OK;
 }
 

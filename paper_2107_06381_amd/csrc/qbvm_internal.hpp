@@ -24,8 +24,6 @@ hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds
 hipError_t launch_thomas(const ThomasArgs& a, hipStream_t s, NodeCtx* nc = nullptr);
 hipError_t launch_time1d(const Time1dArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,
                          NodeCtx* nc = nullptr);
-hipError_t launch_alpha_tables(int Nt, double tau, int variant, double alpha, const double* alpha_dev, c64* tabs,
-                               hipStream_t s, NodeCtx* nc = nullptr);
 hipError_t launch_row(const RowArgs& a, long long nwg, int threads, size_t lds, hipStream_t s);
 hipError_t launch_bisect_init(double* bstate, int count, const double* deltas, double delta_val,
                               double tau_dp, double lo, double hi, hipStream_t s);

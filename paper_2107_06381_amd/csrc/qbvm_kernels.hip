@@ -610,41 +610,6 @@ hipError_t launch_feat_predict(double hd, const double* ghat, double delta, cons
   return hipGetLastError();
 }
 
-// Per-solve tables of the time transform: d_j/tau and f0s/N_t gamma_l^{-1}, j, l < N_t.
-__global__ void k_alpha_tables(int Nt, double tau, int variant, double alpha, const double* alpha_dev, c64* tabs) {
-  const TabJob job{tabs, Nt, variant, tau, alpha, alpha_dev};
-  tab_job_run(job, (long long)blockIdx.x * blockDim.x + threadIdx.x, (long long)gridDim.x * blockDim.x);
-}
-
-hipError_t launch_alpha_tables(int Nt, double tau, int variant, double alpha, const double* alpha_dev, c64* tabs,
-                               hipStream_t s, NodeCtx* nc) {
-  struct Args {
-    int Nt;
-    double tau;
-    int variant;
-    double alpha;
-    const double* alpha_dev;
-    c64* tabs;
-  };
-  void* args[] = {&Nt, &tau, &variant, &alpha, &alpha_dev, &tabs};
-  const dim3 grid((Nt + 255) / 256), block(256);
-  if (!nc) return hipLaunchKernel((const void*)&k_alpha_tables, grid, block, args, 0, s);
-  hipKernelNodeParams p{};
-  p.func = (void*)&k_alpha_tables;
-  p.gridDim = grid;
-  p.blockDim = block;
-  p.sharedMemBytes = 0;
-  p.kernelParams = args;
-  hipGraphNode_t node;
-  const hipError_t e = hipGraphAddKernelNode(&node, nc->graph, nc->has_dep ? &nc->dep : nullptr,
-                                             nc->has_dep ? 1 : 0, &p);
-  if (e == hipSuccess) {
-    nc->dep = node;
-    nc->has_dep = true;
-  }
-  return e;
-}
-
 __global__ void k_copy_scale(const double* in, double* out, long long n, double s) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = in[i] * s;

@@ -146,5 +146,11 @@ def test_invalid_grids_rejected_without_gpu():
         rc = L.qbvm_plan(ctypes.byref(h), ctypes.byref(g), None)
         assert rc == -1, (g.d, g.m, g.n, rc)
         assert not h.value
+    # one past each size limit of include/qbvm.h
+    for g in [qbvm.Grid(1, 2048, 8, 1.0, 1.0), qbvm.Grid(2, 2048, 8, 1.0, 1.0), qbvm.Grid(3, 512, 8, 1.0, 1.0),
+              qbvm.Grid(2, 8, 2048, 1.0, 1.0), qbvm.Grid(1, 8, 4096, 1.0, 1.0)]:
+        rc = L.qbvm_plan(ctypes.byref(h), ctypes.byref(g), None)
+        assert rc == -5, (g.d, g.m, g.n, rc)
+        assert not h.value
     assert L.qbvm_plan(None, None, None) == -1
     assert L.qbvm_strerror(-4).decode().startswith("discrepancy")

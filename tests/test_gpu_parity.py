@@ -134,6 +134,31 @@ def test_config_3d_sampled_levels():
         assert rel(yl[i], yc[i]) < TOL, t
 
 
+@pytest.mark.parametrize("d,m,n,levels", [
+    (1, 2047, 4095, [0, 1, 2048, 4095]),   # 1D: largest m and N_t = 4096
+    (2, 2047, 1, None),                    # 2D: sine length 4096
+    (2, 63, 2047, [0, 1, 1024, 2047]),     # 2D: N_t = 2048
+    (3, 511, 1, None),                     # 3D: 2.1 GB per level array pair
+])
+def test_maximum_sizes(d, m, n, levels):
+    """The largest grids the ABI accepts, against the closed form on the listed levels."""
+    say(f"[case] max size d={d} m={m} n={n}")
+    g = np.random.default_rng(d * 31 + m).standard_normal((m,) * d)
+    p = qbvm.Plan(d, m, n)
+    y = p.solve(1e-4, 0, to_dev(g))
+    torch.cuda.synchronize()
+    lv = list(range(n + 1)) if levels is None else levels
+    yl = y[lv].cpu().numpy()
+    assert bool(torch.isfinite(y).all())
+    del y
+    p.close()
+    torch.cuda.empty_cache()
+    yc = O.closed_form(g, d, m, n, 1.0, 1.0, 1e-4, O.PQ, levels=lv)
+    for i, t in enumerate(lv):
+        ok, r = level_ok(yl[i], yc[i], yc[0], t, n + 1, omega_abs(1e-4, 0, 1.0 / n))
+        assert rel(yl[i], yc[i]) < TOL or ok, (t, r)
+
+
 @pytest.mark.parametrize("d,m,n", [(1, 50, 33), (2, 40, 31), (3, 10, 12)])
 def test_single_level_outputs(d, m, n):
     say(f"[case] out modes d={d}")
