@@ -4,8 +4,9 @@
 //   sine passes: 0 = E16, 256 lanes; 1 = E8, 256 lanes; 2 = E8, one signal, register
 //                twiddles (input transform); 3 = E16, 512 lanes; 4 = E8, 512 lanes; 5, 6 = as 1, 4 with
 //                the lane's twiddles in registers (no LDS table, a third fewer LDS
-//                accesses per tile); 7 = E8, one signal (one wave at N = 512) per
-//                workgroup with register twiddles: barriers stay inside one wave
+//                accesses per tile); 7 = E8, one wave per workgroup (64/P signals;
+//                one signal of N/8 lanes above N = 512) with register twiddles:
+//                barriers stay inside one wave
 //   time kernel: 0 = E16, 128 lanes; 1 = E8, 256 lanes; 2, 3 = as 0, 1 without the
 //                bank-conflict pad (less LDS, more workgroups per CU); 4 = E8, 512
 //                lanes; 5 = E16, 256 lanes (both unpadded: twice the signals per
@@ -25,8 +26,10 @@ constexpr int kTimeVariants = 2;
 constexpr int kTimeMaxN = 2048;
 
 constexpr int dst_E(int V) { return (V == 0 || V == 3) ? 16 : 8; }
-constexpr int dst_T(int N, int V) { return (V == 2 || V == 7) ? N / 8 : ((V == 3 || V == 4 || V == 6) ? 512 : 256); }
-constexpr int dst_S(int N, int V) { return (V == 2 || V == 7) ? 1 : dst_T(N, V) * dst_E(V) / N; }
+constexpr int dst_T(int N, int V) {
+  return V == 2 ? N / 8 : (V == 7 ? (N / 8 < 64 ? 64 : N / 8) : ((V == 3 || V == 4 || V == 6) ? 512 : 256));
+}
+constexpr int dst_S(int N, int V) { return V == 2 ? 1 : dst_T(N, V) * dst_E(V) / N; }
 constexpr size_t dst_lds(int N, int V, bool cols);
 constexpr bool dst_valid(int N, int V) {
   return V >= 0 && V < kDstVariants && N >= 64 && N <= 4096 && (N & (N - 1)) == 0 && dst_S(N, V) >= 1 &&
