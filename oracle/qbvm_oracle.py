@@ -157,6 +157,37 @@ def solve_splu(g_delta, d, m, n, L, T, alpha, variant):
     return lu.solve(f).reshape((n + 1,) + (m,) * d)
 
 
+def solve_general_splu(f, d, m, n, L, T, alpha, variant):
+    """O2 for a general right-hand side f (one block per level, shape (n+1,)+(m,)*d):
+    A y = f with the assembled all-at-once matrix (Sections 3.1, 3.2), by sparse LU.
+    This is one source-term solve, or one application of the PinT system as a
+    preconditioner (Section 6)."""
+    A = assemble_allatonce(d, m, n, L, T, alpha, variant).tocsc()
+    lu = spla.splu(A, permc_spec="COLAMD")
+    return lu.solve(np.ravel(np.asarray(f, dtype=np.float64))).reshape((n + 1,) + (m,) * d)
+
+
+def closed_form_general(f, d, m, n, L, T, alpha, variant):
+    """O3 for a general right-hand side: in the sine basis every mode k obeys the scheme
+    rows (1/tau + mu_k) y^t - y^{t-1}/tau = f^t_k (t >= 1) and
+    (1/tau + mu_k) y^0 - (omega/tau) y^N = f^0_k.  With r = 1/(1 + tau mu_k) the march
+    gives y^t = r y^{t-1} + tau r f^t, so y^N = r^N y^0 + P with
+    P = sum_{t>=1} r^{N-t} tau r f^t; the first row then fixes y^0 and the march the rest."""
+    h, tau, Nt, _ = grid_constants(d, m, n, L, T)
+    omega, _ = omega_and_scale(alpha, variant, tau)
+    mu = stencil_eigenvalues(d, m, L)
+    r = 1.0 / (1.0 + tau * mu)
+    fh = np.stack([dst_ortho(np.asarray(f[t], dtype=np.float64)) for t in range(Nt)], 0)
+    P = np.zeros_like(mu)
+    for t in range(1, Nt):
+        P = r * P + tau * r * fh[t]
+    y = np.empty_like(fh)
+    y[0] = (fh[0] + (omega / tau) * P) / ((1.0 / tau + mu) - (omega / tau) * r ** n)
+    for t in range(1, Nt):
+        y[t] = r * y[t - 1] + tau * r * fh[t]
+    return np.stack([dst_ortho(y[t]) for t in range(Nt)], 0)
+
+
 # ----------------------------------------------------------------------------
 # O3: per-eigenmode closed form
 # ----------------------------------------------------------------------------

@@ -357,3 +357,28 @@ def test_feature_bins_brute_force():
             assert b[idx] == want
     f = O.features(np.ones((9, 9)), 0.5)
     assert f.shape == (33,) and abs(f[32] - math.log10(0.5)) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# general right-hand side (a source term in every block row): the per-mode march
+# against sparse LU of the assembled system, the rank-one case against the closed form
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("d,m,n,alpha,variant", [(1, 17, 12, 1e-3, 0), (2, 9, 7, 1e-5, 1), (3, 4, 5, 1e-2, 0),
+                                                 (2, 6, 1, 0.3, 0)])
+def test_general_rhs_march_vs_sparse_lu(d, m, n, alpha, variant):
+    rng = np.random.default_rng(d * 100 + m + n)
+    f = rng.standard_normal((n + 1,) + (m,) * d)
+    ys = O.solve_general_splu(f, d, m, n, 1.0, 0.8, alpha, variant)
+    yc = O.closed_form_general(f, d, m, n, 1.0, 0.8, alpha, variant)
+    assert np.linalg.norm(ys - yc) <= 1e-10 * np.linalg.norm(ys)
+    A = O.assemble_allatonce(d, m, n, 1.0, 0.8, alpha, variant)
+    assert np.linalg.norm(A @ ys.ravel() - f.ravel()) <= 1e-10 * np.linalg.norm(f)
+
+
+def test_general_rhs_rank_one_is_the_solve():
+    d, m, n, alpha = 2, 11, 9, 1e-4
+    g = np.random.default_rng(5).standard_normal((m, m))
+    f = O.rhs_allatonce(g, n, alpha, O.PQ, 1.0).reshape((n + 1, m, m))
+    yg = O.closed_form_general(f, d, m, n, 1.0, 1.0, alpha, O.PQ)
+    y = O.closed_form(g, d, m, n, 1.0, 1.0, alpha, O.PQ)
+    assert np.linalg.norm(yg - y) <= 1e-11 * np.linalg.norm(y)
