@@ -233,6 +233,37 @@ def batched_bench(reps: int = 3):
             "classes": out, "sampled_parity_max_rel_err": max(errs)}
 
 
+def general_rhs_bench(steps: int = 20):
+    """General right-hand side (every level nonzero) on the 2D workload's grid: seconds per
+    solve through qbvm_solve_general, and the HBM fraction of its schedule (d sine passes
+    in, the time kernel, d passes out: 16 B per unknown each)."""
+    import numpy as np
+    import torch
+    from paper_2107_06381_amd import qbvm
+    d, m, n, alpha = 2, 255, 256, 1e-4
+    plan = qbvm.Plan(d, m, n, 1.0, 1.0)
+    plan.autotune()
+    f = torch.from_numpy(np.random.default_rng(11).standard_normal((n + 1, m, m))).to("cuda:0")
+    y = torch.empty_like(f)
+    for _ in range(3):
+        plan.solve_general(alpha, qbvm.QBVM_PQ, f, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.solve_general(alpha, qbvm.QBVM_PQ, f, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    unknowns = n * m ** d
+    sched_bytes = 16.0 * (n + 1) * m ** d * (2 * d + 1)
+    plan.close()
+    return {"workload": "2D m=255, n=256 (N_t=257), general right-hand side (all 257 levels), alpha=1e-4",
+            "ms_per_solve": round(ms, 4), "Munknowns_per_s": round(unknowns / (ms * 1e-3) / 1e6, 1),
+            "schedule_bytes_per_unknown": 16 * (2 * d + 1),
+            "step_hbm_roofline_frac": round(sched_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +274,7 @@ def main():
     ap.add_argument("--no-alpha", action="store_true", help="skip the learned/bisection alpha-choice section")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched section")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D solve section")
+    ap.add_argument("--no-general", action="store_true", help="skip the general right-hand-side section")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for counter calibration)")
     ap.add_argument("--alpha-train", type=int, default=20000)
@@ -332,6 +364,7 @@ def main():
     solve3d = None if args.no_3d else solve_3d_bench(5)
     alpha = None if args.no_alpha else alpha_choice_bench(args.alpha_train, args.alpha_test, 200, 3000)
     batched = None if args.no_batched else batched_bench()
+    general = None if args.no_general else general_rhs_bench()
     line = {
         "metric": "PinT solve Munknowns/s (n*m^d, FP64)",
         "value": round(value, 2),
@@ -355,6 +388,7 @@ def main():
         "solve_3d": solve3d,
         "alpha_choice": alpha,
         "batched": batched,
+        "general_rhs": general,
         "parity_rel_err": parity,
         "cpu_baseline": cpu,
     }

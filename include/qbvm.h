@@ -141,6 +141,16 @@ int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var
 int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta,
                double* y, int output);
 
+/* Solve the all-at-once system of Sections 3.1/3.2 for a general right-hand side (an
+ * addition beyond the paper's data: source terms, or one application of the PinT
+ * system as a preconditioner).  f: DEVICE, (n+1) m^d doubles, one block per level,
+ * for the rows (I/tau - Lap_h) y^0 - (omega/tau) y^N = f^0 and
+ * (I/tau - Lap_h) y^t - y^{t-1}/tau = f^t (t >= 1); y: DEVICE, (n+1) m^d doubles, may
+ * equal f.  Step (a) becomes a Gamma_omega-scaled DFT along time of every mode.
+ * qbvm_solve is the case f = (f0, 0, ..., 0).  Asynchronous on the plan's stream;
+ * QBVM_EUNSUPPORTED when one time signal and its working copy exceed a workgroup's LDS. */
+int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f, double* y);
+
 /* Solve `count` independent instances of possibly different grids in one
  * batched launch sequence (an addition; not in the paper).  All arrays of
  * length `count` are HOST arrays; g_deltas[i] and ys[i] are DEVICE pointers

@@ -54,7 +54,13 @@ __device__ __forceinline__ void tab_job_run(const TabJob& t, long long gid, long
   const double croot = exp(sc.logabsw / (double)t.Nt);
   for (long long j = gid; j < t.Nt; j += gstride) {
     t.out[j] = shift_over_tau((int)j, t.Nt, croot, 1.0 / t.tau);
-    t.out[t.Nt + j] = inv_gamma((int)j, t.Nt, sc.logabsw, sc.f0s / (double)t.Nt);
+    t.out[t.Nt + j] = inv_gamma((int)j, t.Nt, sc.logabsw, (t.general ? 1.0 : sc.f0s) / (double)t.Nt);
+    if (t.general) {  // gamma_t = |omega|^{t/N_t} exp(i pi t/N_t)
+      double sn, cs;
+      sincospi((double)j / (double)t.Nt, &sn, &cs);
+      const double gm = exp((double)j * sc.logabsw / (double)t.Nt);
+      t.out[2 * t.Nt + j] = {gm * cs, gm * sn};
+    }
   }
 }
 
@@ -204,6 +210,83 @@ __device__ __forceinline__ void time_body(const TimeArgs& a, long long wg, c64* 
   }
 }
 
+
+// ======================================================== k_time_general ====
+// Steps (a)-(c) for a general right-hand side (every level), per pair of sine modes:
+//   z_j = sum_t theta^{jt} gamma_t f_t          (Step (a), the factor 1/sqrt(N_t) moved to (c))
+//   w_j = z_j / (d_j/tau + mu_k)                (Step (b))
+//   y_l = gamma_l^{-1}/N_t sum_j theta^{-jl} w_j  (Step (c)), real.
+// Two real modes a, b share one transform.  Step (a) of a real sequence satisfies
+// z(N_t-1-j) = conj z(j) (gamma_t theta^{jt} is |omega|^{t/N_t} exp(i pi t(2j+1)/N_t)),
+// which separates z_a and z_b before their different shifts; the results of Step (c)
+// are real, so w = w_a + i w_b packs them again.  The sums over theta^{+jt} run on the
+// forward engine through conj(sum_t conj(u_t) theta^{-jt}).  Tables (global, per
+// solve): d_j/tau, gamma_l^{-1}/N_t, gamma_t.  In place: fgen may equal y.
+template <bool WIDE>
+__device__ __forceinline__ void time_general_body(const TimeArgs& a, long long wg, c64* lds) {
+  const int S = a.S, Nt = a.Nt, nc = a.fft.nc;
+  c64* buf = lds;                               // S * nc, engine layout
+  c64* zb = buf + (size_t)S * nc;               // S * N_t, natural order [j][s]
+  c64* side = zb + (size_t)S * Nt;              // 2 S
+  double* mus = reinterpret_cast<double*>(side + 2 * S);  // 2 S
+  const c64* dt = a.tabs;
+  const c64* gi = a.tabs + Nt;
+  const c64* gam = a.tabs + 2 * Nt;
+  const long long k0 = wg * 2LL * S;
+  for (int q = threadIdx.x; q < 2 * S; q += blockDim.x) {
+    const long long k = k0 + q;
+    mus[q] = k < a.nmodes ? mode_mu(k, a.d, a.m, a.mu1d) : 0.0;
+  }
+  // Step (a) input: conj(gamma_t (f_a(t) + i f_b(t))), placed for the engine
+  for (int e = threadIdx.x; e < S * Nt; e += blockDim.x) {
+    const int t = e / S, s = e - t * S;
+    const long long ka = k0 + 2 * s;
+    const double* ft = a.fgen + (long long)t * a.ystride;
+    const c64 f = {ka < a.nmodes ? ft[ka] : 0.0, ka + 1 < a.nmodes ? ft[ka + 1] : 0.0};
+    const c64 u = cconj(cmul(gam[t], f));
+    const int pos = fft_in_pos(a.fft, t);
+    if (pos < 0) side[s] = u;
+    else buf[(size_t)pos * S + s] = u;
+  }
+  __syncthreads();
+  if (a.fft.kind == kBluestein) fft_bluestein_prep(buf, S, a.fft);
+  fft_run<WIDE>(buf, S, a.fft, side);
+  for (int e = threadIdx.x; e < S * Nt; e += blockDim.x) {
+    const int j = e / S, s = e - j * S;
+    zb[(size_t)j * S + s] = cconj(fft_out(buf, S, a.fft, s, j, side));
+  }
+  __syncthreads();
+  // separate, Step (b), pack, place for the second transform
+  for (int e = threadIdx.x; e < S * Nt; e += blockDim.x) {
+    const int j = e / S, s = e - j * S;
+    const c64 zj = zb[(size_t)j * S + s];
+    const c64 zr = cconj(zb[(size_t)(Nt - 1 - j) * S + s]);
+    const c64 za = {0.5 * (zj.re + zr.re), 0.5 * (zj.im + zr.im)};  // (z + conj z')/2
+    const c64 zbm = {0.5 * (zj.im - zr.im), -0.5 * (zj.re - zr.re)};  // (z - conj z')/(2i)
+    const c64 z = dt[j];
+    const double xa = z.re + mus[2 * s], xb = z.re + mus[2 * s + 1];
+    const double qa = recip_nr(xa * xa + z.im * z.im), qb = recip_nr(xb * xb + z.im * z.im);
+    // w_a = za / (xa + i z.im), w_b = zbm / (xb + i z.im)
+    const c64 wa = {(za.re * xa + za.im * z.im) * qa, (za.im * xa - za.re * z.im) * qa};
+    const c64 wb = {(zbm.re * xb + zbm.im * z.im) * qb, (zbm.im * xb - zbm.re * z.im) * qb};
+    const c64 w = {wa.re - wb.im, wa.im + wb.re};  // w_a + i w_b
+    const int pos = fft_in_pos(a.fft, j);
+    if (pos < 0) side[s] = w;
+    else buf[(size_t)pos * S + s] = w;
+  }
+  __syncthreads();
+  if (a.fft.kind == kBluestein) fft_bluestein_prep(buf, S, a.fft);
+  fft_run<WIDE>(buf, S, a.fft, side);
+  // Step (c): gamma_l^{-1}/N_t X_l; real part -> mode a, imaginary part -> mode b
+  for (int e = threadIdx.x; e < S * Nt; e += blockDim.x) {
+    const int l = e / S, s = e - l * S;
+    const c64 v = cmul(gi[l], fft_out(buf, S, a.fft, s, l, side));
+    const long long ka = k0 + 2 * s;
+    double* yl = a.y + (long long)l * a.ystride;
+    if (ka < a.nmodes) yl[ka] = v.re;
+    if (ka + 1 < a.nmodes) yl[ka + 1] = v.im;
+  }
+}
 
 // ============================================================= k_thomas ====
 // Step (b) in 1D: (d_j/tau + 2/h^2) s_i - (s_{i-1} + s_{i+1})/h^2 = f0_i for each shift j.

@@ -250,7 +250,7 @@ struct qbvm_plan_s {
   c64* s2 = nullptr;
   c64* cp = nullptr;
   double* W = nullptr;  // padded level workspace (d >= 2 power-of-two pipeline)
-  c64* tabs = nullptr;  // per-solve time-transform tables, 2 N_t
+  c64* tabs = nullptr;  // per-solve time-transform tables, 3 N_t
   double* partial = nullptr;
   unsigned* counter = nullptr;
   double* dscal = nullptr;   // [0] delta, [1] alpha_pred, [2] log10 alpha_pred, [3] D, [4] alpha_final, ...
@@ -403,7 +403,7 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
     HIP_TRY(dalloc(p, &p->cp, (size_t)p->Nt * p->m));
   }
   if (sched::use_padded(geom(p))) HIP_TRY(dalloc(p, &p->W, (size_t)sched::padded_elems(geom(p))));
-  HIP_TRY(dalloc(p, &p->tabs, 2 * (size_t)p->Nt));
+  HIP_TRY(dalloc(p, &p->tabs, 3 * (size_t)p->Nt));
   // four lanes per mode in the row kernel (64 modes per 256-lane workgroup)
   p->wg_row = (int)std::max<long long>(1, std::min<long long>(4096, (p->nmodes + 63) / 64));
   HIP_TRY(dalloc(p, &p->partial, std::max<long long>(p->wg_row, 32)));  // row reduction; 32 feature bins
@@ -641,6 +641,27 @@ int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta, 
                    nullptr, p->wg_row);
   if (rc) return rc;
   return run_dst(p, p->yrow, y, 1, false);
+}
+
+int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f, double* y) {
+  if (!p || !f || !y) return set_error(QBVM_EINVAL, "NULL argument");
+  int rc = check_alpha(alpha, variant);
+  if (rc) return rc;
+  const sched::Geom G = geom(p);
+  const auto t = sched::time_general_step(G, y, y, p->tabs);
+  if (t.lds > 160 * 1024) return set_error(QBVM_EUNSUPPORTED, "time transform too long for the general solve");
+  // sine transform of every level of f into y
+  rc = run_dst(p, f, y, p->Nt, false);
+  if (rc) return rc;
+  const TabJob job{p->tabs, p->Nt, variant, p->tau, alpha, nullptr, 1};
+  HIP_TRY(launch_tab_job(job, p->stream));
+  {
+    const double nm = (double)p->nmodes;
+    ProfScope ps("time_general", p->stream, 16.0 * nm * p->Nt,
+                 nm * (fft_flops(p->tfft->dev) + 40.0 * p->Nt), nullptr);
+    HIP_TRY(launch_time_general(t.args, t.nwg, t.lds, p->stream));
+  }
+  return run_dst(p, y, y, p->Nt, false);
 }
 
 int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_delta, double* D_out) {

@@ -610,6 +610,16 @@ hipError_t launch_feat_predict(double hd, const double* ghat, double delta, cons
   return hipGetLastError();
 }
 
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_time_general(TimeArgs a) {
+  extern __shared__ c64 lds[];
+  time_general_body<WIDE>(a, blockIdx.x, lds);
+}
+
+__global__ void k_tab_job(TabJob t) {
+  tab_job_run(t, (long long)blockIdx.x * blockDim.x + threadIdx.x, (long long)gridDim.x * blockDim.x);
+}
+
 __global__ void k_copy_scale(const double* in, double* out, long long n, double s) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = in[i] * s;
@@ -714,6 +724,15 @@ hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds
     if (!f) return hipErrorInvalidValue;
   }
   return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
+}
+
+hipError_t launch_time_general(const TimeArgs& a, long long nwg, size_t lds, hipStream_t s) {
+  const void* f = a.fft.wide ? (const void*)&k_time_general<true> : (const void*)&k_time_general<false>;
+  return enqueue1(f, dim3((unsigned)nwg), dim3(256), lds, s, a, nullptr);
+}
+
+hipError_t launch_tab_job(const TabJob& t, hipStream_t s) {
+  return enqueue1((const void*)&k_tab_job, dim3((unsigned)((t.Nt + 255) / 256)), dim3(256), 0, s, t, nullptr);
 }
 
 hipError_t launch_thomas(const ThomasArgs& a, hipStream_t s, NodeCtx* nc) {

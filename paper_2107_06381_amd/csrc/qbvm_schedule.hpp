@@ -213,6 +213,32 @@ inline Launch<TimeArgs> time_step_padded(const Geom& g, SolveScalars sc, const d
   return L;
 }
 
+// Time kernel of the general right-hand side: fgen (sine basis, every level) -> y, in
+// place allowed; tables [d_j/tau | gamma_l^{-1}/N_t | gamma_t] in tabs.
+inline Launch<TimeArgs> time_general_step(const Geom& g, const double* fgen, double* y, const c64* tabs) {
+  TimeArgs t{};
+  t.Nt = g.Nt;
+  t.d = g.d;
+  t.m = g.m;
+  t.S = g.S_time;
+  t.nmodes = g.nmodes;
+  t.ystride = g.nmodes;
+  t.lev_first = 0;
+  t.lev_count = g.Nt;
+  t.tau = g.tau;
+  t.mu1d = g.mu1d;
+  t.y = y;
+  t.fgen = fgen;
+  t.tabs = tabs;
+  t.fft = g.tfft;
+  t.fft.p2 = 0;
+  t.fft.gtA = t.fft.gtB = 0;
+  t.threads = 256;
+  const size_t lds = sizeof(c64) * ((size_t)t.S * g.tfft.nc + (size_t)t.S * g.Nt + 2 * (size_t)t.S) +
+                     sizeof(double) * 2 * (size_t)t.S;
+  return {t, (g.nmodes + 2LL * t.S - 1) / (2LL * t.S), lds};
+}
+
 inline ThomasArgs thomas_step(const Geom& g, SolveScalars sc, const double* alpha_dev, int variant,
                               const double* gd, c64* s2, c64* cp) {
   ThomasArgs ta{};

@@ -75,6 +75,7 @@ struct TimeArgs {
   long long pitch;   // > 0: y rows of m modes padded to this pitch (tiles never straddle rows)
   int tiles_per_row;
   const c64* tabs;   // optional: [N_t] d_j/tau then [N_t] f0s/N_t gamma_l^{-1} for this solve
+  const double* fgen; // general right-hand side in the sine basis, levels ystride apart (general solve)
   FftPlanDev fft;
 };
 
@@ -87,6 +88,7 @@ struct TabJob {
   double tau;
   double alpha;
   const double* alpha_dev;  // if non-null, alpha is read from here
+  int general;              // 1: [N_t] gamma_l^{-1}/N_t (no f0s), then [N_t] gamma_t as well
 };
 
 // Sine-transform pass: data viewed as [outer][len][inner]; transform along len.

@@ -27,7 +27,7 @@ ERR_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOROOT", -5:
 # every symbol include/qbvm.h declares
 EXPORTS = [
     "qbvm_plan", "qbvm_plan_destroy", "qbvm_plan_set_stream", "qbvm_plan_workspace_bytes",
-    "qbvm_solve", "qbvm_solve_batched", "qbvm_batched_cache_clear", "qbvm_discrepancy",
+    "qbvm_solve", "qbvm_solve_general", "qbvm_solve_batched", "qbvm_batched_cache_clear", "qbvm_discrepancy",
     "qbvm_choose_alpha", "qbvm_bisect_batched", "qbvm_features", "qbvm_set_alpha_model",
     "qbvm_mlp_forward", "qbvm_mlp_loss_grad", "qbvm_adam_step", "qbvm_strerror",
     "qbvm_last_error", "qbvm_version", "qbvm_profile_enable", "qbvm_profile_reset",
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qbvm_plan_set_stream": (i, [vp, vp]),
         "qbvm_plan_workspace_bytes": (ll, [vp]),
         "qbvm_solve": (i, [vp, d, i, vp, vp, i]),
+        "qbvm_solve_general": (i, [vp, d, i, vp, vp]),
         "qbvm_solve_batched": (i, [i, ctypes.POINTER(Grid), ctypes.POINTER(d), ctypes.POINTER(i),
                                    ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i), vp]),
         "qbvm_batched_cache_clear": (None, []),
@@ -194,6 +195,17 @@ class Plan:
         nout = self.nmodes * ((self.n + 1) if output == OUT_ALL else 1)
         yp = _dev_tensor(y, nout, torch.float64, "y")
         _check(self.L_.qbvm_solve(self._h, float(alpha), int(variant), gp, yp, int(output)))
+        return y
+
+    def solve_general(self, alpha: float, variant: int, f, y=None):
+        """All-at-once system with right-hand side f ((n+1, m, ..) levels) -> y (may be f)."""
+        import torch
+        if y is None:
+            y = torch.empty(self.out_shape(OUT_ALL), dtype=torch.float64, device=f.device)
+        n = self.nmodes * (self.n + 1)
+        fp = _dev_tensor(f, n, torch.float64, "f")
+        yp = _dev_tensor(y, n, torch.float64, "y")
+        _check(self.L_.qbvm_solve_general(self._h, float(alpha), int(variant), fp, yp))
         return y
 
     def discrepancy(self, alpha: float, variant: int, g_delta) -> float:

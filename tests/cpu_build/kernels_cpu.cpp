@@ -4,6 +4,7 @@
 //   kernels_cpu fft   n S in.bin out.bin          (S signals, signal-major complex)
 //   kernels_cpu solve d m n L T alpha variant in.bin out.bin [var_rows var_cols var_time [padded]]
 //   kernels_cpu dst   d m batch in.bin out.bin [var_rows var_cols input]
+//   kernels_cpu general d m n L T alpha variant f.bin out.bin   (general right-hand side)
 #include "hip_cpu_shim.hpp"
 
 #include <cstdio>
@@ -286,6 +287,38 @@ int main(int argc, char** argv) {
     write_file(argv[6], out, N * sizeof(double));
     delete[] in;
     delete[] out;
+    return 0;
+  }
+  if (cmd == "general" && argc == 11) {
+    const int d = atoi(argv[2]), m = atoi(argv[3]), n = atoi(argv[4]);
+    const double L = atof(argv[5]), T = atof(argv[6]), alpha = atof(argv[7]);
+    const int variant = atoi(argv[8]);
+    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1));
+    const double h = L / (m + 1);
+    std::vector<double> mu(m);
+    for (int k = 1; k <= m; ++k) {
+      const long double s = sinl((long double)k * plan::kPiL / (2.0L * (m + 1)));
+      mu[k - 1] = (double)(4.0L / ((long double)h * h) * s * s);
+    }
+    sched::Geom g = geom(d, m, n, L, T, tt, st, mu);
+    auto raw = read_file(argv[9]);
+    const size_t ny = (size_t)g.Nt * g.nmodes;
+    if (raw.size() != ny * sizeof(double)) return 7;
+    double* y = new double[ny];
+    double* f = new double[ny];
+    std::memcpy(f, raw.data(), raw.size());
+    run_dst(g, f, y, g.Nt, false);
+    std::vector<c64> tabs(3 * (size_t)g.Nt, c64{std::nan(""), std::nan("")});
+    const TabJob job{tabs.data(), g.Nt, variant, g.tau, alpha, nullptr, 1};
+    tab_job_run(job, 0, 1);
+    const auto t = sched::time_general_step(g, y, y, tabs.data());
+    if (t.lds > 160 * 1024) return 16;
+    if (t.args.fft.wide) run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_general_body<true>(t.args, wg, l); });
+    else run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_general_body<false>(t.args, wg, l); });
+    run_dst(g, y, y, g.Nt, false);
+    write_file(argv[10], y, ny * sizeof(double));
+    delete[] y;
+    delete[] f;
     return 0;
   }
   if (cmd == "solve" && (argc == 11 || argc == 14 || argc == 15)) {

@@ -125,6 +125,20 @@ def test_solve_schedule_vs_oracle(exe, tmp_path, case, kv):
     assert ok, r
 
 
+@pytest.mark.parametrize("d,m,n,alpha,variant", [(1, 17, 12, 1e-3, 0), (2, 15, 16, 1e-4, 1), (2, 20, 11, 1e-2, 0),
+                                                 (3, 6, 7, 1e-5, 0), (2, 63, 128, 1e-4, 0), (1, 9, 1, 0.3, 1)])
+def test_general_rhs_vs_oracle(exe, tmp_path, d, m, n, alpha, variant):
+    """General right-hand side (every level): Gamma-scaled time transform per mode,
+    separation of the two packed modes, shifted division, inverse transform."""
+    f = np.random.default_rng(d * 10 + m + n).standard_normal((n + 1,) + (m,) * d)
+    fi, fo = tmp_path / "f.bin", tmp_path / "o.bin"
+    f.tofile(fi)
+    _run(exe, ["general", d, m, n, "1.0", "0.8", repr(alpha), variant, fi, fo], tmp_path)
+    y = np.fromfile(fo).reshape(f.shape)
+    yc = O.closed_form_general(f, d, m, n, 1.0, 0.8, alpha, variant)
+    assert np.linalg.norm(y - yc) <= 1e-10 * np.linalg.norm(yc)
+
+
 def test_library_exports_every_declared_symbol():
     from paper_2107_06381_amd import qbvm
     L = qbvm.load()

@@ -169,6 +169,39 @@ def test_single_level_outputs(d, m, n):
         assert rel(y, yc) < TOL
 
 
+@pytest.mark.parametrize("d,m,n,alpha,variant", [(1, 127, 128, 1e-3, 0), (2, 63, 64, 1e-4, 1), (2, 100, 52, 1e-6, 0),
+                                                 (3, 15, 16, 1e-3, 0), (2, 255, 256, 1e-4, 0), (1, 1, 1, 0.5, 0)])
+def test_general_rhs_vs_oracle(d, m, n, alpha, variant):
+    """General right-hand side in every block row (source terms / preconditioner use)."""
+    say(f"[case] general rhs d={d} m={m} n={n}")
+    f = np.random.default_rng(d * 17 + m + n).standard_normal((n + 1,) + (m,) * d)
+    p = qbvm.Plan(d, m, n, 1.0, 0.9)
+    y = p.solve_general(alpha, variant, to_dev(f))
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    p.close()
+    yc = O.closed_form_general(f, d, m, n, 1.0, 0.9, alpha, variant)
+    assert np.all(np.isfinite(y))
+    assert rel(y, yc) < TOL and rel(y[0], yc[0]) < TOL
+    if m ** d * (n + 1) < 20000:
+        ys = O.solve_general_splu(f, d, m, n, 1.0, 0.9, alpha, variant)
+        assert rel(y, ys) < TOL
+
+
+def test_general_rhs_rank_one_and_in_place():
+    """f = (f0, 0, ..., 0) reproduces qbvm_solve; y may be f itself."""
+    say("[case] general rhs rank one")
+    d, m, n, alpha = 2, 127, 128, 1e-4
+    g = np.random.default_rng(8).standard_normal((m, m))
+    p = qbvm.Plan(d, m, n)
+    f = O.rhs_allatonce(g, n, alpha, O.PQ, 1.0).reshape((n + 1, m, m))
+    fd = to_dev(f)
+    y1 = p.solve(alpha, 0, to_dev(g)).clone()
+    p.solve_general(alpha, 0, fd, fd)  # in place
+    torch.cuda.synchronize()
+    assert rel(fd.cpu().numpy(), y1.cpu().numpy()) < 1e-11
+
+
 def test_pq_pm_identity_and_determinism():
     """PinT-MQBVM with alpha equals PinT-QBVM with alpha/tau (Section 4); repeated solves are bitwise equal."""
     say("[case] identity")
