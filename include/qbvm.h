@@ -120,14 +120,15 @@ long long qbvm_plan_workspace_bytes(qbvm_plan_t p);
 
 /* Autotuner (an addition): for the power-of-two kernels of this plan's shape, time
  * every kernel variant (complex values per lane, signals per workgroup) of the
- * sine passes over the levels and of the time transform on a scratch array of
- * the full solution size, and keep the fastest in the plan.  Results are also
+ * sine passes over the levels, of the time transform and of the general
+ * right-hand side's time transform on a scratch array of the full solution size,
+ * and keep the fastest in the plan.  Results are also
  * cached per (device, kernel role, transform length) and used as the defaults of
  * later plans.  The plan's current variant is kept unless another is more than 3%
  * faster.  Synchronous; allocates and frees (n+1) m^d doubles of scratch.
- * ms_out (HOST, may be NULL) receives 20 timings in milliseconds (-1 where not
+ * ms_out (HOST, may be NULL) receives 26 timings in milliseconds (-1 where not
  * applicable): rows variants 0, 1, 3, 4, 5, 6, 7; columns variants 0, 1, 3, 4, 5,
- * 6, 7; time variants 0..5. */
+ * 6, 7; time variants 0..5; general right-hand-side time variants 0..5. */
 int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out);
 
 /* The kernel variants a plan uses (HOST outputs): sine rows, sine columns, time. */
@@ -147,8 +148,10 @@ int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta,
  * for the rows (I/tau - Lap_h) y^0 - (omega/tau) y^N = f^0 and
  * (I/tau - Lap_h) y^t - y^{t-1}/tau = f^t (t >= 1); y: DEVICE, (n+1) m^d doubles, may
  * equal f.  Step (a) becomes a Gamma_omega-scaled DFT along time of every mode.
- * qbvm_solve is the case f = (f0, 0, ..., 0).  Asynchronous on the plan's stream;
- * QBVM_EUNSUPPORTED when one time signal and its working copy exceed a workgroup's LDS. */
+ * qbvm_solve is the case f = (f0, 0, ..., 0).  f is not modified unless y == f.
+ * Asynchronous on the plan's stream; uses the plan's workspace and tables, so calls
+ * on one plan are ordered by its stream.  QBVM_EUNSUPPORTED when one time signal and
+ * its working copy exceed a workgroup's LDS. */
 int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f, double* y);
 
 /* Solve `count` independent instances of possibly different grids in one

@@ -174,20 +174,111 @@ __device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long fir
   }
 }
 
+// Length-N_t DFT X_l = sum_j x_j e^{-2 pi i jl/N_t} of each signal of the workgroup on the
+// compile-time engine: N_t = N, or N_t = N + 1 prime (Rader: a cyclic convolution of
+// length N carried out by two length-N transforms).  input(j, e) returns x_j for the
+// lane's register slot e (-1: x_0 of a Rader length); emit(l, X_l, e) receives each
+// output the lane holds, every l < N_t once per signal (e = -1: X_0 of a Rader length).
+template <int N, int E, class L, bool RADER, class TW, class In, class Out>
+__device__ __forceinline__ void p2_time_dft(In input, Out emit, int s, int u, c64* buf, const TW& tw,
+                                            const c64* ks, const int* gfw, const int* gbw) {
+  c64 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int q = p2_in_pos<N, E, 0>(u, e);
+    v[e] = input(RADER ? gfw[q] : q, e);
+  }
+  p2_fft<N, E, L>(v, s, u, buf, tw);
+  if constexpr (RADER) {
+    const c64 x0 = input(0, -1);
+    const c64 sum = v[0];  // position 0 on lane u == 0: sum_{j>=1} x_j
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cconj(cmul(v[e], ks[p2_out_pos<N, E>(u, e)]));
+    p2_out_to_in<N, E, L>(v, s, u, buf);
+    p2_fft<N, E, L>(v, s, u, buf, tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) emit(gbw[p2_out_pos<N, E>(u, e)], cadd(x0, cconj(v[e])), e);
+    if (u == 0) emit(0, cadd(x0, sum), -1);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) emit(p2_out_pos<N, E>(u, e), v[e], e);
+  }
+}
+
+// LDS after the exchange buffer: twiddles, Rader kernel spectrum and index maps, tables.
+template <int N, int E, class L, bool RADER>
+struct TimeLds {
+  static constexpr int TWM = p2sz::time_tw_mode(N, E);
+  c64* buf;
+  c64* twl;
+  c64* ks;
+  c64* dt;
+  c64* gi;
+  int* gfw;
+  int* gbw;
+  __device__ __forceinline__ explicit TimeLds(c64* lds, int Nt) {
+    buf = lds;
+    twl = buf + L::lds_elems();
+    ks = twl + p2sz::tw_elems(N, TWM);
+    dt = ks + N;
+    gi = dt + Nt;
+    gfw = reinterpret_cast<int*>(gi + Nt);
+    gbw = gfw + N;
+  }
+  // past the two index maps: further per-kernel tables
+  __device__ __forceinline__ c64* extra() const { return reinterpret_cast<c64*>(gbw + N); }
+  __device__ __forceinline__ void load_rader(const FftPlanDev& f, int t, int T) const {
+    if constexpr (RADER) {
+      for (int i = t; i < N; i += T) {
+        ks[i] = f.kspec[i];
+        gfw[i] = f.gfwd[i];
+        gbw[i] = f.ginvt[i];
+      }
+    }
+  }
+};
+
+// Modes of a time tile: flattened (pitch 0) or 2S consecutive x_1 of one padded row.
+struct TimeTile {
+  long long ka, oa;
+  bool oka, okb;
+  __device__ __forceinline__ TimeTile(const TimeArgs& a, long long wg, int S, int s) {
+    if (a.pitch > 0) {
+      const long long row = wg / a.tiles_per_row;
+      const int c1 = (int)(wg - row * a.tiles_per_row) * 2 * S + 2 * s;
+      ka = row * a.m + c1;
+      oa = row * a.pitch + c1;
+      oka = c1 < a.m;
+      okb = c1 + 1 < a.m;
+    } else {
+      ka = wg * 2LL * S + 2 * s;
+      oa = ka;
+      oka = ka < a.nmodes;
+      okb = ka + 1 < a.nmodes;
+    }
+  }
+  // gamma_l^{-1} X_l to level l: real part -> first mode, imaginary part -> second.
+  // Padded rows (pitch > 0): the pair is one aligned 16-byte store; a pair whose second
+  // mode is past the row end writes that value into the row padding.
+  __device__ __forceinline__ void store(const TimeArgs& a, int l, c64 yv) const {
+    double* yl = a.y + (long long)l * a.ystride;
+    if (a.pitch > 0) {
+      if (oka) *reinterpret_cast<c64*>(yl + oa) = yv;
+    } else {
+      if (oka) yl[oa] = yv.re;
+      if (okb) yl[oa + 1] = yv.im;
+    }
+  }
+};
+
 // Spectral time kernel, every level written.  RADER: N_t = N + 1 prime; else N_t = N.
 template <int N, int E, int S, bool RADER, bool PAD = true>
 __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c64* lds) {
   static_assert(S >= 1, "time kernel needs N <= 2048");
   using L = P2Layout<N, E, S, true, PAD>;
+  using M = TimeLds<N, E, L, RADER>;
   const int Nt = a.Nt;
-  c64* buf = lds;
-  constexpr int TWM = p2sz::time_tw_mode(N, E);
-  c64* twl = buf + L::lds_elems();
-  c64* ks = twl + p2sz::tw_elems(N, TWM);
-  c64* dt = ks + N;
-  c64* gi = dt + Nt;
-  int* gfw = reinterpret_cast<int*>(gi + Nt);
-  int* gbw = gfw + N;
+  const M sh(lds, Nt);
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
 
   SolveScalars sc = a.sc;
@@ -197,87 +288,125 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
   const double gscale = sc.f0s / (double)Nt;
   if (a.tabs) {  // d_j/tau and gamma_l^{-1} f0s/N_t precomputed for this solve
     for (int j = t; j < Nt; j += L::T) {
-      dt[j] = a.tabs[j];
-      gi[j] = a.tabs[Nt + j];
+      sh.dt[j] = a.tabs[j];
+      sh.gi[j] = a.tabs[Nt + j];
     }
   } else {
     for (int j = t; j < Nt; j += L::T) {
-      dt[j] = shift_over_tau(j, Nt, croot, inv_tau);
-      gi[j] = inv_gamma(j, Nt, sc.logabsw, gscale);
+      sh.dt[j] = shift_over_tau(j, Nt, croot, inv_tau);
+      sh.gi[j] = inv_gamma(j, Nt, sc.logabsw, gscale);
     }
   }
-  if constexpr (RADER) {
-    for (int i = t; i < N; i += L::T) {
-      ks[i] = a.fft.kspec[i];
-      gfw[i] = a.fft.gfwd[i];
-      gbw[i] = a.fft.ginvt[i];
-    }
-  }
-  const auto tw = p2_twiddles<N, TWM, E>(a.fft, twl, t, L::T, u);
+  sh.load_rader(a.fft, t, L::T);
+  const auto tw = p2_twiddles<N, M::TWM, E>(a.fft, sh.twl, t, L::T, u);
   __syncthreads();
 
-  // modes of this tile: flattened (pitch 0) or 2S consecutive x_1 of one padded row
-  long long ka, oa;
-  bool oka, okb;
-  if (a.pitch > 0) {
-    const long long row = wg / a.tiles_per_row;
-    const int c1 = (int)(wg - row * a.tiles_per_row) * 2 * S + 2 * s;
-    ka = row * a.m + c1;
-    oa = row * a.pitch + c1;
-    oka = c1 < a.m;
-    okb = c1 + 1 < a.m;
-  } else {
-    ka = wg * 2LL * S + 2 * s;
-    oa = ka;
-    oka = ka < a.nmodes;
-    okb = ka + 1 < a.nmodes;
-  }
-  const long long kb = ka + 1;
-  const double ga = oka ? a.ghat[ka] : 0.0, gb = okb ? a.ghat[kb] : 0.0;
-  const double mua = oka ? mode_mu(ka, a.d, a.m, a.mu1d) : 0.0;
-  const double mub = okb ? mode_mu(kb, a.d, a.m, a.mu1d) : 0.0;
+  const TimeTile tile(a, wg, S, s);
+  const double ga = tile.oka ? a.ghat[tile.ka] : 0.0, gb = tile.okb ? a.ghat[tile.ka + 1] : 0.0;
+  const double mua = tile.oka ? mode_mu(tile.ka, a.d, a.m, a.mu1d) : 0.0;
+  const double mub = tile.okb ? mode_mu(tile.ka + 1, a.d, a.m, a.mu1d) : 0.0;
   // Steps (a)+(b): u_j = g_a/(d_j/tau + mu_a) + i g_b/(d_j/tau + mu_b)
-  auto input = [&](int j) -> c64 {
-    const c64 z = dt[j];
+  auto input = [&](int j, int) -> c64 {
+    const c64 z = sh.dt[j];
     const double xa = z.re + mua, xb = z.re + mub;
     const double ia = ga * recip_nr(xa * xa + z.im * z.im);
     const double ib = gb * recip_nr(xb * xb + z.im * z.im);
     return {ia * xa + ib * z.im, ib * xb - ia * z.im};
   };
-  c64 v[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int q = p2_in_pos<N, E, 0>(u, e);
-    v[e] = input(RADER ? gfw[q] : q);
+  auto emit = [&](int l, c64 X, int) { tile.store(a, l, cmul(sh.gi[l], X)); };
+  p2_time_dft<N, E, L, RADER>(input, emit, s, u, sh.buf, tw, sh.ks, sh.gfw, sh.gbw);
+}
+
+// Time kernel of the general right-hand side on the compile-time engine.  Per signal
+// (modes a, b packed as f_a + i f_b, levels t < N_t read from fgen):
+//   z_j = sum_t gamma_t f_t e^{+2 pi i jt/N_t} = conj(DFT(conj(gamma f)))_j;
+//   for real f_a, f_b the two modes' transforms separate through the pair (j, N_t-1-j):
+//   Z_a(N_t-1-j) = conj Z_a(j), so Z_a = (z_j + conj z_{N_t-1-j})/2 and
+//   Z_b = (z_j - conj z_{N_t-1-j})/(2i);
+//   w_j = Z_a/(d_j/tau + mu_a) + i Z_b/(d_j/tau + mu_b);
+//   y_l = gamma_l^{-1}/N_t DFT(w)_l, real part -> mode a, imaginary part -> mode b.
+// The z exchange reuses the engine buffer ([j][s], position 0 of a Rader length in
+// its own slot).  fgen and y may alias: a tile reads every level before it writes.
+template <int N, int E, int S, bool RADER, bool PAD = true>
+__device__ __forceinline__ void time_general_p2_body(const TimeArgs& a, long long wg, c64* lds) {
+  static_assert(S >= 1, "time kernel needs N <= 2048");
+  using L = P2Layout<N, E, S, true, PAD>;
+  using M = TimeLds<N, E, L, RADER>;
+  static_assert((size_t)N * S <= L::lds_elems(), "z exchange fits the engine buffer");
+  const int Nt = a.Nt;
+  const M sh(lds, Nt);
+  c64* gam = sh.extra();
+  c64* side = gam + Nt;   // S: z_0 of a Rader length
+  double* mus = reinterpret_cast<double*>(side + S);  // 2 S
+  const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
+  for (int j = t; j < Nt; j += L::T) {
+    sh.dt[j] = a.tabs[j];
+    sh.gi[j] = a.tabs[Nt + j];
+    gam[j] = a.tabs[2 * Nt + j];
   }
-  p2_fft<N, E, L>(v, s, u, buf, tw);
-  // padded rows (pitch > 0): the pair is one aligned 16-byte store; a pair whose
-  // second mode is past the row end writes that value into the row padding
+  sh.load_rader(a.fft, t, L::T);
+  const auto tw = p2_twiddles<N, M::TWM, E>(a.fft, sh.twl, t, L::T, u);
+  const TimeTile tile(a, wg, S, s);
+  if (u == 0) {
+    mus[2 * s] = tile.oka ? mode_mu(tile.ka, a.d, a.m, a.mu1d) : 0.0;
+    mus[2 * s + 1] = tile.okb ? mode_mu(tile.ka + 1, a.d, a.m, a.mu1d) : 0.0;
+  }
+  __syncthreads();
+
   const bool pair = a.pitch > 0;
-  auto store = [&](int l, c64 X) {
-    const c64 yv = cmul(gi[l], X);
-    double* yl = a.y + (long long)l * a.ystride;
+  auto load = [&](int j, int) -> c64 {
+    const double* fl = a.fgen + (long long)j * a.ystride;
+    c64 f = {0.0, 0.0};
     if (pair) {
-      if (oka) *reinterpret_cast<c64*>(yl + oa) = yv;
+      if (tile.oka) f = *reinterpret_cast<const c64*>(fl + tile.oa);
+      if (!tile.okb) f.im = 0.0;  // row padding
     } else {
-      if (oka) yl[oa] = yv.re;
-      if (okb) yl[oa + 1] = yv.im;
+      if (tile.oka) f.re = fl[tile.oa];
+      if (tile.okb) f.im = fl[tile.oa + 1];
+    }
+    return cconj(cmul(gam[j], f));
+  };
+  auto zslot = [&](int j) -> c64& {
+    if constexpr (RADER) return j == 0 ? side[s] : sh.buf[(size_t)(j - 1) * S + s];
+    else return sh.buf[(size_t)j * S + s];
+  };
+  c64 zk[E], z0 = {0.0, 0.0};
+  int jk[E];
+  auto keep = [&](int j, c64 X, int e) {
+    if (e < 0) z0 = X;
+    else {
+      zk[e] = X;
+      jk[e] = j;
     }
   };
-  if constexpr (RADER) {
-    const c64 x0 = input(0);
-    const c64 sum = v[0];  // position 0 on lane u == 0: sum_{j>=1} x_j
+  p2_time_dft<N, E, L, RADER>(load, keep, s, u, sh.buf, tw, sh.ks, sh.gfw, sh.gbw);
+  __syncthreads();  // the engine buffer is free: z = conj X, natural order
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = cconj(cmul(v[e], ks[p2_out_pos<N, E>(u, e)]));
-    p2_out_to_in<N, E, L>(v, s, u, buf);
-    p2_fft<N, E, L>(v, s, u, buf, tw);
+  for (int e = 0; e < E; ++e) zslot(jk[e]) = cconj(zk[e]);
+  if (RADER && u == 0) zslot(0) = cconj(z0);
+  __syncthreads();
+  const double mua = mus[2 * s], mub = mus[2 * s + 1];
+  auto wfun = [&](int j) -> c64 {
+    const c64 zj = zslot(j);
+    const c64 zr = cconj(zslot(Nt - 1 - j));
+    const c64 za = {0.5 * (zj.re + zr.re), 0.5 * (zj.im + zr.im)};
+    const c64 zb = {0.5 * (zj.im - zr.im), -0.5 * (zj.re - zr.re)};
+    const c64 z = sh.dt[j];
+    const double xa = z.re + mua, xb = z.re + mub;
+    const double qa = recip_nr(xa * xa + z.im * z.im), qb = recip_nr(xb * xb + z.im * z.im);
+    const c64 wa = {(za.re * xa + za.im * z.im) * qa, (za.im * xa - za.re * z.im) * qa};
+    const c64 wb = {(zb.re * xb + zb.im * z.im) * qb, (zb.im * xb - zb.re * z.im) * qb};
+    return {wa.re - wb.im, wa.im + wb.re};
+  };
+  // the second transform writes the engine buffer: gather this lane's inputs first
+  c64 w[E], w0 = {0.0, 0.0};
 #pragma unroll
-    for (int e = 0; e < E; ++e) store(gbw[p2_out_pos<N, E>(u, e)], cadd(x0, cconj(v[e])));
-    if (u == 0) store(0, cadd(x0, sum));
-  } else {
-#pragma unroll
-    for (int e = 0; e < E; ++e) store(p2_out_pos<N, E>(u, e), v[e]);
-  }
+  for (int e = 0; e < E; ++e) w[e] = wfun(RADER ? sh.gfw[p2_in_pos<N, E, 0>(u, e)] : p2_in_pos<N, E, 0>(u, e));
+  if constexpr (RADER) w0 = wfun(0);
+  __syncthreads();
+  auto winput = [&](int, int e) -> c64 { return e < 0 ? w0 : w[e]; };
+  auto emit = [&](int l, c64 X, int) { tile.store(a, l, cmul(sh.gi[l], X)); };
+  p2_time_dft<N, E, L, RADER>(winput, emit, s, u, sh.buf, tw, sh.ks, sh.gfw, sh.gbw);
 }
 
 }  // namespace qbvm

@@ -244,6 +244,7 @@ struct qbvm_plan_s {
   const FftTables* sfft = nullptr;  // length 2(m+1)
   int S_time = 1, S_dst = 1;
   int var_rows = 5, var_cols = 6, var_time = 4;  // set per transform length in create_plan
+  int var_gen = 1;                                // time kernel of the general right-hand side
   double* mu1d = nullptr;
   double* ghat = nullptr;
   double* yrow = nullptr;
@@ -387,6 +388,8 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
       p->var_time = 1;
       pick(3, p->Nt, p->var_time);
     }
+    p->var_gen = 1;
+    pick(4, p->tfft->dev.p2, p->var_gen);
   }
   // eigenvalues of the 1D three-point stencil: (4/h^2) sin^2(k pi/(2(m+1)))
   std::vector<double> mu(p->m);
@@ -648,20 +651,30 @@ int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f
   int rc = check_alpha(alpha, variant);
   if (rc) return rc;
   const sched::Geom G = geom(p);
-  const auto t = sched::time_general_step(G, y, y, p->tabs);
-  if (t.lds > 160 * 1024) return set_error(QBVM_EUNSUPPORTED, "time transform too long for the general solve");
-  // sine transform of every level of f into y
-  rc = run_dst(p, f, y, p->Nt, false);
-  if (rc) return rc;
+  auto gs = sched::general_schedule(G, f, y, p->W, p->tabs, p->var_gen);
+  if (gs.time.lds > 160 * 1024) return set_error(QBVM_EUNSUPPORTED, "time transform too long for the general solve");
   const TabJob job{p->tabs, p->Nt, variant, p->tau, alpha, nullptr, 1};
-  HIP_TRY(launch_tab_job(job, p->stream));
+  const bool side_job = gs.in.back().args.fft.p2 != 0;  // the tables as side work of the last input pass
+  if (side_job) gs.in.back().args.tab = job;
+  const double elems = (double)p->Nt * p->nmodes;
+  auto passes = [&](const std::vector<sched::Launch<DstArgs>>& v) -> int {
+    for (const auto& L : v) {
+      const int role = L.args.inner == 1 ? 1 : 2;
+      ProfScope ps(role == 1 ? "dst_rows" : "dst_cols", p->stream, 16.0 * elems,
+                   0.5 * (double)L.args.outer * L.args.inner * fft_flops(L.args.fft), nullptr);
+      HIP_TRY(launch_dst(L.args, L.nwg, L.args.threads, L.lds, p->stream, nullptr, role));
+    }
+    return QBVM_OK;
+  };
+  rc = passes(gs.in);
+  if (rc) return rc;
+  if (!side_job) HIP_TRY(launch_tab_job(job, p->stream));
   {
-    const double nm = (double)p->nmodes;
-    ProfScope ps("time_general", p->stream, 16.0 * nm * p->Nt,
-                 nm * (fft_flops(p->tfft->dev) + 40.0 * p->Nt), nullptr);
-    HIP_TRY(launch_time_general(t.args, t.nwg, t.lds, p->stream));
+    ProfScope ps("time_general", p->stream, 16.0 * elems,
+                 (double)p->nmodes * (fft_flops(p->tfft->dev) + 40.0 * p->Nt), nullptr);
+    HIP_TRY(launch_time_general(gs.time.args, gs.time.nwg, gs.time.lds, p->stream));
   }
-  return run_dst(p, y, y, p->Nt, false);
+  return passes(gs.out);
 }
 
 int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_delta, double* D_out) {
@@ -889,8 +902,9 @@ int time_min_ms(hipStream_t s, F launch, double* out_ms) {
 
 }  // namespace
 
-// rows variants 0, 1, 3 .. 7; columns the same; time variants 0 .. kTimeVariants2 - 1
-constexpr int kAutotuneTimings = 14 + p2sz::kTimeVariants2;
+// rows variants 0, 1, 3 .. 7; columns the same; time variants 0 .. kTimeVariants2 - 1;
+// general right-hand-side time variants 0 .. kTimeVariants2 - 1
+constexpr int kAutotuneTimings = 14 + 2 * p2sz::kTimeVariants2;
 constexpr double kKeepMargin = 1.03;
 
 extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
@@ -961,6 +975,31 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
     const double tcur = (p->var_time >= 0 && p->var_time < p2sz::kTimeVariants2) ? ms[14 + p->var_time] : -1.0;
     if (bestv >= 0 && !(tcur > 0 && tcur <= kKeepMargin * best)) p->var_time = bestv;
   }
+  const sched::Geom G0 = geom(p);
+  if (p->W && sched::use_padded_general(G0)) {
+    // general right-hand-side time kernel in place on W, tables of one solve
+    HIP_TRY(launch_tab_job(TabJob{p->tabs, p->Nt, QBVM_PQ, p->tau, 1e-3, nullptr, 1}, p->stream));
+    constexpr int o = 14 + p2sz::kTimeVariants2;
+    double best = 1e30;
+    int bestv = -1;
+    for (int V = 0; V < p2sz::kTimeVariants2; ++V) {
+      if (!p2sz::time_general_valid(Nt2, V)) continue;
+      const auto gs = sched::general_schedule(G0, scratch, scratch, p->W, p->tabs, V);
+      double tm = 0;
+      const int rc = time_min_ms(p->stream, [&]() -> int {
+        HIP_TRY(launch_time_general(gs.time.args, gs.time.nwg, gs.time.lds, p->stream));
+        return QBVM_OK;
+      }, &tm);
+      if (rc) return rc;
+      ms[o + V] = tm;
+      if (tm < best) {
+        best = tm;
+        bestv = V;
+      }
+    }
+    const double tcur = p2sz::time_general_valid(Nt2, p->var_gen) ? ms[o + p->var_gen] : -1.0;
+    if (bestv >= 0 && !(tcur > 0 && tcur <= kKeepMargin * best)) p->var_gen = bestv;
+  }
   HIP_TRY(hipStreamSynchronize(p->stream));
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -970,6 +1009,7 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
     }
     if (Nt2 && p->d >= 2) g_tuned[std::make_tuple(p->device, 2, Nt2)] = p->var_time;
     if (gt && p->d >= 2) g_tuned[std::make_tuple(p->device, 3, p->Nt)] = p->var_time;
+    if (p->W && sched::use_padded_general(G0)) g_tuned[std::make_tuple(p->device, 4, Nt2)] = p->var_gen;
   }
   if (ms_out)
     for (int i = 0; i < kAutotuneTimings; ++i) ms_out[i] = ms[i];

@@ -143,7 +143,40 @@ static const void* time_fn_n(int V, bool rader) {
     default: return nullptr;                           \
   }
 
+// general right-hand side; a Rader length N + 1 is prime only at N = 256 in this range
+template <int N, int V, bool RADER>
+__global__ __launch_bounds__(p2sz::time_T(V)) void k_time_general_p2(TimeArgs a) {
+  extern __shared__ c64 lds[];
+  time_general_p2_body<N, p2sz::time_E(V), p2sz::time_S(N, V), RADER, p2sz::time_pad(V)>(a, blockIdx.x, lds);
+}
+
+template <int N, int V>
+static const void* general_fn_nv(bool rader) {
+  if constexpr (p2sz::time_general_valid(N, V)) {
+    if constexpr (N == 256) {
+      if (rader) return (const void*)&k_time_general_p2<N, V, true>;
+    }
+    return rader ? nullptr : (const void*)&k_time_general_p2<N, V, false>;
+  } else {
+    return nullptr;
+  }
+}
+
+template <int N>
+static const void* general_fn_n(int V, bool rader) {
+  switch (V) {
+    case 0: return general_fn_nv<N, 0>(rader);
+    case 1: return general_fn_nv<N, 1>(rader);
+    case 2: return general_fn_nv<N, 2>(rader);
+    case 3: return general_fn_nv<N, 3>(rader);
+    case 4: return general_fn_nv<N, 4>(rader);
+    case 5: return general_fn_nv<N, 5>(rader);
+    default: return nullptr;
+  }
+}
+
 static const void* dst_p2_fn(int N, int V, bool cols, bool vec2) { QBVM_P2_SWITCH(N, dst_fn_n, V, cols, vec2) }
+static const void* general_p2_fn(int N, int V, bool rader) { QBVM_P2_SWITCH(N, general_fn_n, V, rader) }
 static const void* time_p2_fn(int N, int V, bool rader) { QBVM_P2_SWITCH(N, time_fn_n, V, rader) }
 
 // ROLE only separates the kernel symbols (0: transform of g_delta, 1: rows of the
@@ -728,7 +761,11 @@ hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds
 
 hipError_t launch_time_general(const TimeArgs& a, long long nwg, size_t lds, hipStream_t s) {
   const void* f = a.fft.wide ? (const void*)&k_time_general<true> : (const void*)&k_time_general<false>;
-  return enqueue1(f, dim3((unsigned)nwg), dim3(256), lds, s, a, nullptr);
+  if (a.fft.p2) {
+    f = general_p2_fn(a.fft.p2, a.var, a.fft.kind == kRader);
+    if (!f) return hipErrorInvalidValue;
+  }
+  return enqueue1(f, dim3((unsigned)nwg), dim3(a.threads), lds, s, a, nullptr);
 }
 
 hipError_t launch_tab_job(const TabJob& t, hipStream_t s) {

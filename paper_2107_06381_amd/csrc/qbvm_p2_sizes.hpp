@@ -77,6 +77,15 @@ constexpr size_t time_lds(int N, int V, int Nt) {
          sizeof(int) * 2 * (size_t)N;
 }
 
+// general right-hand side: the same, plus gamma_t, the z_0 slot of a Rader length and
+// the two mode eigenvalues of each signal
+constexpr size_t time_general_lds(int N, int V, int Nt) {
+  return time_lds(N, V, Nt) + sizeof(c64) * ((size_t)Nt + (size_t)time_S(N, V)) + sizeof(double) * 2 * (size_t)time_S(N, V);
+}
+constexpr bool time_general_valid(int N, int V) {
+  return time_valid(N, V) && time_general_lds(N, V, N + 1) <= 160 * 1024;
+}
+
 // Columns pass whose two columns per signal form aligned 16-byte pairs: padded
 // rows (colmod > 0) and even strides, 16-byte aligned buffers.
 inline bool dst_pairs_aligned(const DstArgs& a) {

@@ -137,8 +137,7 @@ inline Launch<DstArgs> dst_pass_custom(const Geom& g, const double* in, double* 
 
 // Padded-pipeline sine passes over all levels: strided axes in place on W, then
 // the x_1 pass W -> y.
-inline std::vector<Launch<DstArgs>> padded_passes(const Geom& g, double* W, double* y) {
-  std::vector<Launch<DstArgs>> v;
+inline void strided_passes(const Geom& g, double* W, std::vector<Launch<DstArgs>>& v) {
   const int m = g.m;
   const long long P1 = padded_pitch(m);
   long long kstride = P1;  // axis 1 (x_2)
@@ -149,7 +148,13 @@ inline std::vector<Launch<DstArgs>> padded_passes(const Geom& g, double* W, doub
     kstride *= m;
     blocks /= m;
   }
-  v.push_back(dst_pass_custom(g, W, y, (long long)g.Nt * (g.nmodes / m), 1, P1, m, 0, 0, 0, 0, g.var_rows));
+}
+inline std::vector<Launch<DstArgs>> padded_passes(const Geom& g, double* W, double* y) {
+  std::vector<Launch<DstArgs>> v;
+  strided_passes(g, W, v);
+  const int m = g.m;
+  v.push_back(dst_pass_custom(g, W, y, (long long)g.Nt * (g.nmodes / m), 1, padded_pitch(m), m, 0, 0, 0, 0,
+                              g.var_rows));
   return v;
 }
 
@@ -237,6 +242,52 @@ inline Launch<TimeArgs> time_general_step(const Geom& g, const double* fgen, dou
   const size_t lds = sizeof(c64) * ((size_t)t.S * g.tfft.nc + (size_t)t.S * g.Nt + 2 * (size_t)t.S) +
                      sizeof(double) * 2 * (size_t)t.S;
   return {t, (g.nmodes + 2LL * t.S - 1) / (2LL * t.S), lds};
+}
+
+// General right-hand side, every level: sine transform of f, time kernel, sine
+// transform back.  Padded (d >= 2, power-of-two sine and time lengths, W given): the
+// x_1 pass f -> W (padded rows), the strided passes and the time kernel in W, then the
+// padded output passes W -> y.  Otherwise the passes run in y and the generic time
+// kernel between them.  tabs: [d_j/tau | gamma_l^{-1}/N_t | gamma_t], filled by a job
+// attached to the last input pass (padded) or by a launch of its own.
+inline bool use_padded_general(const Geom& g) {
+  return g.d >= 2 && g.sfft.p2 && g.tfft.p2 && p2sz::time_general_valid(g.tfft.p2, 0);
+}
+struct GeneralSchedule {
+  bool padded = false;
+  std::vector<Launch<DstArgs>> in, out;
+  Launch<TimeArgs> time;
+};
+inline GeneralSchedule general_schedule(const Geom& g, const double* f, double* y, double* W, const c64* tabs,
+                                        int var_gen) {
+  GeneralSchedule gs;
+  if (W && use_padded_general(g)) {
+    gs.padded = true;
+    const int m = g.m;
+    const long long P1 = padded_pitch(m);
+    gs.in.push_back(dst_pass_custom(g, f, W, (long long)g.Nt * (g.nmodes / m), 1, m, P1, 0, 0, 0, 0, g.var_rows));
+    strided_passes(g, W, gs.in);
+    const int N = g.tfft.p2;
+    const int V = p2sz::time_general_valid(N, var_gen) ? var_gen : 0;
+    auto t = time_general_step(g, W, W, tabs);
+    t.args.fft = g.tfft;
+    t.args.var = V;
+    t.args.S = p2sz::time_S(N, V);
+    t.args.threads = p2sz::time_T(V);
+    t.args.pitch = P1;
+    const long long rows = g.nmodes / m;
+    t.args.ystride = rows * P1;
+    t.args.tiles_per_row = (int)((m + 2LL * t.args.S - 1) / (2LL * t.args.S));
+    t.nwg = rows * t.args.tiles_per_row;
+    t.lds = p2sz::time_general_lds(N, V, g.Nt);
+    gs.time = t;
+    gs.out = padded_passes(g, W, y);
+  } else {
+    gs.in = dst_passes(g, f, y, g.Nt, false);
+    gs.time = time_general_step(g, y, y, tabs);
+    gs.out = dst_passes(g, y, y, g.Nt, false);
+  }
+  return gs;
 }
 
 inline ThomasArgs thomas_step(const Geom& g, SolveScalars sc, const double* alpha_dev, int variant,

@@ -172,11 +172,11 @@ class Plan:
 
     def autotune(self) -> dict:
         """Time the kernel variants on this plan's shape and keep the fastest."""
-        ms = (ctypes.c_double * 20)()
+        ms = (ctypes.c_double * 26)()
         _check(self.L_.qbvm_plan_autotune(self._h, ms))
         v = [round(x, 5) for x in ms]
         return {"ms_rows_v0134567": v[0:7], "ms_cols_v0134567": v[7:14], "ms_time_v012345": v[14:20],
-                "variants": self.variants()}
+                "ms_general_v012345": v[20:26], "variants": self.variants()}
 
     def variants(self):
         r, c, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -4,7 +4,7 @@
 //   kernels_cpu fft   n S in.bin out.bin          (S signals, signal-major complex)
 //   kernels_cpu solve d m n L T alpha variant in.bin out.bin [var_rows var_cols var_time [padded]]
 //   kernels_cpu dst   d m batch in.bin out.bin [var_rows var_cols input]
-//   kernels_cpu general d m n L T alpha variant f.bin out.bin   (general right-hand side)
+//   kernels_cpu general d m n L T alpha variant f.bin out.bin [padded var_gen]   (general right-hand side)
 #include "hip_cpu_shim.hpp"
 
 #include <cstdio>
@@ -226,6 +226,45 @@ static void run_time_fast(const Launch<TimeArgs>& t) {
   P2_SWITCH(A.fft.p2, time_p2_n, t)
 }
 
+template <int N, int V>
+static void general_p2_nv(const Launch<TimeArgs>& t) {
+  if constexpr (p2sz::time_general_valid(N, V)) {
+    const TimeArgs& A = t.args;
+    constexpr int E = p2sz::time_E(V), S = p2sz::time_S(N, V);
+    constexpr bool PAD = p2sz::time_pad(V);
+    if (A.threads != p2sz::time_T(V)) exit(19);
+    if constexpr (N == 256) {
+      if (A.fft.kind == kRader) {
+        run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_general_p2_body<N, E, S, true, PAD>(A, wg, l); });
+        return;
+      }
+    }
+    if (A.fft.kind == kRader) exit(13);
+    run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_general_p2_body<N, E, S, false, PAD>(A, wg, l); });
+  } else {
+    exit(13);
+  }
+}
+
+template <int N>
+static void general_p2_n(const Launch<TimeArgs>& t) {
+  switch (t.args.var) {
+    case 0: general_p2_nv<N, 0>(t); break;
+    case 1: general_p2_nv<N, 1>(t); break;
+    case 2: general_p2_nv<N, 2>(t); break;
+    case 3: general_p2_nv<N, 3>(t); break;
+    case 4: general_p2_nv<N, 4>(t); break;
+    case 5: general_p2_nv<N, 5>(t); break;
+    default: exit(14);
+  }
+}
+
+static void run_dst_generic(const Launch<DstArgs>& Lz) {
+  const DstArgs& A = Lz.args;
+  if (A.fft.wide) run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_body<true>(A, wg, l); });
+  else run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_body<false>(A, wg, l); });
+}
+
 static void run_dst(const sched::Geom& g, const double* in, double* out, long long batch, bool input,
                     const TabJob* tab = nullptr) {
   auto passes = sched::dst_passes(g, in, out, batch, input);
@@ -289,10 +328,12 @@ int main(int argc, char** argv) {
     delete[] out;
     return 0;
   }
-  if (cmd == "general" && argc == 11) {
+  if (cmd == "general" && (argc == 11 || argc == 13)) {
     const int d = atoi(argv[2]), m = atoi(argv[3]), n = atoi(argv[4]);
     const double L = atof(argv[5]), T = atof(argv[6]), alpha = atof(argv[7]);
     const int variant = atoi(argv[8]);
+    const bool want_pad = argc == 13 && atoi(argv[11]) != 0;
+    const int var_gen = argc == 13 ? atoi(argv[12]) : 0;
     Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1));
     const double h = L / (m + 1);
     std::vector<double> mu(m);
@@ -307,18 +348,47 @@ int main(int argc, char** argv) {
     double* y = new double[ny];
     double* f = new double[ny];
     std::memcpy(f, raw.data(), raw.size());
-    run_dst(g, f, y, g.Nt, false);
+    double* W = nullptr;
+    if (want_pad) {
+      if (!sched::use_padded_general(g)) return 17;
+      W = new double[sched::padded_elems(g)];
+      for (long long i = 0; i < sched::padded_elems(g); ++i) W[i] = std::nan("");  // pad slots must not leak
+    }
     std::vector<c64> tabs(3 * (size_t)g.Nt, c64{std::nan(""), std::nan("")});
+    auto gs = sched::general_schedule(g, f, y, W, tabs.data(), var_gen);
+    if (gs.padded != want_pad) return 18;
+    if (gs.time.lds > 160 * 1024) return 16;
     const TabJob job{tabs.data(), g.Nt, variant, g.tau, alpha, nullptr, 1};
-    tab_job_run(job, 0, 1);
-    const auto t = sched::time_general_step(g, y, y, tabs.data());
-    if (t.lds > 160 * 1024) return 16;
-    if (t.args.fft.wide) run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_general_body<true>(t.args, wg, l); });
-    else run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_general_body<false>(t.args, wg, l); });
-    run_dst(g, y, y, g.Nt, false);
+    // the host attaches the tables to the last input pass when it is a power-of-two kernel
+    const bool side_job = gs.in.back().args.fft.p2 != 0;
+    if (side_job) gs.in.back().args.tab = job;
+    for (const auto& Lz : gs.in) {
+      if (Lz.args.fft.p2) {
+        P2_SWITCH(Lz.args.fft.p2, dst_p2_n, Lz)
+      } else {
+        run_dst_generic(Lz);
+      }
+    }
+    if (!side_job) tab_job_run(job, 0, 1);
+    const auto& t = gs.time;
+    if (t.args.fft.p2) {
+      P2_SWITCH(t.args.fft.p2, general_p2_n, t)
+    } else if (t.args.fft.wide) {
+      run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_general_body<true>(t.args, wg, l); });
+    } else {
+      run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time_general_body<false>(t.args, wg, l); });
+    }
+    for (const auto& Lz : gs.out) {
+      if (Lz.args.fft.p2) {
+        P2_SWITCH(Lz.args.fft.p2, dst_p2_n, Lz)
+      } else {
+        run_dst_generic(Lz);
+      }
+    }
     write_file(argv[10], y, ny * sizeof(double));
     delete[] y;
     delete[] f;
+    delete[] W;
     return 0;
   }
   if (cmd == "solve" && (argc == 11 || argc == 14 || argc == 15)) {

@@ -125,15 +125,27 @@ def test_solve_schedule_vs_oracle(exe, tmp_path, case, kv):
     assert ok, r
 
 
-@pytest.mark.parametrize("d,m,n,alpha,variant", [(1, 17, 12, 1e-3, 0), (2, 15, 16, 1e-4, 1), (2, 20, 11, 1e-2, 0),
-                                                 (3, 6, 7, 1e-5, 0), (2, 63, 128, 1e-4, 0), (1, 9, 1, 0.3, 1)])
-def test_general_rhs_vs_oracle(exe, tmp_path, d, m, n, alpha, variant):
+GENERAL_CASES = [
+    # generic engine, sine passes in y: Stockham, Rader (N_t = 17), Good-Thomas size 129, N_t = 2
+    (1, 17, 12, 1e-3, 0, 0, 0), (2, 15, 16, 1e-4, 1, 0, 0), (2, 20, 11, 1e-2, 0, 0, 0), (3, 6, 7, 1e-5, 0, 0, 0),
+    (2, 63, 128, 1e-4, 0, 0, 0), (1, 9, 1, 0.3, 1, 0, 0),
+    # padded pipeline, compile-time engine: N_t = 64, 128, 256 and 257 (Rader), variants 0 .. 5
+    (2, 31, 63, 1e-4, 0, 1, 0), (2, 31, 127, 1e-5, 0, 1, 1), (2, 31, 256, 1e-6, 0, 1, 2), (2, 31, 255, 1e-4, 0, 1, 3),
+    (2, 63, 63, 1e-4, 1, 1, 4), (2, 31, 256, 1e-3, 1, 1, 5),
+] + ([(3, 31, 63, 1e-3, 0, 1, 2), (2, 63, 255, 1e-4, 0, 1, 3)] if FULL else [])
+
+
+@pytest.mark.parametrize("d,m,n,alpha,variant,padded,vg", GENERAL_CASES,
+                         ids=[f"{c[0]}d-m{c[1]}-n{c[2]}-{'pad-v' + str(c[6]) if c[5] else 'generic'}"
+                              for c in GENERAL_CASES])
+def test_general_rhs_vs_oracle(exe, tmp_path, d, m, n, alpha, variant, padded, vg):
     """General right-hand side (every level): Gamma-scaled time transform per mode,
-    separation of the two packed modes, shifted division, inverse transform."""
+    separation of the two packed modes, shifted division, inverse transform; generic
+    kernels in place, or the padded pipeline with the compile-time time kernel."""
     f = np.random.default_rng(d * 10 + m + n).standard_normal((n + 1,) + (m,) * d)
     fi, fo = tmp_path / "f.bin", tmp_path / "o.bin"
     f.tofile(fi)
-    _run(exe, ["general", d, m, n, "1.0", "0.8", repr(alpha), variant, fi, fo], tmp_path)
+    _run(exe, ["general", d, m, n, "1.0", "0.8", repr(alpha), variant, fi, fo, padded, vg], tmp_path)
     y = np.fromfile(fo).reshape(f.shape)
     yc = O.closed_form_general(f, d, m, n, 1.0, 0.8, alpha, variant)
     assert np.linalg.norm(y - yc) <= 1e-10 * np.linalg.norm(yc)
