@@ -131,8 +131,17 @@ long long qbvm_plan_workspace_bytes(qbvm_plan_t p);
  * 6, 7; time variants 0..5; general right-hand-side time variants 0..5. */
 int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out);
 
-/* The kernel variants a plan uses (HOST outputs): sine rows, sine columns, time. */
-int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var_time);
+/* The kernel variants a plan uses (HOST outputs, each may be NULL): sine rows, sine
+ * columns, time, general right-hand-side time. */
+int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var_time, int* var_general);
+
+/* Select kernel variants by hand (an addition, for tests and tuning outside the
+ * autotuner): -1 keeps the current one.  A variant must exist for the plan's
+ * transform lengths (sine variants 0..7 for a power-of-two sine length, time
+ * variants 0..5 for a power-of-two or Rader length and 0..1 for Good-Thomas,
+ * general variants 0..5 where the padded general pipeline runs), else QBVM_EINVAL and
+ * nothing changes.  Shapes that use the generic kernels accept only -1. */
+int qbvm_plan_set_variants(qbvm_plan_t p, int var_rows, int var_cols, int var_time, int var_general);
 
 /* -------------------------------------------------------------- solving ---- */
 

@@ -1016,11 +1016,31 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
   return QBVM_OK;
 }
 
-extern "C" int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var_time) {
+extern "C" int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var_time,
+                                      int* var_general) {
   if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
   if (var_rows) *var_rows = p->var_rows;
   if (var_cols) *var_cols = p->var_cols;
   if (var_time) *var_time = p->var_time;
+  if (var_general) *var_general = p->var_gen;
+  return QBVM_OK;
+}
+
+extern "C" int qbvm_plan_set_variants(qbvm_plan_t p, int var_rows, int var_cols, int var_time, int var_general) {
+  if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
+  const int Ns = p->sfft->dev.p2, Nt2 = p->tfft->dev.p2;
+  const bool gt = p->tfft->dev.gtA != 0;
+  auto dst_ok = [&](int V) { return V == -1 || (Ns && p->d >= 2 && p2sz::dst_valid(Ns, V)); };
+  const bool time_ok = var_time == -1 || (p->d >= 2 && ((Nt2 && p2sz::time_valid(Nt2, var_time)) ||
+                                                        (gt && (var_time == 0 || var_time == 1))));
+  const bool gen_ok = var_general == -1 ||
+                      (p->W && sched::use_padded_general(geom(p)) && p2sz::time_general_valid(Nt2, var_general));
+  if (!dst_ok(var_rows) || !dst_ok(var_cols) || !time_ok || !gen_ok)
+    return set_error(QBVM_EINVAL, "kernel variant not available for this plan's transform lengths");
+  if (var_rows != -1) p->var_rows = var_rows;
+  if (var_cols != -1) p->var_cols = var_cols;
+  if (var_time != -1) p->var_time = var_time;
+  if (var_general != -1) p->var_gen = var_general;
   return QBVM_OK;
 }
 

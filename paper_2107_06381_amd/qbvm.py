@@ -32,6 +32,7 @@ EXPORTS = [
     "qbvm_mlp_forward", "qbvm_mlp_loss_grad", "qbvm_adam_step", "qbvm_strerror",
     "qbvm_last_error", "qbvm_version", "qbvm_profile_enable", "qbvm_profile_reset",
     "qbvm_profile_count", "qbvm_profile_get", "qbvm_plan_autotune", "qbvm_plan_get_variants",
+    "qbvm_plan_set_variants",
 ]
 
 
@@ -95,7 +96,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qbvm_last_error": (ctypes.c_char_p, []),
         "qbvm_version": (i, []),
         "qbvm_plan_autotune": (i, [vp, ctypes.POINTER(d)]),
-        "qbvm_plan_get_variants": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "qbvm_plan_get_variants": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
+                                       ctypes.POINTER(i)]),
+        "qbvm_plan_set_variants": (i, [vp, i, i, i, i]),
         "qbvm_profile_enable": (None, [i]),
         "qbvm_profile_reset": (None, []),
         "qbvm_profile_count": (i, []),
@@ -179,9 +182,14 @@ class Plan:
                 "ms_general_v012345": v[20:26], "variants": self.variants()}
 
     def variants(self):
-        r, c, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(self.L_.qbvm_plan_get_variants(self._h, ctypes.byref(r), ctypes.byref(c), ctypes.byref(t)))
-        return {"rows": r.value, "cols": c.value, "time": t.value}
+        r, c, t, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self.L_.qbvm_plan_get_variants(self._h, ctypes.byref(r), ctypes.byref(c), ctypes.byref(t),
+                                              ctypes.byref(g)))
+        return {"rows": r.value, "cols": c.value, "time": t.value, "general": g.value}
+
+    def set_variants(self, rows: int = -1, cols: int = -1, time: int = -1, general: int = -1):
+        """Select kernel variants by hand (-1 keeps the current one)."""
+        _check(self.L_.qbvm_plan_set_variants(self._h, int(rows), int(cols), int(time), int(general)))
 
     def out_shape(self, output: int):
         sp = (self.m,) * self.d

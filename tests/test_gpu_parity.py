@@ -188,10 +188,12 @@ def test_general_rhs_vs_oracle(d, m, n, alpha, variant):
         assert rel(y, ys) < TOL
 
 
-def test_general_rhs_rank_one_and_in_place():
-    """f = (f0, 0, ..., 0) reproduces qbvm_solve; y may be f itself."""
-    say("[case] general rhs rank one")
-    d, m, n, alpha = 2, 127, 128, 1e-4
+@pytest.mark.parametrize("m,n", [(127, 128), (255, 256)])
+def test_general_rhs_rank_one_and_in_place(m, n):
+    """f = (f0, 0, ..., 0) reproduces qbvm_solve; y may be f itself (generic kernels at
+    N_t = 129, the padded pipeline at N_t = 257)."""
+    say(f"[case] general rhs rank one m={m} n={n}")
+    d, alpha = 2, 1e-4
     g = np.random.default_rng(8).standard_normal((m, m))
     p = qbvm.Plan(d, m, n)
     f = O.rhs_allatonce(g, n, alpha, O.PQ, 1.0).reshape((n + 1, m, m))
@@ -200,6 +202,53 @@ def test_general_rhs_rank_one_and_in_place():
     p.solve_general(alpha, 0, fd, fd)  # in place
     torch.cuda.synchronize()
     assert rel(fd.cpu().numpy(), y1.cpu().numpy()) < 1e-11
+
+
+@pytest.mark.parametrize("d,m,n", [(2, 255, 256), (3, 63, 63)])
+def test_every_kernel_variant(d, m, n):
+    """Every sine-pass, time and general-time kernel variant, selected by hand, against
+    the oracle (the autotuner keeps one per role; the others must be right too)."""
+    say(f"[case] every variant d={d} m={m} n={n}")
+    rng = np.random.default_rng(21)
+    g = rng.standard_normal((m,) * d)
+    f = rng.standard_normal((n + 1,) + (m,) * d)
+    alpha = 1e-4
+    p = qbvm.Plan(d, m, n)
+    base = p.variants()
+    yc = O.closed_form(g, d, m, n, 1.0, 1.0, alpha, O.PQ)
+    ygc = O.closed_form_general(f, d, m, n, 1.0, 1.0, alpha, O.PQ)
+    gd, fd = to_dev(g), to_dev(f)
+    y = torch.empty((n + 1,) + (m,) * d, dtype=torch.float64, device="cuda:0")
+
+    def check(rhs_general, **kw):
+        p.set_variants(**kw)
+        assert all(p.variants()[k] == v for k, v in kw.items())
+        if rhs_general:
+            p.solve_general(alpha, qbvm.QBVM_PQ, fd, y)
+        else:
+            p.solve(alpha, qbvm.QBVM_PQ, gd, y)
+        torch.cuda.synchronize()
+        e = rel(y.cpu().numpy(), ygc if rhs_general else yc)
+        p.set_variants(**base)
+        assert e < TOL, (kw, e)
+
+    for V in range(8):
+        check(False, rows=V)
+        check(False, cols=V)
+        check(True, rows=V, cols=V)
+    for V in range(6):
+        check(False, time=V)
+        check(True, general=V)
+    for bad in (dict(rows=8), dict(cols=-2), dict(time=6), dict(general=6)):
+        with pytest.raises(qbvm.QbvmError):
+            p.set_variants(**bad)
+    assert p.variants() == base
+    p.close()
+    q = qbvm.Plan(2, 20, 11)  # generic kernels only
+    with pytest.raises(qbvm.QbvmError):
+        q.set_variants(rows=0)
+    q.set_variants()
+    q.close()
 
 
 def test_pq_pm_identity_and_determinism():
