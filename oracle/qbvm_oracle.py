@@ -24,6 +24,9 @@ What is computed, and from which passage:
   dense form for tiny sizes (``pint_three_step``), with the explicit
   omega-circulant eigen-decomposition C = V D V^{-1}, V = Gamma^{-1} F^*.
 * The residual of the all-at-once rows, matrix free (``residual``).
+* The same rows in 1D with a general tridiagonal spatial matrix A in place of
+  -Lap_h (Section 3.3: the operator enters only Step (b)): ``solve_splu_operator``
+  (SuperLU) and ``closed_form_operator`` (eigenbasis of A).
 * Discrepancy-principle quantities and the bisection used to label alpha, the
   spectral features of g_delta (``discrepancy``, ``bisect_alpha``, ``features``);
   these are additions not taken from the paper, see their docstrings.
@@ -246,6 +249,60 @@ def laplacian_matrix(d: int, m: int, L: float) -> sp.csr_matrix:
     cols = np.concatenate([np.arange(Nx), nb[:, 1]])
     vals = np.concatenate([np.full(Nx, -2.0 * d / h ** 2), np.full(nb.shape[0], 1.0 / h ** 2)])
     return sp.csr_matrix((vals, (rows, cols)), shape=(Nx, Nx))
+
+
+# ----------------------------------------------------------------------------
+# Another spatial operator (1D): Section 3.3 notes that the diagonalisation in time
+# is independent of the spatial operator, which enters only through Step (b).  A is
+# a general m x m tridiagonal matrix standing in for -Lap_h in every block row.
+# ----------------------------------------------------------------------------
+def tridiagonal_matrix(lower, diag, upper) -> sp.csr_matrix:
+    """A with A[i, i-1] = lower[i-1], A[i, i] = diag[i], A[i, i+1] = upper[i]."""
+    m = len(diag)
+    return sp.diags([np.asarray(lower, float), np.asarray(diag, float), np.asarray(upper, float)],
+                    [-1, 0, 1], shape=(m, m), format="csr")
+
+
+def assemble_allatonce_operator(A, n: int, T: float, alpha: float, variant: int) -> sp.csr_matrix:
+    """The rows of Sections 3.1/3.2 with A in place of -Lap_h:
+    t = 0: (I/tau + A) y^0 - (omega/tau) y^N = f0;  t >= 1: (I/tau + A) y^t - y^{t-1}/tau = 0."""
+    tau = T / n
+    Nt = n + 1
+    omega, _ = omega_and_scale(alpha, variant, tau)
+    Nx = A.shape[0]
+    Ix = sp.identity(Nx, format="csr")
+    It = sp.identity(Nt, format="csr")
+    back = sp.diags([np.ones(Nt - 1)], [-1], shape=(Nt, Nt), format="csr")   # (t, t-1)
+    corner = sp.csr_matrix(([1.0], ([0], [Nt - 1])), shape=(Nt, Nt))          # (0, N)
+    return (sp.kron(It, Ix / tau + A) - sp.kron(back, Ix) / tau - (omega / tau) * sp.kron(corner, Ix)).tocsr()
+
+
+def solve_splu_operator(g_delta, A, n: int, T: float, alpha: float, variant: int):
+    """O2 with the operator A: SuperLU on the assembled rows; (n+1, m) levels."""
+    M = assemble_allatonce_operator(A, n, T, alpha, variant).tocsc()
+    f = rhs_allatonce(np.asarray(g_delta, float), n, alpha, variant, T)
+    return spla.splu(M, permc_spec="COLAMD").solve(f).reshape(n + 1, -1)
+
+
+def closed_form_operator(g_delta, A, n: int, T: float, alpha: float, variant: int):
+    """O3 with the operator A: in the eigenbasis of A (A = U diag(lam) U^{-1}; LAPACK eigh
+    when A is symmetric, eig otherwise) every mode obeys the closed form of the Dirichlet
+    case with mu -> lam: y^t = r^t y^0, r = 1/(1 + tau lam),
+    y^0 = f0_hat / ((1/tau + lam) - (omega/tau) r^N).  Returns the real part."""
+    tau = T / n
+    omega, scale = omega_and_scale(alpha, variant, tau)
+    Ad = A.toarray() if sp.issparse(A) else np.asarray(A, float)
+    f0 = scale * np.ravel(np.asarray(g_delta, float))
+    if np.array_equal(Ad, Ad.T):
+        lam, U = np.linalg.eigh(Ad)
+        fh = U.T @ f0
+    else:
+        lam, U = np.linalg.eig(Ad)
+        fh = np.linalg.solve(U, f0.astype(complex))
+    r = 1.0 / (1.0 + tau * lam)
+    y0 = fh / ((1.0 / tau + lam) - (omega / tau) * r ** n)
+    levels = np.stack([U @ (r ** t * y0) for t in range(n + 1)], 0)
+    return np.real(levels)
 
 
 def pint_three_step(g_delta, d, m, n, L, T, alpha, variant):

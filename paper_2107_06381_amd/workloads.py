@@ -166,6 +166,28 @@ def sine_mode_instance(d: int, m: int, n: int, T: float, alpha: float, eps: floa
     return Instance(d, m, n, L, T, alpha, variant, g_delta, delta, z0, g, eps)
 
 
+def diffusion_operator_1d(m: int, rng: np.random.Generator, L: float = 1.0, contrast: float = 4.0,
+                          advection: float = 0.0):
+    """Input data for a 1D problem with another spatial operator: the three diagonals
+    (lower[m-1], diag[m], upper[m-1]) of the matrix A that stands in for -Lap_h.
+    A is -(kappa u')' + advection u' with Dirichlet ends on the m interior nodes:
+    kappa at the half points x_{i+1/2} is smooth and positive (log kappa a sum of
+    random low sine modes, max/min about `contrast`), the diffusion term in
+    conservative three-point form, the advection term upwinded (advection >= 0).
+    advection = 0 gives a symmetric A."""
+    h = L / (m + 1)
+    xh = (np.arange(m + 1) + 0.5) * h
+    k = np.arange(1, 5)
+    logk = (rng.standard_normal(4) / k) @ np.sin(np.outer(k, np.pi * xh / L))
+    span = float(np.ptp(logk))
+    logk *= (np.log(contrast) / span) if span > 0 else 0.0
+    kappa = np.exp(logk - logk.mean())
+    diag = (kappa[:-1] + kappa[1:]) / h ** 2 + advection / h
+    upper = -kappa[1:-1] / h ** 2
+    lower = -kappa[1:-1] / h ** 2 - advection / h
+    return np.ascontiguousarray(lower), np.ascontiguousarray(diag), np.ascontiguousarray(upper)
+
+
 def config_1d(seed: int = 0, m: int = 127, n: int = 128, alpha: float = 1e-3,
               eps: float = 0.01) -> Instance:
     """1D, (0,1), z0 = sin(pi x) + 0.5 sin(3 pi x), T=1, 1% relative Gaussian noise."""

@@ -382,3 +382,46 @@ def test_general_rhs_rank_one_is_the_solve():
     yg = O.closed_form_general(f, d, m, n, 1.0, 1.0, alpha, O.PQ)
     y = O.closed_form(g, d, m, n, 1.0, 1.0, alpha, O.PQ)
     assert np.linalg.norm(yg - y) <= 1e-11 * np.linalg.norm(y)
+
+
+# --------------------------------------------------------------------------
+# another spatial operator (1D): sparse LU of the assembled rows against the
+# eigenbasis closed form; the Dirichlet stencil reduces to the sine-basis form
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,alpha,variant,adv", [(17, 12, 1e-3, 0, 0.0), (40, 33, 1e-5, 1, 0.0),
+                                                   (25, 8, 1e-2, 0, 3.0), (9, 1, 0.3, 0, 0.0), (1, 4, 1e-2, 1, 0.0)])
+def test_operator_splu_vs_eigenbasis(m, n, alpha, variant, adv):
+    from paper_2107_06381_amd import workloads as W
+    rng = np.random.default_rng(m * 7 + n)
+    lo, di, up = W.diffusion_operator_1d(m, rng, advection=adv)
+    A = O.tridiagonal_matrix(lo, di, up)
+    g = rng.standard_normal(m)
+    ys = O.solve_splu_operator(g, A, n, 0.7, alpha, variant)
+    yc = O.closed_form_operator(g, A, n, 0.7, alpha, variant)
+    assert np.linalg.norm(ys - yc) <= 1e-9 * np.linalg.norm(ys)
+    M = O.assemble_allatonce_operator(A, n, 0.7, alpha, variant)
+    f = O.rhs_allatonce(g, n, alpha, variant, 0.7)
+    assert np.linalg.norm(M @ ys.ravel() - f) <= 1e-10 * np.linalg.norm(f)
+
+
+def test_operator_dirichlet_stencil_is_the_sine_form():
+    m, n, alpha, L, T = 31, 20, 1e-4, 1.0, 1.0
+    h = L / (m + 1)
+    off = np.full(m - 1, -1.0 / h ** 2)
+    A = O.tridiagonal_matrix(off, np.full(m, 2.0 / h ** 2), off)
+    g = np.random.default_rng(4).standard_normal(m)
+    for variant in (O.PQ, O.PM):
+        ye = O.closed_form_operator(g, A, n, T, alpha, variant)
+        ys = O.closed_form(g, 1, m, n, L, T, alpha, variant)
+        assert np.linalg.norm(ye - ys) <= 1e-10 * np.linalg.norm(ys)
+
+
+def test_diffusion_operator_input():
+    from paper_2107_06381_amd import workloads as W
+    lo, di, up = W.diffusion_operator_1d(50, np.random.default_rng(1))
+    assert np.all(di > 0) and np.all(lo < 0) and np.array_equal(lo, up)
+    # diagonally dominant, rows sum to the Dirichlet end terms only
+    rs = di.copy()
+    rs[1:] += lo
+    rs[:-1] += up
+    assert np.all(rs[1:-1] > -1e-9 * di[1:-1]) and np.all(np.abs(rs[1:-1]) <= 1e-9 * di[1:-1])
