@@ -264,6 +264,45 @@ def general_rhs_bench(steps: int = 20):
             "step_hbm_roofline_frac": round(sched_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
 
 
+def operator_1d_bench(steps: int = 20):
+    """1D solve with a variable-coefficient operator -(kappa u')' in place of -Lap_h
+    (Step (b) as a complex Thomas solve per shift) on the largest 1D grid: seconds per
+    solve and the kernel split."""
+    import numpy as np
+    import torch
+    from paper_2107_06381_amd import qbvm, workloads as W
+    m, n, alpha = 2047, 4095, 1e-4
+    rng = np.random.default_rng(17)
+    lo, di, up = W.diffusion_operator_1d(m, rng)
+    plan = qbvm.Plan(1, m, n, 1.0, 1.0)
+    plan.set_operator_1d(lo, di, up)
+    g = torch.from_numpy(rng.standard_normal(m)).to("cuda:0")
+    y = torch.empty((n + 1, m), dtype=torch.float64, device="cuda:0")
+    for _ in range(3):
+        plan.solve(alpha, qbvm.QBVM_PQ, g, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.solve(alpha, qbvm.QBVM_PQ, g, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    qbvm.profile_reset()
+    qbvm.profile_enable(True)
+    for _ in range(5):
+        plan.solve(alpha, qbvm.QBVM_PQ, g, y)
+    torch.cuda.synchronize()
+    rep = qbvm.profile_report()
+    qbvm.profile_enable(False)
+    plan.close()
+    kernels = {k: {"avg_us": round(r["total_ms"] / r["launches"] * 1e3, 1),
+                   "GBps": round(r["bytes"] / (r["total_ms"] * 1e-3) / 1e9, 1)} for k, r in rep.items()}
+    return {"workload": "1D m=2047, n=4095 (N_t=4096), variable kappa (contrast 4), alpha=1e-4, every level",
+            "ms_per_solve": round(ms, 4), "Munknowns_per_s": round(n * m / (ms * 1e-3) / 1e6, 1),
+            "kernels": kernels}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +314,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched section")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D solve section")
     ap.add_argument("--no-general", action="store_true", help="skip the general right-hand-side section")
+    ap.add_argument("--no-operator", action="store_true", help="skip the 1D variable-coefficient section")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for counter calibration)")
     ap.add_argument("--alpha-train", type=int, default=20000)
@@ -365,6 +405,7 @@ def main():
     alpha = None if args.no_alpha else alpha_choice_bench(args.alpha_train, args.alpha_test, 200, 3000)
     batched = None if args.no_batched else batched_bench()
     general = None if args.no_general else general_rhs_bench()
+    operator_1d = None if args.no_operator else operator_1d_bench()
     line = {
         "metric": "PinT solve Munknowns/s (n*m^d, FP64)",
         "value": round(value, 2),
@@ -389,6 +430,7 @@ def main():
         "alpha_choice": alpha,
         "batched": batched,
         "general_rhs": general,
+        "operator_1d": operator_1d,
         "parity_rel_err": parity,
         "cpu_baseline": cpu,
     }

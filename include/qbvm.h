@@ -151,6 +151,19 @@ int qbvm_plan_set_variants(qbvm_plan_t p, int var_rows, int var_cols, int var_ti
 int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta,
                double* y, int output);
 
+/* Another spatial operator (1D plans; Section 3.3 notes that the operator enters only
+ * Step (b)): every later qbvm_solve on this plan uses the tridiagonal matrix A in
+ * place of -Lap_h, A[i][i-1] = lower[i-1], A[i][i] = diag[i], A[i][i+1] = upper[i]
+ * (HOST arrays of m-1, m, m-1 doubles, copied; lower/upper may be NULL when m = 1),
+ * e.g. -(kappa u')' with variable kappa.  Step (b) is then a complex Thomas solve per
+ * shift d_j/tau without pivoting: d_j/tau I + A must not need pivoting (A diagonally
+ * dominant with positive diagonal, as diffusion operators are).  diag == NULL restores
+ * the Dirichlet stencil.  Synchronous (waits for the plan's stream).  While an
+ * operator is set, qbvm_solve_general, qbvm_discrepancy, qbvm_choose_alpha and
+ * qbvm_bisect_batched return QBVM_EUNSUPPORTED (they work in the sine basis).
+ * QBVM_EINVAL for d > 1 or non-finite entries. */
+int qbvm_plan_set_operator_1d(qbvm_plan_t p, const double* lower, const double* diag, const double* upper);
+
 /* Solve the all-at-once system of Sections 3.1/3.2 for a general right-hand side (an
  * addition beyond the paper's data: source terms, or one application of the PinT
  * system as a preconditioner).  f: DEVICE, (n+1) m^d doubles, one block per level,

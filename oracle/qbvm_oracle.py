@@ -301,8 +301,8 @@ def closed_form_operator(g_delta, A, n: int, T: float, alpha: float, variant: in
         fh = np.linalg.solve(U, f0.astype(complex))
     r = 1.0 / (1.0 + tau * lam)
     y0 = fh / ((1.0 / tau + lam) - (omega / tau) * r ** n)
-    levels = np.stack([U @ (r ** t * y0) for t in range(n + 1)], 0)
-    return np.real(levels)
+    modes = y0[:, None] * r[:, None] ** np.arange(n + 1)[None, :]   # [mode][t] = r^t y^0
+    return np.ascontiguousarray(np.real(U @ modes).T)
 
 
 def pint_three_step(g_delta, d, m, n, L, T, alpha, variant):

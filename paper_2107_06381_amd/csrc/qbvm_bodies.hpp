@@ -288,35 +288,142 @@ __device__ __forceinline__ void time_general_body(const TimeArgs& a, long long w
   }
 }
 
-// ============================================================= k_thomas ====
-// Step (b) in 1D: (d_j/tau + 2/h^2) s_i - (s_{i-1} + s_{i+1})/h^2 = f0_i for each shift j.
-__device__ __forceinline__ void thomas_body(const ThomasArgs& a, int j) {
-  const int Nt = a.Nt, m = a.m;
+// ============================================================= k_tri1d =====
+// Step (b) in 1D for each shift j: (d_j/tau I + A) s = f0 with A = -Lap_h (the
+// three-point Dirichlet stencil, 2/h^2 on the diagonal, -1/h^2 beside it) or a
+// tridiagonal operator given by the caller.  Row i reads l_i s_{i-1} + (d_j/tau + b_i) s_i
+// + u_i s_{i+1} = f0_i (l_0 = u_{m-1} = 0).
+//
+// Partition method with parallel cyclic reduction: the P lanes of a system each take
+// a chunk [lo, hi) of 2..8 consecutive rows (P = ceil(m/8), rows spread evenly).
+// Eliminating a chunk's interior rows, with its first and last unknowns F_p = s_lo and
+// L_p = s_{hi-1} kept as parameters, gives per chunk
+//   interior:  s_i + c_i s_{i+1} + a_i F_p = d_i           (downward sweep)
+//   first row: l_lo L_{p-1} + (b_lo + u_lo A) F_p + u_lo C L_p = f_lo - u_lo D
+//   last row:  -l_{hi-1} a' F_p + (b_{hi-1} - l_{hi-1} c') L_p + u_{hi-1} F_{p+1} = f_{hi-1} - l_{hi-1} d'
+// with (c', a', d') those of the last interior row and s_{lo+1} = D + C L_p + A F_p from
+// the upward recurrence.  In the order F_0, L_0, F_1, L_1, ... the 2P boundary equations
+// are tridiagonal; PCR solves them in LDS in ceil(log2 2P) steps, then each lane
+// recovers its interior rows.  No pivoting: the shifted operator must be diagonally
+// dominant enough for elimination without it (diffusion operators are).
+__device__ __forceinline__ c64 cdiv_nr(c64 a, c64 b) {
+  const double q = recip_nr(b.re * b.re + b.im * b.im);
+  return {(a.re * b.re + a.im * b.im) * q, (a.im * b.re - a.re * b.im) * q};
+}
+
+struct TriEq {
+  c64 lo, di, up, rh;
+};
+
+__device__ __forceinline__ void tri1d_body(const ThomasArgs& a, long long wg, c64* lds) {
+  const int Nt = a.Nt, m = a.m, P = a.P;
+  const int t = threadIdx.x, sl = t / P, p = t - sl * P;
+  const long long jl = wg * a.S + sl;
+  const bool live = sl < a.S && jl < Nt;
+  const int j = live ? (int)jl : 0;
   const SolveScalars sc = a.alpha_dev ? scalars_from_alpha(*a.alpha_dev, a.variant, a.tau) : a.sc;
   const double croot = exp(sc.logabsw / (double)Nt);
   const c64 z = shift_over_tau(j, Nt, croot, 1.0 / a.tau);
   const double ih2 = 1.0 / (a.h * a.h);
-  const c64 bdiag = {z.re + 2.0 * ih2, z.im};
-  const double off = -ih2;
-  // forward sweep
-  c64 cp = {0.0, 0.0}, dp = {0.0, 0.0};
-  for (int i = 0; i < m; ++i) {
-    const c64 den = {bdiag.re - off * cp.re, bdiag.im - off * cp.im};
-    const double q = 1.0 / (den.re * den.re + den.im * den.im);
-    const c64 inv = {den.re * q, -den.im * q};
-    const double r = sc.f0s * a.g[i];
-    cp = cscale(inv, off);
-    dp = cmul({r - off * dp.re, -off * dp.im}, inv);
-    a.cp[(long long)i * Nt + j] = cp;
-    a.s2[(long long)i * Nt + j] = dp;
+  const bool op = a.op_di != nullptr;
+  auto bdiag = [&](int i) -> c64 { return {z.re + (op ? a.op_di[i] : 2.0 * ih2), z.im}; };
+  auto lower = [&](int i) -> double { return i > 0 ? (op ? a.op_lo[i - 1] : -ih2) : 0.0; };
+  auto upper = [&](int i) -> double { return i + 1 < m ? (op ? a.op_up[i] : -ih2) : 0.0; };
+  auto rhs = [&](int i) -> double { return sc.f0s * a.g[i]; };
+  c64* out = a.s2 + jl * (long long)m;
+  if (m == 1) {  // one row, one lane: s = f0 / (d_j/tau + b)
+    if (live) out[0] = cdiv_nr({rhs(0), 0.0}, bdiag(0));
+    return;
   }
-  // back substitution
-  c64 x = dp;
-  for (int i = m - 2; i >= 0; --i) {
-    const c64 c = a.cp[(long long)i * Nt + j];
-    const c64 d = a.s2[(long long)i * Nt + j];
-    x = csub(d, cmul(c, x));
-    a.s2[(long long)i * Nt + j] = x;
+  const int lo = (int)((long long)p * m / P), hi = (int)((long long)(p + 1) * m / P);
+  const int ni = hi - lo - 2;  // interior rows, 0..6
+  // downward sweep over the interior, from the virtual row s_lo - F_p = 0
+  c64 cr[6], ar[6], dr[6];
+  c64 cpv = {0.0, 0.0}, apv = {-1.0, 0.0}, dpv = {0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (q < ni) {
+      const int i = lo + 1 + q;
+      const double l = lower(i);
+      const c64 den = {bdiag(i).re - l * cpv.re, bdiag(i).im - l * cpv.im};
+      const c64 inv = cdiv_nr({1.0, 0.0}, den);
+      cpv = cscale(inv, upper(i));
+      apv = cscale(cmul(apv, inv), -l);
+      dpv = cmul({rhs(i) - l * dpv.re, -l * dpv.im}, inv);
+      cr[q] = cpv;
+      ar[q] = apv;
+      dr[q] = dpv;
+    }
+  }
+  TriEq e1, e2;
+  {
+    const int i = hi - 1;
+    const double l = lower(i);
+    e2.lo = cscale(apv, -l);
+    e2.di = {bdiag(i).re - l * cpv.re, bdiag(i).im - l * cpv.im};
+    e2.up = {upper(i), 0.0};
+    e2.rh = {rhs(i) - l * dpv.re, -l * dpv.im};
+  }
+  {
+    // upward recurrence: s_i = D + C L_p + A F_p, from the virtual row s_{hi-1} = L_p
+    c64 D = {0.0, 0.0}, C = {1.0, 0.0}, A = {0.0, 0.0};
+#pragma unroll
+    for (int q = 5; q >= 0; --q) {
+      if (q < ni) {
+        D = csub(dr[q], cmul(cr[q], D));
+        C = cscale(cmul(cr[q], C), -1.0);
+        A = csub(cscale(ar[q], -1.0), cmul(cr[q], A));
+      }
+    }
+    const double u = upper(lo);
+    e1.lo = {lower(lo), 0.0};
+    e1.di = cadd(bdiag(lo), cscale(A, u));
+    e1.up = cscale(C, u);
+    e1.rh = {rhs(lo) - u * D.re, -u * D.im};
+  }
+  // PCR over the 2P boundary equations of each system (identity outside the range)
+  const int n2 = 2 * P;
+  TriEq* eq = reinterpret_cast<TriEq*>(lds) + (size_t)sl * n2;
+  const TriEq id = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  if (sl < a.S) {
+    eq[2 * p] = e1;
+    eq[2 * p + 1] = e2;
+  }
+  __syncthreads();
+  for (int st = 1; st < n2; st *= 2) {
+    TriEq nw[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = 2 * p + h;
+      const TriEq c = h ? e2 : e1;
+      const TriEq L = (sl < a.S && q - st >= 0) ? eq[q - st] : id;
+      const TriEq R = (sl < a.S && q + st < n2) ? eq[q + st] : id;
+      const c64 k1 = cdiv_nr(c.lo, L.di), k2 = cdiv_nr(c.up, R.di);
+      nw[h].lo = cscale(cmul(L.lo, k1), -1.0);
+      nw[h].up = cscale(cmul(R.up, k2), -1.0);
+      nw[h].di = csub(csub(c.di, cmul(L.up, k1)), cmul(R.lo, k2));
+      nw[h].rh = csub(csub(c.rh, cmul(L.rh, k1)), cmul(R.rh, k2));
+    }
+    e1 = nw[0];
+    e2 = nw[1];
+    __syncthreads();
+    if (sl < a.S) {
+      eq[2 * p] = e1;
+      eq[2 * p + 1] = e2;
+    }
+    __syncthreads();
+  }
+  if (!live) return;
+  const c64 F = cdiv_nr(e1.rh, e1.di), L = cdiv_nr(e2.rh, e2.di);
+  out[lo] = F;
+  out[hi - 1] = L;
+  c64 x = L;
+#pragma unroll
+  for (int q = 5; q >= 0; --q) {
+    if (q < ni) {
+      x = csub(csub(dr[q], cmul(cr[q], x)), cmul(ar[q], F));
+      out[lo + 1 + q] = x;
+    }
   }
 }
 
@@ -335,10 +442,11 @@ __device__ __forceinline__ void time1d_body(const Time1dArgs& a, long long wg, c
     gi[li] = inv_gamma(a.lev_first + li, Nt, sc.logabsw, gscale);
   const long long x0 = wg * 2LL * S;
   for (int e = threadIdx.x; e < S * Nt; e += blockDim.x) {
-    const int s = e / Nt, j = e - s * Nt;
+    const int j = e / S, s = e - j * S;  // consecutive lanes: consecutive points of one shift
     const long long xa = x0 + 2 * s, xb = xa + 1;
-    const c64 A = xa < m ? a.s2[xa * Nt + j] : c64{0.0, 0.0};
-    const c64 B = xb < m ? a.s2[xb * Nt + j] : c64{0.0, 0.0};
+    const c64* row = a.s2 + (long long)j * m;
+    const c64 A = xa < m ? row[xa] : c64{0.0, 0.0};
+    const c64 B = xb < m ? row[xb] : c64{0.0, 0.0};
     const c64 u = {A.re - B.im, A.im + B.re};
     const int pos = fft_in_pos(a.fft, j);
     if (pos < 0) side[s] = u;

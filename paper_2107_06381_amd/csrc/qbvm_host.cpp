@@ -249,9 +249,10 @@ struct qbvm_plan_s {
   double* ghat = nullptr;
   double* yrow = nullptr;
   c64* s2 = nullptr;
-  c64* cp = nullptr;
   double* W = nullptr;  // padded level workspace (d >= 2 power-of-two pipeline)
   c64* tabs = nullptr;  // per-solve time-transform tables, 3 N_t
+  double* op = nullptr;  // 1D spatial operator: [m-1] lower, [m] diagonal, [m-1] upper (3m doubles)
+  bool has_op = false;
   double* partial = nullptr;
   unsigned* counter = nullptr;
   double* dscal = nullptr;   // [0] delta, [1] alpha_pred, [2] log10 alpha_pred, [3] D, [4] alpha_final, ...
@@ -403,7 +404,6 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
   HIP_TRY(dalloc(p, &p->yrow, p->nmodes));
   if (p->d == 1) {
     HIP_TRY(dalloc(p, &p->s2, (size_t)p->Nt * p->m));
-    HIP_TRY(dalloc(p, &p->cp, (size_t)p->Nt * p->m));
   }
   if (sched::use_padded(geom(p))) HIP_TRY(dalloc(p, &p->W, (size_t)sched::padded_elems(geom(p))));
   HIP_TRY(dalloc(p, &p->tabs, 3 * (size_t)p->Nt));
@@ -482,7 +482,7 @@ int check_alpha(double alpha, int variant) {
 // Enqueue one full solve (every level).  alpha_dev (optional) overrides alpha.
 // W: padded workspace for the aligned pipeline (nullptr: in-place pipeline in y).
 int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, int variant, const double* g,
-                 double* y, c64* s2, c64* cp, NodeCtx* nc, hipStream_t stream, double* W = nullptr) {
+                 double* y, c64* s2, NodeCtx* nc, hipStream_t stream, double* W = nullptr) {
   const sched::Geom G = geom(p);
   const SolveScalars sc = sched::host_scalars(alpha, variant, p->tau);
   if (W && p->d >= 2 && sched::use_padded(G)) {
@@ -512,8 +512,14 @@ int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, in
   if (p->d == 1) {
     const double cells = (double)p->Nt * p->m;
     {
-      ProfScope ps("thomas_1d", stream, 8.0 * p->m + 64.0 * cells, 40.0 * cells, nc);
-      HIP_TRY(launch_thomas(sched::thomas_step(G, sc, alpha_dev, variant, g, s2, cp), stream, nc));
+      ProfScope ps("tridiag_1d", stream, 8.0 * p->m + 16.0 * cells, 150.0 * cells, nc);
+      auto ta = sched::thomas_step(G, sc, alpha_dev, variant, g, s2);
+      if (p->has_op) {
+        ta.args.op_lo = p->op;
+        ta.args.op_di = p->op + p->m;
+        ta.args.op_up = p->op + 2 * p->m;
+      }
+      HIP_TRY(launch_thomas(ta.args, ta.nwg, ta.lds, stream, nc));
     }
     const auto t = sched::time1d_step(G, sc, alpha_dev, variant, s2, y);
     ProfScope ps("time_1d", stream, 24.0 * cells, 0.5 * p->m * (fft_flops(p->tfft->dev) + 8.0 * p->Nt), nc);
@@ -636,18 +642,60 @@ int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta, 
   if (output != QBVM_OUT_ALL && output != QBVM_OUT_Y0 && output != QBVM_OUT_YN)
     return set_error(QBVM_EINVAL, "output must be QBVM_OUT_ALL, QBVM_OUT_Y0 or QBVM_OUT_YN");
   if (output == QBVM_OUT_ALL)
-    return enqueue_full(p, alpha, nullptr, variant, g_delta, y, p->s2, p->cp, nullptr, p->stream, p->W);
+    return enqueue_full(p, alpha, nullptr, variant, g_delta, y, p->s2, nullptr, p->stream, p->W);
+  const int level = output == QBVM_OUT_Y0 ? 0 : p->n;
+  if (p->has_op) {  // no sine basis: the Thomas path, one level of Step (c)
+    const sched::Geom G = geom(p);
+    const SolveScalars sc = sched::host_scalars(alpha, variant, p->tau);
+    auto ta = sched::thomas_step(G, sc, nullptr, variant, g_delta, p->s2);
+    ta.args.op_lo = p->op;
+    ta.args.op_di = p->op + p->m;
+    ta.args.op_up = p->op + 2 * p->m;
+    HIP_TRY(launch_thomas(ta.args, ta.nwg, ta.lds, p->stream, nullptr));
+    auto t = sched::time1d_step(G, sc, nullptr, variant, p->s2, y);
+    t.args.lev_first = level;
+    t.args.lev_count = 1;
+    t.lds = sched::lds_time1d(G, 1);
+    HIP_TRY(launch_time1d(t.args, t.nwg, kThreads, t.lds, p->stream, nullptr));
+    return QBVM_OK;
+  }
   rc = run_dst(p, g_delta, p->ghat, 1, true);
   if (rc) return rc;
-  const int level = output == QBVM_OUT_Y0 ? 0 : p->n;
   rc = enqueue_row(p, 1, p->ghat, level, alpha, nullptr, variant, p->yrow, false, nullptr, 0, nullptr, nullptr,
                    nullptr, p->wg_row);
   if (rc) return rc;
   return run_dst(p, p->yrow, y, 1, false);
 }
 
+int qbvm_plan_set_operator_1d(qbvm_plan_t p, const double* lower, const double* diag, const double* upper) {
+  if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
+  if (!diag) {
+    p->has_op = false;
+    return QBVM_OK;
+  }
+  if (p->d != 1) return set_error(QBVM_EINVAL, "a spatial operator can be set on 1D plans only");
+  const int m = p->m;
+  if (m > 1 && (!lower || !upper)) return set_error(QBVM_EINVAL, "lower and upper diagonals are required");
+  std::vector<double> h(3 * (size_t)m, 0.0);
+  for (int i = 0; i < m; ++i) {
+    h[(size_t)m + i] = diag[i];
+    if (i + 1 < m) {
+      h[i] = lower[i];
+      h[2 * (size_t)m + i] = upper[i];
+    }
+  }
+  for (double v : h)
+    if (!std::isfinite(v)) return set_error(QBVM_EINVAL, "operator entries must be finite");
+  if (!p->op) HIP_TRY(dalloc(p, &p->op, 3 * (size_t)m));
+  HIP_TRY(hipStreamSynchronize(p->stream));  // solves in flight may still read the old operator
+  HIP_TRY(hipMemcpy(p->op, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+  p->has_op = true;
+  return QBVM_OK;
+}
+
 int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f, double* y) {
   if (!p || !f || !y) return set_error(QBVM_EINVAL, "NULL argument");
+  if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "general right-hand side with a spatial operator set");
   int rc = check_alpha(alpha, variant);
   if (rc) return rc;
   const sched::Geom G = geom(p);
@@ -679,6 +727,7 @@ int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f
 
 int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_delta, double* D_out) {
   if (!p || !g_delta || !D_out) return set_error(QBVM_EINVAL, "NULL argument");
+  if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "discrepancy with a spatial operator set");
   int rc = check_alpha(alpha, variant);
   if (rc) return rc;
   rc = run_dst(p, g_delta, p->ghat, 1, true);
@@ -722,6 +771,7 @@ static int check_opts(const qbvm_alpha_opts* o) {
 int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double delta, const qbvm_alpha_opts* o,
                       double* alpha_out, qbvm_alpha_info* info) {
   if (!p || !g_delta || !alpha_out) return set_error(QBVM_EINVAL, "NULL argument");
+  if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
   int rc = check_opts(o);
   if (rc) return rc;
   if (!(delta > 0) || !std::isfinite(delta)) return set_error(QBVM_EINVAL, "delta must be positive");
@@ -782,6 +832,7 @@ static int ensure_batch_ws(qbvm_plan_t p, size_t bytes) {
 int qbvm_bisect_batched(qbvm_plan_t p, int variant, int count, const double* g_deltas, const double* deltas,
                         const qbvm_alpha_opts* o, double* alphas_out, int* hits_out) {
   if (!p || !g_deltas || !deltas || !alphas_out) return set_error(QBVM_EINVAL, "NULL argument");
+  if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
   int rc = check_opts(o);
   if (rc) return rc;
   if (count < 1) return set_error(QBVM_EINVAL, "count must be >= 1");
@@ -1095,19 +1146,17 @@ int build_entry(BatchEntry* e, int count, hipStream_t stream) {
     qbvm_plan_s* p = e->plans[i];
     NodeCtx nc{e->graph, nullptr, false};
     c64* s2 = nullptr;
-    c64* cp = nullptr;
     const int out = e->outputs[i];
     if (out == QBVM_OUT_ALL && p->d == 1) {
       void* w = nullptr;
-      HIP_TRY(hipMalloc(&w, sizeof(c64) * 2 * (size_t)p->Nt * p->m));
+      HIP_TRY(hipMalloc(&w, sizeof(c64) * (size_t)p->Nt * p->m));
       e->ws.push_back(w);
       s2 = static_cast<c64*>(w);
-      cp = s2 + (size_t)p->Nt * p->m;
     }
     // one plan may serve many instances: only its tables and geometry are used here
     int rc;
     if (out == QBVM_OUT_ALL) {
-      rc = enqueue_full(p, 1.0, e->alphas_dev + i, e->variants[i], e->gs[i], e->ys[i], s2, cp, &nc, stream);
+      rc = enqueue_full(p, 1.0, e->alphas_dev + i, e->variants[i], e->gs[i], e->ys[i], s2, &nc, stream);
       if (rc) return rc;
     } else {
       return set_error(QBVM_EUNSUPPORTED, "batched solve supports QBVM_OUT_ALL");

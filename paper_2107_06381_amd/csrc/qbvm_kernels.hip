@@ -13,7 +13,7 @@
 //                  scaling, real part -> y_hat[t][k]
 //        k_dst   : y[t] = Q y_hat[t]                        (d passes per level)
 //   d = 1: paper order, Step (b) by a complex Thomas sweep per shift d_j
-//     (k_thomas), Step (c) as a length-N_t DFT per grid point (k_time1d).
+//     (k_tri1d), Step (c) as a length-N_t DFT per grid point (k_time1d).
 // Two real sequences are packed into one complex transform wherever the result
 // of each is real (sine transforms; time transforms after the inverse scaling).
 #include "qbvm_internal.hpp"
@@ -193,9 +193,9 @@ __global__ __launch_bounds__(256) void k_time(TimeArgs a) {
   time_body<WIDE>(a, blockIdx.x, lds);
 }
 
-__global__ __launch_bounds__(256) void k_thomas(ThomasArgs a) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < a.Nt) thomas_body(a, j);
+__global__ __launch_bounds__(256) void k_tri1d(ThomasArgs a) {
+  extern __shared__ c64 lds[];
+  tri1d_body(a, blockIdx.x, lds);
 }
 
 template <bool WIDE>
@@ -772,9 +772,9 @@ hipError_t launch_tab_job(const TabJob& t, hipStream_t s) {
   return enqueue1((const void*)&k_tab_job, dim3((unsigned)((t.Nt + 255) / 256)), dim3(256), 0, s, t, nullptr);
 }
 
-hipError_t launch_thomas(const ThomasArgs& a, hipStream_t s, NodeCtx* nc) {
-  const int threads = 64;
-  return enqueue1((const void*)&k_thomas, dim3((a.Nt + threads - 1) / threads), dim3(threads), 0, s, a, nc);
+hipError_t launch_thomas(const ThomasArgs& a, long long nwg, size_t lds, hipStream_t s, NodeCtx* nc) {
+  if (a.P < 1 || a.S < 1 || a.P * a.S > 256 || (a.m > 1 && (a.m + a.P - 1) / a.P > 8)) return hipErrorInvalidValue;
+  return enqueue1((const void*)&k_tri1d, dim3((unsigned)nwg), dim3(a.P * a.S), lds, s, a, nc);
 }
 
 hipError_t launch_time1d(const Time1dArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,

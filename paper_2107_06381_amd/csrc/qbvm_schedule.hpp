@@ -290,8 +290,10 @@ inline GeneralSchedule general_schedule(const Geom& g, const double* f, double* 
   return gs;
 }
 
-inline ThomasArgs thomas_step(const Geom& g, SolveScalars sc, const double* alpha_dev, int variant,
-                              const double* gd, c64* s2, c64* cp) {
+// 1D Step (b): partition solver with P = ceil(m/8) lanes per shift's system and
+// S = 256/P systems per workgroup; LDS holds the 2P boundary equations of each system.
+inline Launch<ThomasArgs> thomas_step(const Geom& g, SolveScalars sc, const double* alpha_dev, int variant,
+                                      const double* gd, c64* s2) {
   ThomasArgs ta{};
   ta.Nt = g.Nt;
   ta.m = g.m;
@@ -302,8 +304,10 @@ inline ThomasArgs thomas_step(const Geom& g, SolveScalars sc, const double* alph
   ta.variant = variant;
   ta.g = gd;
   ta.s2 = s2;
-  ta.cp = cp;
-  return ta;
+  ta.P = g.m == 1 ? 1 : (g.m + 7) / 8;
+  ta.S = ta.P >= 256 ? 1 : 256 / ta.P;
+  const long long nwg = (g.Nt + ta.S - 1) / ta.S;
+  return {ta, nwg, sizeof(c64) * 4 * 2 * (size_t)ta.P * ta.S};
 }
 
 inline Launch<Time1dArgs> time1d_step(const Geom& g, SolveScalars sc, const double* alpha_dev, int variant,

@@ -124,8 +124,14 @@ struct ThomasArgs {
   const double* alpha_dev;  // if non-null, alpha is read from here
   int variant;
   const double* g;   // m
-  c64* s2;           // [m][Nt] solution of (d_j/tau - Lap_h) s = f0
-  c64* cp;           // [m][Nt] Thomas scratch
+  c64* s2;           // [Nt][m] solution of (d_j/tau - Lap_h) s = f0, one row per shift
+  int P;             // lanes per system (each holds a chunk of at most 8 rows)
+  int S;             // systems per workgroup
+  // optional spatial operator A in place of -Lap_h (op_di == nullptr: the Dirichlet
+  // stencil): A[i][i-1] = op_lo[i-1], A[i][i] = op_di[i], A[i][i+1] = op_up[i]
+  const double* op_lo;
+  const double* op_di;
+  const double* op_up;
 };
 
 // 1D Step (c) from the Thomas output: inverse DFT per spatial point.

@@ -32,7 +32,7 @@ EXPORTS = [
     "qbvm_mlp_forward", "qbvm_mlp_loss_grad", "qbvm_adam_step", "qbvm_strerror",
     "qbvm_last_error", "qbvm_version", "qbvm_profile_enable", "qbvm_profile_reset",
     "qbvm_profile_count", "qbvm_profile_get", "qbvm_plan_autotune", "qbvm_plan_get_variants",
-    "qbvm_plan_set_variants",
+    "qbvm_plan_set_variants", "qbvm_plan_set_operator_1d",
 ]
 
 
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qbvm_plan_get_variants": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                        ctypes.POINTER(i)]),
         "qbvm_plan_set_variants": (i, [vp, i, i, i, i]),
+        "qbvm_plan_set_operator_1d": (i, [vp, vp, vp, vp]),
         "qbvm_profile_enable": (None, [i]),
         "qbvm_profile_reset": (None, []),
         "qbvm_profile_count": (i, []),
@@ -186,6 +187,18 @@ class Plan:
         _check(self.L_.qbvm_plan_get_variants(self._h, ctypes.byref(r), ctypes.byref(c), ctypes.byref(t),
                                               ctypes.byref(g)))
         return {"rows": r.value, "cols": c.value, "time": t.value, "general": g.value}
+
+    def set_operator_1d(self, lower=None, diag=None, upper=None):
+        """Tridiagonal spatial operator in place of -Lap_h (1D); diag=None restores it."""
+        import numpy as np
+        if diag is None:
+            _check(self.L_.qbvm_plan_set_operator_1d(self._h, None, None, None))
+            return
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (lower, diag, upper)]
+        if arrs[1].shape != (self.m,) or arrs[0].shape != (self.m - 1,) or arrs[2].shape != (self.m - 1,):
+            raise ValueError("operator diagonals must have m-1, m, m-1 entries")
+        ptr = [a.ctypes.data if a.size else None for a in arrs]
+        _check(self.L_.qbvm_plan_set_operator_1d(self._h, *ptr))
 
     def set_variants(self, rows: int = -1, cols: int = -1, time: int = -1, general: int = -1):
         """Select kernel variants by hand (-1 keeps the current one)."""

@@ -5,6 +5,8 @@
 //   kernels_cpu solve d m n L T alpha variant in.bin out.bin [var_rows var_cols var_time [padded]]
 //   kernels_cpu dst   d m batch in.bin out.bin [var_rows var_cols input]
 //   kernels_cpu general d m n L T alpha variant f.bin out.bin [padded var_gen]   (general right-hand side)
+//   kernels_cpu solveop m n L T alpha variant in.bin out.bin op.bin level   (1D, tridiagonal operator;
+//       op.bin: lower[m-1] diag[m] upper[m-1]; level -1: every level, else that level only)
 #include "hip_cpu_shim.hpp"
 
 #include <cstdio>
@@ -391,6 +393,49 @@ int main(int argc, char** argv) {
     delete[] W;
     return 0;
   }
+  if (cmd == "solveop" && argc == 12) {
+    const int m = atoi(argv[2]), n = atoi(argv[3]);
+    const double L = atof(argv[4]), T = atof(argv[5]), alpha = atof(argv[6]);
+    const int variant = atoi(argv[7]), level = atoi(argv[11]);
+    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1));
+    const double h = L / (m + 1);
+    std::vector<double> mu(m, 0.0);
+    sched::Geom g = geom(1, m, n, L, T, tt, st, mu);
+    (void)h;
+    auto raw = read_file(argv[8]);
+    if (raw.size() != (size_t)m * sizeof(double)) return 7;
+    auto rop = read_file(argv[10]);
+    if (rop.size() != (size_t)(3 * m - 2) * sizeof(double)) return 8;
+    std::vector<double> gd(m), opf(3 * m - 2), op(3 * (size_t)m, std::nan(""));
+    std::memcpy(gd.data(), raw.data(), raw.size());
+    std::memcpy(opf.data(), rop.data(), rop.size());
+    for (int i = 0; i < m; ++i) {  // the library's device layout: [m] lower, [m] diag, [m] upper
+      op[m + i] = opf[(m - 1) + i];
+      if (i + 1 < m) {
+        op[i] = opf[i];
+        op[2 * (size_t)m + i] = opf[(2 * m - 1) + i];
+      }
+    }
+    const SolveScalars sc = sched::host_scalars(alpha, variant, g.tau);
+    std::vector<c64> s2((size_t)g.Nt * m, c64{std::nan(""), std::nan("")});
+    auto ta = sched::thomas_step(g, sc, nullptr, variant, gd.data(), s2.data());
+    ta.args.op_lo = op.data();
+    ta.args.op_di = op.data() + m;
+    ta.args.op_up = op.data() + 2 * m;
+    run_grid(ta.nwg, ta.args.P * ta.args.S, ta.lds, [&](long long wg, c64* l) { tri1d_body(ta.args, wg, l); });
+    const size_t ny = level < 0 ? (size_t)g.Nt * m : (size_t)m;
+    std::vector<double> y(ny);
+    auto t = sched::time1d_step(g, sc, nullptr, variant, s2.data(), y.data());
+    if (level >= 0) {
+      t.args.lev_first = level;
+      t.args.lev_count = 1;
+      t.lds = sched::lds_time1d(g, 1);
+    }
+    if (t.args.fft.wide) run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time1d_body<true>(t.args, wg, l); });
+    else run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time1d_body<false>(t.args, wg, l); });
+    write_file(argv[9], y.data(), ny * sizeof(double));
+    return 0;
+  }
   if (cmd == "solve" && (argc == 11 || argc == 14 || argc == 15)) {
     const int d = atoi(argv[2]), m = atoi(argv[3]), n = atoi(argv[4]);
     const double L = atof(argv[5]), T = atof(argv[6]), alpha = atof(argv[7]);
@@ -434,14 +479,13 @@ int main(int argc, char** argv) {
       delete[] W;
     } else if (d == 1) {
       c64* s2 = new c64[(size_t)g.Nt * m];
-      c64* cp = new c64[(size_t)g.Nt * m];
-      const ThomasArgs ta = sched::thomas_step(g, sc, nullptr, variant, gd, s2, cp);
-      for (int j = 0; j < g.Nt; ++j) thomas_body(ta, j);
+      for (size_t q = 0; q < (size_t)g.Nt * m; ++q) s2[q] = c64{std::nan(""), std::nan("")};
+      const auto ta = sched::thomas_step(g, sc, nullptr, variant, gd, s2);
+      run_grid(ta.nwg, ta.args.P * ta.args.S, ta.lds, [&](long long wg, c64* l) { tri1d_body(ta.args, wg, l); });
       const auto t = sched::time1d_step(g, sc, nullptr, variant, s2, y);
       if (t.args.fft.wide) run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time1d_body<true>(t.args, wg, l); });
       else run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time1d_body<false>(t.args, wg, l); });
       delete[] s2;
-      delete[] cp;
     } else {
       run_dst(g, gd, y, 1, true);
       const auto t = sched::time_step(g, sc, nullptr, variant, y, y, 0, g.Nt);
