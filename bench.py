@@ -298,9 +298,25 @@ def operator_1d_bench(steps: int = 20):
     plan.close()
     kernels = {k: {"avg_us": round(r["total_ms"] / r["launches"] * 1e3, 1),
                    "GBps": round(r["bytes"] / (r["total_ms"] * 1e-3) / 1e9, 1)} for k, r in rep.items()}
+    # the 1D configuration (m=127, n=128, Dirichlet stencil): latency of one solve
+    inst = W.config_1d()
+    p1 = qbvm.Plan(1, inst.m, inst.n, inst.L, inst.T)
+    g1 = torch.from_numpy(inst.g_delta).to("cuda:0")
+    y1 = torch.empty((inst.n + 1, inst.m), dtype=torch.float64, device="cuda:0")
+    for _ in range(5):
+        p1.solve(inst.alpha, qbvm.QBVM_PQ, g1, y1)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(100):
+        p1.solve(inst.alpha, qbvm.QBVM_PQ, g1, y1)
+    e1.record()
+    torch.cuda.synchronize()
+    us1 = e0.elapsed_time(e1) / 100 * 1e3
+    p1.close()
     return {"workload": "1D m=2047, n=4095 (N_t=4096), variable kappa (contrast 4), alpha=1e-4, every level",
             "ms_per_solve": round(ms, 4), "Munknowns_per_s": round(n * m / (ms * 1e-3) / 1e6, 1),
-            "kernels": kernels}
+            "kernels": kernels,
+            "config_1d_m127_n128_us_per_solve": round(us1, 2)}
 
 
 def main():

@@ -381,13 +381,31 @@ __device__ __forceinline__ void tri1d_body(const ThomasArgs& a, long long wg, c6
     e1.up = cscale(C, u);
     e1.rh = {rhs(lo) - u * D.re, -u * D.im};
   }
-  // PCR over the 2P boundary equations of each system (identity outside the range)
+  // PCR over the 2P boundary equations of each system (identity outside the range).
+  // LDS: four coefficient arrays per system; equation q sits in slot q/2 (q even) or
+  // P + q/2 (q odd), so the lanes of a step always read consecutive 16-byte slots.
   const int n2 = 2 * P;
-  TriEq* eq = reinterpret_cast<TriEq*>(lds) + (size_t)sl * n2;
+  c64* elo = lds + (size_t)sl * 4 * n2;
+  c64* edi = elo + n2;
+  c64* eup = edi + n2;
+  c64* erh = eup + n2;
+  auto slot = [&](int q) { return (q & 1) ? P + (q >> 1) : (q >> 1); };
+  auto put = [&](int q, const TriEq& e) {
+    const int k = slot(q);
+    elo[k] = e.lo;
+    edi[k] = e.di;
+    eup[k] = e.up;
+    erh[k] = e.rh;
+  };
+  auto get = [&](int q) -> TriEq {
+    const int k = slot(q);
+    return {elo[k], edi[k], eup[k], erh[k]};
+  };
   const TriEq id = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-  if (sl < a.S) {
-    eq[2 * p] = e1;
-    eq[2 * p + 1] = e2;
+  const bool own = sl < a.S;
+  if (own) {
+    put(2 * p, e1);
+    put(2 * p + 1, e2);
   }
   __syncthreads();
   for (int st = 1; st < n2; st *= 2) {
@@ -396,8 +414,8 @@ __device__ __forceinline__ void tri1d_body(const ThomasArgs& a, long long wg, c6
     for (int h = 0; h < 2; ++h) {
       const int q = 2 * p + h;
       const TriEq c = h ? e2 : e1;
-      const TriEq L = (sl < a.S && q - st >= 0) ? eq[q - st] : id;
-      const TriEq R = (sl < a.S && q + st < n2) ? eq[q + st] : id;
+      const TriEq L = (own && q - st >= 0) ? get(q - st) : id;
+      const TriEq R = (own && q + st < n2) ? get(q + st) : id;
       const c64 k1 = cdiv_nr(c.lo, L.di), k2 = cdiv_nr(c.up, R.di);
       nw[h].lo = cscale(cmul(L.lo, k1), -1.0);
       nw[h].up = cscale(cmul(R.up, k2), -1.0);
@@ -407,9 +425,9 @@ __device__ __forceinline__ void tri1d_body(const ThomasArgs& a, long long wg, c6
     e1 = nw[0];
     e2 = nw[1];
     __syncthreads();
-    if (sl < a.S) {
-      eq[2 * p] = e1;
-      eq[2 * p + 1] = e2;
+    if (own) {
+      put(2 * p, e1);
+      put(2 * p + 1, e2);
     }
     __syncthreads();
   }

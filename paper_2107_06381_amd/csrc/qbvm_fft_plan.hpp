@@ -141,8 +141,22 @@ inline void fill_stages(FftPlanDev& d, int nc) {
 inline bool build_tables(int n, HostFft& t, std::string& err) {
   FftPlanDev& d = t.dev;
   d.n = n;
+  // Prefer cores whose radices are all <= 7 (the narrow kernels keep a butterfly in
+  // registers without spilling): Stockham, Rader on n - 1, else Bluestein if its core
+  // fits; only lengths beyond that use the wide kernels (odd radices up to 47).
   int nc;
-  if (smooth(n, kMaxOddRadixWide)) {
+  int blue = 2 * n - 1;
+  while (!smooth(blue, kMaxOddRadixNarrow)) ++blue;
+  if (smooth(n, kMaxOddRadixNarrow)) {
+    d.kind = kStockham;
+    nc = n;
+  } else if (is_prime(n) && smooth(n - 1, kMaxOddRadixNarrow)) {
+    d.kind = kRader;
+    nc = n - 1;
+  } else if (blue <= kMaxCore) {
+    d.kind = kBluestein;
+    nc = blue;
+  } else if (smooth(n, kMaxOddRadixWide)) {
     d.kind = kStockham;
     nc = n;
   } else if (is_prime(n) && smooth(n - 1, kMaxOddRadixWide)) {
@@ -150,8 +164,7 @@ inline bool build_tables(int n, HostFft& t, std::string& err) {
     nc = n - 1;
   } else {
     d.kind = kBluestein;
-    nc = 2 * n - 1;
-    while (!smooth(nc, kMaxOddRadixNarrow)) ++nc;
+    nc = blue;
   }
   if (nc > kMaxCore) {
     err = "FFT length " + std::to_string(n) + " needs a core of " + std::to_string(nc) + " > 4096";
