@@ -408,23 +408,22 @@ __device__ __forceinline__ void tri1d_body(const ThomasArgs& a, long long wg, c6
     put(2 * p + 1, e2);
   }
   __syncthreads();
-  // one reduction step of equation q (current coefficients c) with its neighbours at +-st
-  auto reduce = [&](int q, const TriEq& c, int st) -> TriEq {
-    const TriEq L = (own && q - st >= 0) ? get(q - st) : id;
-    const TriEq R = (own && q + st < n2) ? get(q + st) : id;
-    const c64 k1 = cdiv_nr(c.lo, L.di), k2 = cdiv_nr(c.up, R.di);
-    TriEq r;
-    r.lo = cscale(cmul(L.lo, k1), -1.0);
-    r.up = cscale(cmul(R.up, k2), -1.0);
-    r.di = csub(csub(c.di, cmul(L.up, k1)), cmul(R.lo, k2));
-    r.rh = csub(csub(c.rh, cmul(L.rh, k1)), cmul(R.rh, k2));
-    return r;
-  };
   for (int st = 1; st < n2; st *= 2) {
-    const TriEq r1 = reduce(2 * p, e1, st);
-    const TriEq r2 = reduce(2 * p + 1, e2, st);
-    e1 = r1;
-    e2 = r2;
+    TriEq nw[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = 2 * p + h;
+      const TriEq c = h ? e2 : e1;
+      const TriEq L = (own && q - st >= 0) ? get(q - st) : id;
+      const TriEq R = (own && q + st < n2) ? get(q + st) : id;
+      const c64 k1 = cdiv_nr(c.lo, L.di), k2 = cdiv_nr(c.up, R.di);
+      nw[h].lo = cscale(cmul(L.lo, k1), -1.0);
+      nw[h].up = cscale(cmul(R.up, k2), -1.0);
+      nw[h].di = csub(csub(c.di, cmul(L.up, k1)), cmul(R.lo, k2));
+      nw[h].rh = csub(csub(c.rh, cmul(L.rh, k1)), cmul(R.rh, k2));
+    }
+    e1 = nw[0];
+    e2 = nw[1];
     __syncthreads();
     if (own) {
       put(2 * p, e1);
