@@ -164,7 +164,7 @@ def solve_general_splu(f, d, m, n, L, T, alpha, variant):
     """O2 for a general right-hand side f (one block per level, shape (n+1,)+(m,)*d):
     A y = f with the assembled all-at-once matrix (Sections 3.1, 3.2), by sparse LU.
     This is one source-term solve, or one application of the PinT system as a
-    preconditioner (Section 6)."""
+    preconditioner (mentioned at the end of Section 2 and in Section 5)."""
     A = assemble_allatonce(d, m, n, L, T, alpha, variant).tocsc()
     lu = spla.splu(A, permc_spec="COLAMD")
     return lu.solve(np.ravel(np.asarray(f, dtype=np.float64))).reshape((n + 1,) + (m,) * d)
