@@ -60,6 +60,9 @@ CASES = [
     (2, 255, 6, 1e-3, 0), (2, 511, 3, 1e-2, 1), (2, 1023, 2, 1e-3, 0), (3, 63, 64, 1e-4, 0),
     # padded level pipeline: 2D N_t = 256, 3D N_t = 64, 2D m = 511 with N_t = 128
     (2, 63, 255, 1e-5, 1), (3, 31, 63, 1e-3, 0), (2, 511, 127, 1e-4, 0),
+    # the ends of the bisection bracket (alpha = 1e-20 .. 1), both variants
+    (2, 63, 64, 1e-20, 0), (2, 63, 64, 1.0, 1), (1, 127, 128, 1e-20, 1), (3, 15, 16, 1e-20, 0),
+    (2, 255, 256, 1e-20, 0), (2, 255, 256, 1.0, 0),
 ]
 
 
