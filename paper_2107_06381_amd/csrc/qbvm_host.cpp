@@ -253,6 +253,7 @@ struct qbvm_plan_s {
   c64* tabs = nullptr;  // per-solve time-transform tables, 3 N_t
   double* op = nullptr;  // 1D spatial operator: [m-1] lower, [m] diagonal, [m-1] upper (3m doubles)
   bool has_op = false;
+  bool no_sine = false;  // 1D only: the sine transform of length 2(m+1) exceeds the FFT core
   double* partial = nullptr;
   unsigned* counter = nullptr;
   double* dscal = nullptr;   // [0] delta, [1] alpha_pred, [2] log10 alpha_pred, [3] D, [4] alpha_final, ...
@@ -368,9 +369,17 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
   rc = get_fft(p->device, p->Nt, &p->tfft);
   if (rc) return rc;
   rc = get_fft(p->device, 2 * (p->m + 1), &p->sfft);
+  if (rc == QBVM_EUNSUPPORTED && p->d == 1) {
+    // the 1D solve never needs the sine transform (Step (b) is tridiagonal); only the
+    // calls that work in the sine basis are refused on this plan
+    static const FftTables kNoSine{};
+    p->sfft = &kNoSine;
+    p->no_sine = true;
+    rc = QBVM_OK;
+  }
   if (rc) return rc;
   p->S_time = plan::signals_for(p->tfft->dev.nc);
-  p->S_dst = plan::signals_for(p->sfft->dev.nc);
+  p->S_dst = p->no_sine ? 1 : plan::signals_for(p->sfft->dev.nc);
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto pick = [&](int role, int N, int& var) {
@@ -456,6 +465,7 @@ sched::Geom geom(const qbvm_plan_s* p) {
 // (power-of-two passes only; returns QBVM_EUNSUPPORTED before enqueueing otherwise)
 int run_dst(const qbvm_plan_s* p, const double* in, double* out, long long batch, bool input_transform,
             NodeCtx* nc = nullptr, hipStream_t stream = nullptr, const TabJob* tab = nullptr) {
+  if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   hipStream_t s = nc ? stream : p->stream;
   auto passes = sched::dst_passes(geom(p), in, out, batch, input_transform);
   if (tab) {
@@ -644,13 +654,15 @@ int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta, 
   if (output == QBVM_OUT_ALL)
     return enqueue_full(p, alpha, nullptr, variant, g_delta, y, p->s2, nullptr, p->stream, p->W);
   const int level = output == QBVM_OUT_Y0 ? 0 : p->n;
-  if (p->has_op) {  // no sine basis: the Thomas path, one level of Step (c)
+  if (p->has_op || p->no_sine) {  // no sine basis: the tridiagonal path, one level of Step (c)
     const sched::Geom G = geom(p);
     const SolveScalars sc = sched::host_scalars(alpha, variant, p->tau);
     auto ta = sched::thomas_step(G, sc, nullptr, variant, g_delta, p->s2);
-    ta.args.op_lo = p->op;
-    ta.args.op_di = p->op + p->m;
-    ta.args.op_up = p->op + 2 * p->m;
+    if (p->has_op) {
+      ta.args.op_lo = p->op;
+      ta.args.op_di = p->op + p->m;
+      ta.args.op_up = p->op + 2 * p->m;
+    }
     HIP_TRY(launch_thomas(ta.args, ta.nwg, ta.lds, p->stream, nullptr));
     auto t = sched::time1d_step(G, sc, nullptr, variant, p->s2, y);
     t.args.lev_first = level;
@@ -696,6 +708,7 @@ int qbvm_plan_set_operator_1d(qbvm_plan_t p, const double* lower, const double* 
 int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f, double* y) {
   if (!p || !f || !y) return set_error(QBVM_EINVAL, "NULL argument");
   if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "general right-hand side with a spatial operator set");
+  if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_alpha(alpha, variant);
   if (rc) return rc;
   const sched::Geom G = geom(p);
@@ -728,6 +741,7 @@ int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f
 int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_delta, double* D_out) {
   if (!p || !g_delta || !D_out) return set_error(QBVM_EINVAL, "NULL argument");
   if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "discrepancy with a spatial operator set");
+  if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_alpha(alpha, variant);
   if (rc) return rc;
   rc = run_dst(p, g_delta, p->ghat, 1, true);
@@ -772,6 +786,7 @@ int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double 
                       double* alpha_out, qbvm_alpha_info* info) {
   if (!p || !g_delta || !alpha_out) return set_error(QBVM_EINVAL, "NULL argument");
   if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
+  if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_opts(o);
   if (rc) return rc;
   if (!(delta > 0) || !std::isfinite(delta)) return set_error(QBVM_EINVAL, "delta must be positive");
@@ -833,6 +848,7 @@ int qbvm_bisect_batched(qbvm_plan_t p, int variant, int count, const double* g_d
                         const qbvm_alpha_opts* o, double* alphas_out, int* hits_out) {
   if (!p || !g_deltas || !deltas || !alphas_out) return set_error(QBVM_EINVAL, "NULL argument");
   if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
+  if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_opts(o);
   if (rc) return rc;
   if (count < 1) return set_error(QBVM_EINVAL, "count must be >= 1");
@@ -859,6 +875,7 @@ int qbvm_bisect_batched(qbvm_plan_t p, int variant, int count, const double* g_d
 int qbvm_features(qbvm_plan_t p, int count, const double* g_deltas, const double* deltas, float* feats) {
   if (!p || !g_deltas || !deltas || !feats) return set_error(QBVM_EINVAL, "NULL argument");
   if (count < 1) return set_error(QBVM_EINVAL, "count must be >= 1");
+  if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   const size_t gh = (size_t)count * p->nmodes * sizeof(double);
   int rc = ensure_batch_ws(p, gh + 256);
   if (rc) return rc;

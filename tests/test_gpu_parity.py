@@ -288,6 +288,28 @@ def test_operator_1d_vs_oracle(m, n, alpha, variant, adv):
     p.close()
 
 
+def test_1d_plan_without_sine_transform():
+    """1D m = 1251: the sine length 2(m+1) = 2504 = 8 * 313 needs a Bluestein core above
+    4096 points.  The plan still solves (tridiagonal path, every output mode); the calls
+    that work in the sine basis are refused."""
+    say("[case] 1d without sine transform")
+    m, n, alpha = 1251, 106, 1e-4
+    g = np.random.default_rng(12).standard_normal(m)
+    p = qbvm.Plan(1, m, n, 1.0, 0.8)
+    gd = to_dev(g)
+    y = p.solve(alpha, 0, gd)
+    yn = p.solve(alpha, 0, gd, output=qbvm.OUT_YN)
+    torch.cuda.synchronize()
+    yc = O.closed_form(g, 1, m, n, 1.0, 0.8, alpha, O.PQ)
+    assert rel(y.cpu().numpy(), yc) < TOL and rel(yn.cpu().numpy(), yc[-1]) < TOL
+    for call in (lambda: p.discrepancy(alpha, 0, gd),
+                 lambda: p.solve_general(alpha, 0, to_dev(np.zeros((n + 1, m))))):
+        with pytest.raises(qbvm.QbvmError) as ei:
+            call()
+        assert ei.value.code == -5
+    p.close()
+
+
 def test_operator_rejected_off_1d():
     say("[case] operator on a 2D plan")
     p = qbvm.Plan(2, 15, 8)
@@ -457,3 +479,52 @@ def test_autotune_then_solve():
     torch.cuda.synchronize()
     yc = O.closed_form(g, d, m, n, 1.0, 1.0, 1e-5, O.PQ)
     assert rel(y.cpu().numpy(), yc) < TOL
+
+
+def _random_cases(count=24, seed=2024):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        d = int(rng.integers(1, 4))
+        mmax = {1: 1500, 2: 160, 3: 40}[d]
+        m = int(rng.integers(1, mmax + 1))
+        n = int(rng.integers(1, {1: 1200, 2: 300, 3: 80}[d]))
+        alpha = float(10.0 ** rng.uniform(-12, 0))
+        out.append((d, m, n, alpha, int(rng.integers(0, 2))))
+    return out
+
+
+@pytest.mark.parametrize("d,m,n,alpha,variant", _random_cases())
+def test_random_grids_vs_oracle(d, m, n, alpha, variant):
+    """Seeded random grids (every FFT path: Stockham, Rader, Bluestein, Good-Thomas,
+    power-of-two; ragged tiles): rank-one solve and general right-hand side against the
+    closed forms; in 1D also a variable-coefficient operator."""
+    say(f"[case] random d={d} m={m} n={n} alpha={alpha:.3g} variant={variant}")
+    rng = np.random.default_rng(d * 7919 + m * 31 + n)
+    L, T = 1.0, 0.8
+    g = rng.standard_normal((m,) * d)
+    p = qbvm.Plan(d, m, n, L, T)
+    y = p.solve(alpha, variant, to_dev(g))
+    y0 = p.solve(alpha, variant, to_dev(g), output=qbvm.OUT_Y0)
+    f = rng.standard_normal((n + 1,) + (m,) * d)
+    try:
+        yg = p.solve_general(alpha, variant, to_dev(f))
+    except qbvm.QbvmError as e:
+        # a 1D plan whose sine length 2(m+1) exceeds the FFT core keeps only the
+        # tridiagonal path (include/qbvm.h); nothing else may refuse here
+        assert e.code == -5 and d == 1, e
+        yg = None
+    torch.cuda.synchronize()
+    yc = O.closed_form(g, d, m, n, L, T, alpha, variant)
+    assert rel(y.cpu().numpy(), yc) < TOL
+    assert rel(y0.cpu().numpy(), yc[0]) < TOL
+    if yg is not None:
+        assert rel(yg.cpu().numpy(), O.closed_form_general(f, d, m, n, L, T, alpha, variant)) < TOL
+    if d == 1:
+        lo, di, up = W.diffusion_operator_1d(m, rng)
+        p.set_operator_1d(lo, di, up)
+        yo = p.solve(alpha, variant, to_dev(g))
+        torch.cuda.synchronize()
+        yoc = O.closed_form_operator(g, O.tridiagonal_matrix(lo, di, up), n, T, alpha, variant)
+        assert rel(yo.cpu().numpy(), yoc) < TOL
+    p.close()
