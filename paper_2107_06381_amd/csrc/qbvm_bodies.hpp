@@ -318,6 +318,7 @@ struct TriEq {
 __device__ __forceinline__ void tri1d_body(const ThomasArgs& a, long long wg, c64* lds) {
   const int Nt = a.Nt, m = a.m, P = a.P;
   const int t = threadIdx.x, sl = t / P, p = t - sl * P;
+  tab_job_run(a.tab, wg * blockDim.x + t, (long long)gridDim.x * blockDim.x);
   const long long jl = wg * a.S + sl;
   const bool live = sl < a.S && jl < Nt;
   const int j = live ? (int)jl : 0;
@@ -453,11 +454,15 @@ __device__ __forceinline__ void time1d_body(const Time1dArgs& a, long long wg, c
   const int S = a.S, Nt = a.Nt, nc = a.fft.nc, m = a.m;
   c64* buf = lds;
   c64* side = buf + (size_t)S * nc;
-  c64* gi = side + 2 * S;
-  const double gscale = 1.0 / (double)Nt;
-  const SolveScalars sc = a.alpha_dev ? scalars_from_alpha(*a.alpha_dev, a.variant, a.tau) : a.sc;
-  for (int li = threadIdx.x; li < a.lev_count; li += blockDim.x)
-    gi[li] = inv_gamma(a.lev_first + li, Nt, sc.logabsw, gscale);
+  // gamma_l^{-1}/N_t of the written levels: from the per-solve table, else into LDS
+  const c64* gi = a.gitab ? a.gitab + Nt + a.lev_first : side + 2 * S;
+  if (!a.gitab) {
+    const double gscale = 1.0 / (double)Nt;
+    const SolveScalars sc = a.alpha_dev ? scalars_from_alpha(*a.alpha_dev, a.variant, a.tau) : a.sc;
+    c64* gl = side + 2 * S;
+    for (int li = threadIdx.x; li < a.lev_count; li += blockDim.x)
+      gl[li] = inv_gamma(a.lev_first + li, Nt, sc.logabsw, gscale);
+  }
   const long long x0 = wg * 2LL * S;
   for (int e = threadIdx.x; e < S * Nt; e += blockDim.x) {
     const int j = e / S, s = e - j * S;  // consecutive lanes: consecutive points of one shift

@@ -529,9 +529,16 @@ int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, in
         ta.args.op_di = p->op + p->m;
         ta.args.op_up = p->op + 2 * p->m;
       }
+      // a single solve owns the plan's tables: the time kernel's gamma table is side work
+      // here; batched instances may share a plan concurrently and keep it in LDS
+      if (!nc) ta.args.tab = TabJob{p->tabs, p->Nt, variant, p->tau, alpha, alpha_dev, 1};
       HIP_TRY(launch_thomas(ta.args, ta.nwg, ta.lds, stream, nc));
     }
-    const auto t = sched::time1d_step(G, sc, alpha_dev, variant, s2, y);
+    auto t = sched::time1d_step(G, sc, alpha_dev, variant, s2, y);
+    if (!nc) {
+      t.args.gitab = p->tabs;
+      t.lds = sched::lds_time1d(G, 0);
+    }
     ProfScope ps("time_1d", stream, 24.0 * cells, 0.5 * p->m * (fft_flops(p->tfft->dev) + 8.0 * p->Nt), nc);
     HIP_TRY(launch_time1d(t.args, t.nwg, kThreads, t.lds, stream, nc));
     return QBVM_OK;

@@ -127,6 +127,7 @@ struct ThomasArgs {
   c64* s2;           // [Nt][m] solution of (d_j/tau - Lap_h) s = f0, one row per shift
   int P;             // lanes per system (each holds a chunk of at most 8 rows)
   int S;             // systems per workgroup
+  TabJob tab;        // optional side work: the per-solve tables of the time kernel
   // optional spatial operator A in place of -Lap_h (op_di == nullptr: the Dirichlet
   // stencil): A[i][i-1] = op_lo[i-1], A[i][i] = op_di[i], A[i][i+1] = op_up[i]
   const double* op_lo;
@@ -147,6 +148,7 @@ struct Time1dArgs {
   double tau;
   const c64* s2;
   double* y;
+  const c64* gitab;  // optional per-solve table ([N_t] d_j/tau, [N_t] gamma_l^{-1}/N_t); else in LDS
   FftPlanDev fft;
 };
 

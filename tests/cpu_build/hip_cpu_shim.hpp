@@ -19,6 +19,7 @@ struct EmuDim {
 inline thread_local EmuDim threadIdx;
 inline thread_local EmuDim blockDim;
 inline thread_local EmuDim blockIdx;
+inline thread_local EmuDim gridDim;
 inline std::barrier<>* g_emu_barrier = nullptr;
 
 inline void __syncthreads() { g_emu_barrier->arrive_and_wait(); }

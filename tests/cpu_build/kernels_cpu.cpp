@@ -37,6 +37,7 @@ static void run_grid(long long nwg, int T, size_t lds_bytes, F body) {
     th.emplace_back([&, t] {
       threadIdx.x = t;
       blockDim.x = T;
+      gridDim.x = (unsigned)nwg;
       for (long long wg = 0; wg < nwg; ++wg) {
         blockIdx.x = (unsigned)wg;
         body(wg, reinterpret_cast<c64*>(lds));
@@ -422,10 +423,17 @@ int main(int argc, char** argv) {
     ta.args.op_lo = op.data();
     ta.args.op_di = op.data() + m;
     ta.args.op_up = op.data() + 2 * m;
+    // every level: the gamma table as side work of the solver kernel, as the host does
+    std::vector<c64> tabs(3 * (size_t)g.Nt, c64{std::nan(""), std::nan("")});
+    if (level < 0) ta.args.tab = TabJob{tabs.data(), g.Nt, variant, g.tau, alpha, nullptr, 1};
     run_grid(ta.nwg, ta.args.P * ta.args.S, ta.lds, [&](long long wg, c64* l) { tri1d_body(ta.args, wg, l); });
     const size_t ny = level < 0 ? (size_t)g.Nt * m : (size_t)m;
     std::vector<double> y(ny);
     auto t = sched::time1d_step(g, sc, nullptr, variant, s2.data(), y.data());
+    if (level < 0) {
+      t.args.gitab = tabs.data();
+      t.lds = sched::lds_time1d(g, 0);
+    }
     if (level >= 0) {
       t.args.lev_first = level;
       t.args.lev_count = 1;
@@ -480,9 +488,13 @@ int main(int argc, char** argv) {
     } else if (d == 1) {
       c64* s2 = new c64[(size_t)g.Nt * m];
       for (size_t q = 0; q < (size_t)g.Nt * m; ++q) s2[q] = c64{std::nan(""), std::nan("")};
-      const auto ta = sched::thomas_step(g, sc, nullptr, variant, gd, s2);
+      auto ta = sched::thomas_step(g, sc, nullptr, variant, gd, s2);
+      std::vector<c64> tabs(3 * (size_t)g.Nt, c64{std::nan(""), std::nan("")});
+      ta.args.tab = TabJob{tabs.data(), g.Nt, variant, g.tau, alpha, nullptr, 1};
       run_grid(ta.nwg, ta.args.P * ta.args.S, ta.lds, [&](long long wg, c64* l) { tri1d_body(ta.args, wg, l); });
-      const auto t = sched::time1d_step(g, sc, nullptr, variant, s2, y);
+      auto t = sched::time1d_step(g, sc, nullptr, variant, s2, y);
+      t.args.gitab = tabs.data();
+      t.lds = sched::lds_time1d(g, 0);
       if (t.args.fft.wide) run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time1d_body<true>(t.args, wg, l); });
       else run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time1d_body<false>(t.args, wg, l); });
       delete[] s2;
