@@ -173,7 +173,8 @@ def test_single_level_outputs(d, m, n):
 
 
 @pytest.mark.parametrize("d,m,n,alpha,variant", [(1, 127, 128, 1e-3, 0), (2, 63, 64, 1e-4, 1), (2, 100, 52, 1e-6, 0),
-                                                 (3, 15, 16, 1e-3, 0), (2, 255, 256, 1e-4, 0), (1, 1, 1, 0.5, 0)])
+                                                 (3, 15, 16, 1e-3, 0), (2, 255, 256, 1e-4, 0), (1, 1, 1, 0.5, 0),
+                                                 (3, 127, 128, 1e-5, 0)])
 def test_general_rhs_vs_oracle(d, m, n, alpha, variant):
     """General right-hand side in every block row (source terms / preconditioner use)."""
     say(f"[case] general rhs d={d} m={m} n={n}")
