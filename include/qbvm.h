@@ -160,9 +160,10 @@ int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta,
  * Step (b)): every later qbvm_solve on this plan uses the tridiagonal matrix A in
  * place of -Lap_h, A[i][i-1] = lower[i-1], A[i][i] = diag[i], A[i][i+1] = upper[i]
  * (HOST arrays of m-1, m, m-1 doubles, copied; lower/upper may be NULL when m = 1),
- * e.g. -(kappa u')' with variable kappa.  Step (b) is then a complex Thomas solve per
- * shift d_j/tau without pivoting: d_j/tau I + A must not need pivoting (A diagonally
- * dominant with positive diagonal, as diffusion operators are).  diag == NULL restores
+ * e.g. -(kappa u')' with variable kappa.  Step (b) is then the partitioned tridiagonal
+ * elimination (cyclic reduction between chunks) per shift d_j/tau, without pivoting:
+ * d_j/tau I + A must not need pivoting (A diagonally dominant with positive diagonal,
+ * as diffusion operators are).  diag == NULL restores
  * the Dirichlet stencil.  Synchronous (waits for the plan's stream).  While an
  * operator is set, qbvm_solve_general, qbvm_discrepancy, qbvm_choose_alpha and
  * qbvm_bisect_batched return QBVM_EUNSUPPORTED (they work in the sine basis).
@@ -178,7 +179,8 @@ int qbvm_plan_set_operator_1d(qbvm_plan_t p, const double* lower, const double* 
  * qbvm_solve is the case f = (f0, 0, ..., 0).  f is not modified unless y == f.
  * Asynchronous on the plan's stream; uses the plan's workspace and tables, so calls
  * on one plan are ordered by its stream.  QBVM_EUNSUPPORTED when one time signal and
- * its working copy exceed a workgroup's LDS. */
+ * its working copy exceed a workgroup's LDS, while a 1D operator is set, or on a 1D
+ * plan whose sine length exceeds the FFT core (see the size limits). */
 int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f, double* y);
 
 /* Solve `count` independent instances of possibly different grids in one
