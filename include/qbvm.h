@@ -74,6 +74,10 @@ extern "C" {
 #define QBVM_MODEL_FLOATS 6469
 #define QBVM_NFEAT        33
 
+/* A plan holds what one grid fixes (Section 2 discretisation, Section 3.3 factorisation):
+ * the stencil eigenvalues, the FFT factorisations and tables of the time length n+1
+ * (Steps a and c) and of the sine length 2(m+1) (the Step (b) diagonalisation in
+ * 2D/3D), and the solve workspace.  Opaque; created by qbvm_plan. */
 typedef struct qbvm_plan_s* qbvm_plan_t;
 
 /* Discretisation (Section 2): d in {1,2,3}; m >= 1 interior points per

@@ -425,3 +425,133 @@ def test_diffusion_operator_input():
     rs[1:] += lo
     rs[:-1] += up
     assert np.all(rs[1:-1] > -1e-9 * di[1:-1]) and np.all(np.abs(rs[1:-1]) <= 1e-9 * di[1:-1])
+
+
+# --------------------------------------------------------------------------
+# worked example on the 1D workload (m=127, n=128, T=1, alpha=1e-3, PinT-QBVM), noise free:
+# one sine mode at a time, the all-at-once rows of Section 3.1 restricted to that mode and
+# solved in 50-digit arithmetic (mpmath LU), with the mode's eigenvalue taken from the
+# three-point stencil applied to the sampled sine.  A route that shares nothing with the
+# oracle's closed form, checked against the worked-example digits and against the oracle.
+# --------------------------------------------------------------------------
+WORKED_1D = {  # mode k: (mu_k, r_k^n, y^0 / z_0 coefficient)
+    1: (9.869108962780114, 7.431972776244753e-5, 6.454602971541187e-2),
+    3: (88.78631555267900, 5.138040086577600e-30, 3.033720691295754e-27),
+}
+WORKED_ROOT = complex(1.0546953067069173, 0.025690528953764659)   # omega^{1/N_t}, omega = -1e3
+WORKED_D0 = complex(-0.054695306706917302, -0.025690528953764659)  # d_0 = 1 - omega^{1/N_t}
+
+
+def _mp_mode_gain(k, m=127, n=128, T=1, alpha="1e-3"):
+    import mpmath as mp
+    mp.mp.dps = 50
+    h = mp.mpf(1) / (m + 1)
+    tau = mp.mpf(T) / n
+    a = mp.mpf(alpha)
+    s = [mp.sin(k * mp.pi * i * h) for i in range(m + 2)]
+    i = 5
+    mu = -(s[i - 1] - 2 * s[i] + s[i + 1]) / (h ** 2 * s[i])   # stencil on the sampled sine
+    rn = (1 / (1 + tau * mu)) ** n                               # n backward-Euler steps
+    Nt = n + 1
+    A = mp.zeros(Nt, Nt)
+    f = mp.zeros(Nt, 1)
+    for t in range(Nt):
+        A[t, t] = 1 / tau + mu
+        if t == 0:
+            A[0, Nt - 1] = 1 / (a * tau)        # -(omega/tau), omega = -1/alpha
+            f[0] = rn / (tau * a)               # f0 = g/(tau alpha), g = r^n z0 with z0 = 1
+        else:
+            A[t, t - 1] = -1 / tau
+    y = mp.lu_solve(A, f)
+    return float(mu), float(rn), float(y[0]), [float(y[t]) for t in range(Nt)]
+
+
+def test_worked_example_config_1d():
+    m, n, T, alpha = 127, 128, 1.0, 1e-3
+    x = np.arange(1, m + 1) / (m + 1)
+    z0 = np.zeros(m)
+    g = np.zeros(m)
+    want_y = np.zeros((n + 1, m))
+    for k, coef in ((1, 1.0), (3, 0.5)):
+        mu, rn, gain, ylev = _mp_mode_gain(k)
+        w_mu, w_rn, w_gain = WORKED_1D[k]
+        assert abs(mu - w_mu) <= 1e-13 * w_mu
+        assert abs(rn - w_rn) <= 1e-13 * w_rn
+        assert abs(gain - w_gain) <= 1e-13 * w_gain
+        z0 += coef * np.sin(k * np.pi * x)
+        g += coef * rn * np.sin(k * np.pi * x)
+        want_y += coef * np.outer(ylev, np.sin(k * np.pi * x))
+    y = O.closed_form(g, 1, m, n, 1.0, T, alpha, O.PQ)
+    assert np.max(np.abs(y - want_y)) <= 1e-13 * np.max(np.abs(want_y))
+    assert np.max(np.abs(y[0] - WORKED_1D[1][2] * np.sin(np.pi * x))) <= 1e-13
+    # the discrete final state of the workload generator is the same g (noise free)
+    inst = W.config_1d(eps=0.0)
+    assert np.max(np.abs(inst.g - g)) <= 1e-13 * np.max(np.abs(g))
+    # omega^{1/N_t} and the first eigenvalue d_0 of C_omega (Section 3.3)
+    import mpmath as mp
+    mp.mp.dps = 50
+    root = mp.exp((mp.log(1000) + 1j * mp.pi) / (n + 1))
+    assert abs(complex(root ** (n + 1)) + 1000.0) < 1e-30
+    assert abs(complex(root) - WORKED_ROOT) < 1e-15 and abs(complex(1 - root) - WORKED_D0) < 1e-15
+    _, gam, Dv = O.circulant_factors(-1.0 / alpha, n + 1)
+    assert abs(gam[1] - WORKED_ROOT) < 1e-14 and abs(Dv[0] - WORKED_D0) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# features: against an explicit per-mode loop with the explicit sine matrix
+# Q[j][k] = sqrt(2/(m+1)) sin(pi j k/(m+1)) and brute-force bins; Parseval over the bins
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("d,m", [(1, 40), (2, 11), (3, 5)])
+def test_features_explicit_loop(d, m):
+    rng = np.random.default_rng(100 + d * m)
+    g = rng.standard_normal((m,) * d) * np.linspace(0.5, 2.0, m)   # not a pure mode: g != g_hat
+    L = 0.8
+    h = L / (m + 1)
+    j = np.arange(1, m + 1)
+    Q = math.sqrt(2.0 / (m + 1)) * np.sin(np.pi * np.outer(j, j) / (m + 1))
+    energy = [0.0] * 32
+    lo, hi = math.sqrt(d), m * math.sqrt(d)
+    for kk in np.ndindex(*(m,) * d):
+        # coefficient of mode kk: sum over nodes of g times the product of the 1D sines
+        c = 0.0
+        for p in np.ndindex(*(m,) * d):
+            w = 1.0
+            for ax in range(d):
+                w *= Q[p[ax], kk[ax]]
+            c += w * g[p]
+        rho = math.sqrt(sum((q + 1) ** 2 for q in kk))
+        b = min(int(math.floor((rho - lo) / (hi - lo) * 32)), 31)
+        energy[b] += c * c
+    want = [math.log10(h ** d * e + 1e-300) for e in energy] + [math.log10(0.03)]
+    got = O.features(g, 0.03, L=L)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+    # Parseval: the bins together hold h^d ||g||^2 (Q orthogonal)
+    tot = sum(10.0 ** v for v in got[:32] if v > -299)
+    assert abs(tot - h ** d * float(np.sum(g * g))) <= 1e-12 * h ** d * float(np.sum(g * g))
+
+
+# --------------------------------------------------------------------------
+# residual: the matrix-free rows against the assembled matrix on arbitrary vectors, and a
+# perturbed solution must be rejected
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("d,m,n,variant", [(1, 9, 6, O.PQ), (2, 5, 4, O.PM), (3, 3, 3, O.PQ)])
+def test_residual_detects_wrong_solutions(d, m, n, variant):
+    rng = np.random.default_rng(7 * d + m)
+    L, T, alpha = 1.0, 0.7, 1e-3
+    g = rng.standard_normal((m,) * d)
+    A = O.assemble_allatonce(d, m, n, L, T, alpha, variant)
+    f = O.rhs_allatonce(g, n, alpha, variant, T)
+    # arbitrary vector: the residual equals ||f - A v|| / ||f|| of the assembled rows
+    v = rng.standard_normal((n + 1,) + (m,) * d)
+    want = np.linalg.norm(f - A @ v.ravel()) / np.linalg.norm(f)
+    assert abs(O.residual(v, g, d, m, n, L, T, alpha, variant) - want) <= 1e-12 * want
+    y = O.solve_splu(g, d, m, n, L, T, alpha, variant)
+    assert O.residual(y, g, d, m, n, L, T, alpha, variant) < 1e-12
+    # wrong solutions: levels shifted by one, y^N dropped, one entry off by 1e-3 of the max
+    assert O.residual(np.roll(y, 1, axis=0), g, d, m, n, L, T, alpha, variant) > 1e-3
+    y2 = y.copy()
+    y2[n] = 0.0
+    assert O.residual(y2, g, d, m, n, L, T, alpha, variant) > 1e-3
+    y3 = y.copy()
+    y3.flat[y3.size // 2] += 1e-3 * np.max(np.abs(y))
+    assert O.residual(y3, g, d, m, n, L, T, alpha, variant) > 1e-6
