@@ -258,6 +258,22 @@ int qbvm_mlp_forward(const float* params, int B, const float* X, float* out, voi
 int qbvm_mlp_loss_grad(const float* params, int B, const float* X, const float* y,
                        float* grad, float* loss, void* hip_stream);
 
+/* Largest batch of qbvm_mlp_loss_grad_noalloc. */
+#define QBVM_NOALLOC_MAX_BATCH 16384
+
+/* qbvm_mlp_loss_grad without any allocation, for callers that cannot allocate (code
+ * under HIP graph capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc).  Same kernels, arguments and results as qbvm_mlp_loss_grad; the
+ * per-sample activations go to a fixed array of QBVM_NOALLOC_MAX_BATCH * 193 floats
+ * (12.1 MiB) that every GPU the library runs on holds until the process ends.  The
+ * first call on a device looks up that device's copy.  B > QBVM_NOALLOC_MAX_BATCH
+ * returns QBVM_EINVAL and enqueues nothing.  All calls on one GPU share the array: calls
+ * that overlap in time on one GPU (other streams, other threads) race and must be
+ * ordered by the caller, e.g. by issuing them on one stream.  Nothing in the array needs
+ * to start at zero (each call writes every entry it reads). */
+int qbvm_mlp_loss_grad_noalloc(const float* params, int B, const float* X, const float* y,
+                               float* grad, float* loss, void* hip_stream);
+
 /* One Adam step (bias-corrected, step >= 1) on n parameters. */
 int qbvm_adam_step(float* params, const float* grad, float* m, float* v, int n, int step,
                    float lr, float beta1, float beta2, float eps, void* hip_stream);

@@ -939,6 +939,16 @@ int qbvm_mlp_loss_grad(const float* params, int B, const float* X, const float* 
   return QBVM_OK;
 }
 
+int qbvm_mlp_loss_grad_noalloc(const float* params, int B, const float* X, const float* y, float* grad,
+                               float* loss, void* stream) {
+  if (!params || !X || !y || !grad || !loss || B < 1) return set_error(QBVM_EINVAL, "invalid argument");
+  if (B > QBVM_NOALLOC_MAX_BATCH)
+    return set_error(QBVM_EINVAL, "batch exceeds QBVM_NOALLOC_MAX_BATCH (" + std::to_string(QBVM_NOALLOC_MAX_BATCH) +
+                                      ") samples of the fixed scratch array");
+  HIP_TRY(launch_mlp_loss_grad_static(params, B, X, y, grad, loss, (hipStream_t)stream));
+  return QBVM_OK;
+}
+
 int qbvm_adam_step(float* params, const float* grad, float* m, float* v, int n, int step, float lr, float beta1,
                    float beta2, float eps, void* stream) {
   if (!params || !grad || !m || !v || n < 1 || step < 1) return set_error(QBVM_EINVAL, "invalid argument");

@@ -45,6 +45,9 @@ hipError_t launch_mlp_forward(const float* p, int B, const float* X, float* out,
 hipError_t launch_mlp_loss_grad(const float* p, int B, const float* X, const float* y,
                                 float* grad, float* loss, float* scratch, int nscratch_wg,
                                 hipStream_t s);
+// same kernels on the file-scope scratch array (B <= QBVM_NOALLOC_MAX_BATCH); allocates nothing
+hipError_t launch_mlp_loss_grad_static(const float* p, int B, const float* X, const float* y,
+                                       float* grad, float* loss, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int step, float lr,
                        float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_copy_scale(const double* in, double* out, long long n, double s, hipStream_t st);

@@ -16,6 +16,7 @@
 //     (k_tri1d), Step (c) as a length-N_t DFT per grid point (k_time1d).
 // Two real sequences are packed into one complex transform wherever the result
 // of each is real (sine transforms; time transforms after the inverse scaling).
+#include "../../include/qbvm.h"
 #include "qbvm_internal.hpp"
 #include "qbvm_bodies.hpp"
 #include "qbvm_bodies_p2.hpp"
@@ -827,6 +828,41 @@ hipError_t launch_mlp_loss_grad(const float* p, int B, const float* X, const flo
                      grad, loss);
   hipLaunchKernelGGL(k_mlp_w3_grad, dim3(1), dim3(64), 0, s, p, B, A1, R, grad);
   return hipGetLastError();
+}
+
+// Allocation-free loss and gradient (for callers that cannot allocate): the per-sample
+// activations a1, dH2, dH1 (64 floats each) and residuals of at most
+// QBVM_NOALLOC_MAX_BATCH samples live in this file-scope array, one copy per GPU for the
+// life of the process.  In host code the array's name is only a stand-in; kernels get the
+// device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) float mlp_scratch[(size_t)QBVM_NOALLOC_MAX_BATCH * (64 * 3 + 1)];
+
+static std::mutex g_mlp_scratch_mu;
+static std::map<int, float*> g_mlp_scratch_addr;  // device -> address of its mlp_scratch
+
+hipError_t mlp_scratch_address(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_mlp_scratch_mu);
+  auto it = g_mlp_scratch_addr.find(dev);
+  if (it == g_mlp_scratch_addr.end()) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(mlp_scratch));
+    if (e != hipSuccess) return e;
+    it = g_mlp_scratch_addr.emplace(dev, static_cast<float*>(ptr)).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
+hipError_t launch_mlp_loss_grad_static(const float* p, int B, const float* X, const float* y, float* grad,
+                                       float* loss, hipStream_t s) {
+  if (B < 1 || B > QBVM_NOALLOC_MAX_BATCH) return hipErrorInvalidValue;
+  float* ptr = nullptr;
+  const hipError_t e = mlp_scratch_address(&ptr);
+  if (e != hipSuccess) return e;
+  return launch_mlp_loss_grad(p, B, X, y, grad, loss, ptr, 0, s);
 }
 
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int step, float lr, float b1,

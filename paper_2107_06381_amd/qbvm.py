@@ -29,7 +29,7 @@ EXPORTS = [
     "qbvm_plan", "qbvm_plan_destroy", "qbvm_plan_set_stream", "qbvm_plan_workspace_bytes",
     "qbvm_solve", "qbvm_solve_general", "qbvm_solve_batched", "qbvm_batched_cache_clear", "qbvm_discrepancy",
     "qbvm_choose_alpha", "qbvm_bisect_batched", "qbvm_features", "qbvm_set_alpha_model",
-    "qbvm_mlp_forward", "qbvm_mlp_loss_grad", "qbvm_adam_step", "qbvm_strerror",
+    "qbvm_mlp_forward", "qbvm_mlp_loss_grad", "qbvm_mlp_loss_grad_noalloc", "qbvm_adam_step", "qbvm_strerror",
     "qbvm_last_error", "qbvm_version", "qbvm_profile_enable", "qbvm_profile_reset",
     "qbvm_profile_count", "qbvm_profile_get", "qbvm_plan_autotune", "qbvm_plan_get_variants",
     "qbvm_plan_set_variants", "qbvm_plan_set_operator_1d",
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qbvm_set_alpha_model": (i, [vp, ctypes.POINTER(ctypes.c_float)]),
         "qbvm_mlp_forward": (i, [vp, i, vp, vp, vp]),
         "qbvm_mlp_loss_grad": (i, [vp, i, vp, vp, vp, vp, vp]),
+        "qbvm_mlp_loss_grad_noalloc": (i, [vp, i, vp, vp, vp, vp, vp]),
         "qbvm_adam_step": (i, [vp, vp, vp, vp, i, i, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                ctypes.c_float, vp]),
         "qbvm_strerror": (ctypes.c_char_p, [i]),
@@ -329,6 +330,22 @@ def mlp_loss_grad(params, X, y, grad=None, loss=None, stream=None):
                                      _dev_tensor(grad, MLP_PARAMS, torch.float32, "grad"),
                                      _dev_tensor(loss, 1, torch.float32, "loss"),
                                      ctypes.c_void_p(_stream(stream))))
+    return loss, grad
+
+
+NOALLOC_MAX_BATCH = 16384
+
+
+def mlp_loss_grad_noalloc(params, X, y, grad, loss, stream=None):
+    """qbvm_mlp_loss_grad_noalloc: the caller passes grad and loss; the library allocates nothing."""
+    import torch
+    B = X.shape[0]
+    _check(load().qbvm_mlp_loss_grad_noalloc(_dev_tensor(params, MLP_PARAMS, torch.float32, "params"), B,
+                                             _dev_tensor(X, B * NFEAT, torch.float32, "X"),
+                                             _dev_tensor(y, B, torch.float32, "y"),
+                                             _dev_tensor(grad, MLP_PARAMS, torch.float32, "grad"),
+                                             _dev_tensor(loss, 1, torch.float32, "loss"),
+                                             ctypes.c_void_p(_stream(stream))))
     return loss, grad
 
 
