@@ -1,11 +1,13 @@
 """Benchmark of the PinT-QBVM all-at-once solve on one MI355X.
 
-Workload: 2D, Omega=(0,1)^2, m=255 interior points per dimension (5-point
-Laplacian), n=256 backward-Euler steps (N_t = 257), T=1, alpha=1e-4, PinT-QBVM,
-FP64; initial datum = 64 random lowest sine modes, 0.5% relative Gaussian noise
-(seeded, synthetic).  One step = one full solve (every level, n+1 = 257 levels of
-255^2 values), inputs resident in HBM.  Metric: solve throughput in Munknowns/s
-on the n*m^d basis.
+Headline workload (the largest single-GPU configuration): 3D, Omega=(0,1)^3, m=127
+interior points per dimension (7-point Laplacian), n=128 backward-Euler steps
+(N_t = 129), T=0.5, alpha=1e-5, PinT-QBVM, FP64; initial datum = Gaussian bump
+(centre (0.4,0.5,0.6), width 0.1), 0.1% relative Gaussian noise (seeded,
+synthetic).  One step = one full solve (every level: 129 levels of 127^3 values,
+2.1 GB), inputs resident in HBM.  Metric: solve throughput in Munknowns/s on the
+n*m^d basis.  Side sections: the 2D workload (m=255, n=256), alpha choice,
+batched solves, general right-hand side, 1D operator.
 
 Prints one JSON line.  --gpus above 1 is refused: this build measures one GPU.
 """
@@ -48,69 +50,142 @@ def read_traffic(kernel: str, workload: str, variant: int):
     return entry.get("hbm_bytes_per_launch") if entry else None
 
 
+def cpu_share() -> int:
+    """Host threads this process may use (its affinity mask, at most 16: one GPU's share of the box)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return "unknown"
+
+
 def cpu_baseline(inst, alpha, budget_s: float):
-    """The oracle's closed form (as it stands) on the host cores, repeated up to ~budget_s."""
+    """The oracle's closed form (as it stands: orthonormal DST-I by scipy.fft, the per-mode
+    formula, every level) on the host cores, repeated until ~budget_s has passed."""
+    import scipy.fft
+
     from oracle import qbvm_oracle as O
     d, m, n = inst.d, inst.m, inst.n
+    workers = cpu_share()
     runs = 0
     t0 = time.perf_counter()
-    c0 = time.process_time()
-    while True:
-        O.closed_form(inst.g_delta, d, m, n, inst.L, inst.T, alpha, O.PQ)
-        runs += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
+    with scipy.fft.set_workers(workers):
+        while True:
+            O.closed_form(inst.g_delta, d, m, n, inst.L, inst.T, alpha, O.PQ)
+            runs += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
     wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
     value = runs * n * m ** d / wall / 1e6
-    return {"value": round(value, 3), "unit": "Munknowns/s", "cores": max(1, round(cpu / wall)),
-            "kind": "oracle",
-            "sample": f"{runs} full closed-form solves of the same 2D m={m} n={n} instance "
-                      f"(orthonormal DST-I via scipy, per-mode formula, all {n + 1} levels), {wall:.1f} s"}
+    return {"value": round(value, 3), "unit": "Munknowns/s", "cores": workers, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "sample": f"{runs} full closed-form solves of the {d}D m={m} n={n} workload instance (orthonormal "
+                      f"DST-I via scipy.fft with workers={workers}, per-mode formula, all {n + 1} levels), "
+                      f"{wall:.1f} s"}
 
 
-def solve_3d_bench(steps: int):
-    """3D m=127, n=128, T=0.5, alpha=1e-5 full solve (2.1 GB output): time and per-kernel rooflines."""
+def copy_ceiling_gbps(numel: int, reps: int = 5) -> float:
+    """Plain device-to-device copy of an FP64 array of this size: bytes read + written per second."""
+    import torch
+    src = torch.ones(numel, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = 1e30
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * 8.0 * numel / best / 1e9
+
+
+ROLE_OF_KERNEL = {"dst_rows": "rows", "dst_cols": "cols", "time_spectral": "time"}
+
+
+def solve_bench(inst, steps: int, warmup: int, tag: str, parity_levels=None):
+    """Time `steps` full solves (every level) of one workload instance on the current stream,
+    then the per-kernel durations (HIP events around each launch on the plan's stream) and the
+    roofline of the kernel with the largest share of time."""
+    import numpy as np
     import torch
 
-    from paper_2107_06381_amd import qbvm, workloads as W
+    from paper_2107_06381_amd import qbvm
 
-    inst = W.config_3d()
+    d, m, n = inst.d, inst.m, inst.n
     dev = torch.device("cuda:0")
     g = torch.from_numpy(inst.g_delta).to(dev)
-    plan = qbvm.Plan(3, 127, 128, 1.0, 0.5)
-    tune = plan.autotune()
-    y = torch.empty((129, 127, 127, 127), dtype=torch.float64, device=dev)
-    for _ in range(2):
-        plan.solve(1e-5, qbvm.QBVM_PQ, g, y)
+    plan = qbvm.Plan(d, m, n, inst.L, inst.T)
+    tune = plan.autotune()  # kernel-variant choice, excluded from the timed region
+    y = torch.empty((n + 1,) + (m,) * d, dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        plan.solve(inst.alpha, qbvm.QBVM_PQ, g, y)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        plan.solve(1e-5, qbvm.QBVM_PQ, g, y)
+        plan.solve(inst.alpha, qbvm.QBVM_PQ, g, y)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    parity = None
+    if parity_levels is not None:
+        from oracle import qbvm_oracle as O
+        yc = O.closed_form(inst.g_delta, d, m, n, inst.L, inst.T, inst.alpha, O.PQ, levels=parity_levels)
+        yl = y[parity_levels].cpu().numpy()
+        parity = float(max(np.linalg.norm(yl[i] - yc[i]) / np.linalg.norm(yc[i])
+                           for i in range(len(parity_levels))))
     qbvm.profile_reset()
     qbvm.profile_enable(True)
     for _ in range(steps):
-        plan.solve(1e-5, qbvm.QBVM_PQ, g, y)
+        plan.solve(inst.alpha, qbvm.QBVM_PQ, g, y)
     torch.cuda.synchronize()
     rep = qbvm.profile_report()
     qbvm.profile_enable(False)
-    kernels = {k: {"launches_per_step": r["launches"] / steps, "avg_us": round(r["total_ms"] / r["launches"] * 1e3, 1),
-                   "hbm_frac": round(r["bytes"] / (r["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-               for k, r in rep.items()}
+    kernels = {}
+    for k, r in rep.items():
+        avg_ms = r["total_ms"] / r["launches"]
+        kernels[k] = {"launches_per_step": r["launches"] / steps, "avg_us": round(avg_ms * 1e3, 2),
+                      "GBps": round(r["bytes"] / (r["total_ms"] * 1e-3) / 1e9, 1),
+                      "TFLOPs": round(r["flops"] / (r["total_ms"] * 1e-3) / 1e12, 2)}
+    dom = max(rep, key=lambda k: rep[k]["total_ms"])
+    r = rep[dom]
+    avg_s = r["total_ms"] / r["launches"] * 1e-3
+    bytes_per_launch = r["bytes"] / r["launches"]
+    achieved = bytes_per_launch / avg_s / 1e9
+    role = ROLE_OF_KERNEL.get(dom)
+    traffic = read_traffic(dom, tag, tune["variants"][role]) if role else None
     step_bytes = sum(v["bytes"] for v in rep.values()) / steps
+    numel = y.numel()
     del y
     plan.close()
     torch.cuda.empty_cache()
-    unk = 128 * 127 ** 3
-    return {"workload": "3D PinT-QBVM, m=127 (7-point), n=128 (N_t=129), T=0.5, alpha=1e-5, Gaussian bump, 0.1% noise",
-            "ms_per_solve": round(ms, 4), "Munknowns_per_s": round(unk / (ms * 1e-3) / 1e6, 1),
+    copy = copy_ceiling_gbps(numel)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2),
+                "launch_timing": "HIP events around each launch on the plan's stream",
+                "copy_ceiling_GBps": round(copy, 1), "frac_of_copy": round(achieved / copy, 4)}
+    return {"ms": ms, "value": n * m ** d / (ms * 1e-3) / 1e6, "kernels": kernels, "roofline": roofline,
             "step_hbm_roofline_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "kernels": kernels, "autotune": tune}
+            "step_bytes_per_unknown": round(step_bytes / ((n + 1) * m ** d), 2),
+            "autotune": tune, "parity_rel_err": parity}
 
 
 def alpha_choice_bench(train_count: int, test_count: int, lat_count: int, steps: int):
@@ -319,31 +394,147 @@ def operator_1d_bench(steps: int = 20):
             "config_1d_m127_n128_us_per_solve": round(us1, 2)}
 
 
+# kernels of each benchmarked workload: sine-transform length and the time kernel's symbol prefix
+TRAFFIC_WORKLOADS = {
+    "3d_m127_n128": {"sine_n": 256, "time_prefix": "k_time_gt<3, 43,", "title": "3D PinT-QBVM solve, m=127, n=128 (N_t=129)",
+                     "flags": "--no-2d"},
+    "2d_m255_n256": {"sine_n": 512, "time_prefix": "k_time_p2<256,", "title": "2D PinT-QBVM solve, m=255, n=256 (N_t=257)",
+                     "flags": ""},
+}
+
+
+def _read_pmc(directory: str, counter: str):
+    """{dispatch id: (kernel name, counter value)} from the rocprofv3 counter CSVs under directory."""
+    import csv
+    import glob
+    out = {}
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *counter_collection.csv under {directory}")
+    for path in files:
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                key = (path, row["Dispatch_Id"])
+                name, val = out.get(key, (row["Kernel_Name"], 0.0))
+                out[key] = (name, val + float(row["Counter_Value"]))
+    return out
+
+
+def _kernel_role(name: str, w: dict):
+    """(role, variant) of a solve kernel of workload w from its symbol, else None."""
+    import re
+    n = w["sine_n"]
+    mm = re.search(r"k_dst_(rows|cols)_p2<(\d+), (\d+)", name)
+    if mm and int(mm.group(2)) == n:
+        var = int(mm.group(3))
+        if var == 2 and ("rows" in mm.group(1) or "false" in name):
+            return ("dst_input", var)
+        return ("dst_" + mm.group(1), var)
+    if w["time_prefix"] in name:
+        mm = re.search(r"k_time_(?:gt<\d+, \d+|p2<\d+), (\d+)", name)
+        if mm:
+            return ("time_spectral", int(mm.group(1)))
+    return None
+
+
+def write_traffic_summary(fetch_dir: str, write_dir: str, tag: str, out_dir: str = None):
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by what they read for the 1 GiB
+    reference copy of --copy-probe and write profiles/<role>_<tag>_traffic.json (bytes per
+    launch per kernel variant, keyed to the current kernel sources) and a Markdown table."""
+    import statistics
+    w = TRAFFIC_WORKLOADS[tag]
+    fetch = _read_pmc(fetch_dir, "FETCH_SIZE")
+    write = _read_pmc(write_dir, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+
+    def copy_kib(rec):
+        # the reference copies are the first three copy dispatches of the run (--copy-probe runs first)
+        ids = sorted((k for k, (nm, _) in rec.items() if "copy" in nm.lower()), key=lambda k: (k[0], int(k[1])))
+        vals = [rec[k][1] for k in ids[:3]]
+        if not vals:
+            raise SystemExit("reference copy not found: run the profiled command with --copy-probe")
+        return statistics.median(vals)
+
+    fscale = gib_kib / copy_kib(fetch)
+    wscale = gib_kib / copy_kib(write)
+
+    def per_kernel(rec):
+        d = {}
+        for nm, v in rec.values():
+            d.setdefault(nm, []).append(v)
+        return d
+
+    fk, wk = per_kernel(fetch), per_kernel(write)
+    roles = {}
+    rows = []
+    for nm in sorted(set(fk) & set(wk)):
+        rv = _kernel_role(nm, w)
+        if rv is None:
+            continue
+        role, var = rv
+        fm, wm = statistics.median(fk[nm]), statistics.median(wk[nm])
+        hbm = (fm * fscale + wm * wscale) * 1024.0
+        roles.setdefault(role, {})[str(var)] = {"kernel": nm, "dispatches": len(fk[nm]), "fetch_kib_median": fm,
+                                                "write_kib_median": wm, "hbm_bytes_per_launch": round(hbm)}
+        rows.append((nm, role, len(fk[nm]), fm, wm, fm * fscale * 1024 / 1e6, wm * wscale * 1024 / 1e6))
+    prof = out_dir or os.path.join(ROOT, "profiles")
+    cmd = ("rocprofv3 --pmc {c} --output-format csv -d <{d}> -o {o} -- python3 bench.py --steps 3 --warmup 1 "
+           "--no-cpu {flags} --no-alpha --no-batched --no-general --no-operator --copy-probe")
+    cmds = [cmd.format(c="FETCH_SIZE", d="fetch_dir", o="fetch", flags=w["flags"]).replace("  ", " "),
+            cmd.format(c="WRITE_SIZE", d="write_dir", o="write", flags=w["flags"]).replace("  ", " "),
+            f"python3 bench.py --traffic-summary <fetch_dir> <write_dir> {tag}"]
+    for role, per in roles.items():
+        with open(os.path.join(prof, f"{role}_{tag}_traffic.json"), "w") as f:
+            json.dump({"source_hash": source_hash(), "fetch_scale": fscale, "write_scale": wscale,
+                       "per_variant": per, "commands": cmds}, f, indent=1)
+    with open(os.path.join(prof, f"traffic_{tag}.md"), "w") as f:
+        f.write(f"# HBM traffic per launch: {w['title']}\n\n")
+        f.write("Commands (repository root, one MI355X; `cd /tmp && export TMPDIR=/tmp` first for the profiler):\n\n")
+        for c in cmds:
+            f.write(f"    {c}\n")
+        f.write(f"\n`--copy-probe` first runs a plain 1 GiB device-to-device copy three times, the reference "
+                f"kernel; its counters give the scale factors {fscale:.3f} (FETCH_SIZE) and {wscale:.3f} (WRITE_SIZE).  Median over the "
+                f"dispatches of each kernel (the autotuner runs every variant; the kept one has the most "
+                f"dispatches).  Kernel sources hash {source_hash()}.\n\n")
+        f.write("| kernel | role | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled MB read | scaled MB written |\n")
+        f.write("|---|---|---|---|---|---|---|\n")
+        for nm, role, nd, fm, wm, rmb, wmb in rows:
+            f.write(f"| `{nm}` | {role} | {nd} | {fm:.0f} | {wm:.0f} | {rmb:.1f} | {wmb:.1f} |\n")
+    print(f"wrote {len(roles)} traffic records for {tag}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D solve section")
     ap.add_argument("--no-alpha", action="store_true", help="skip the learned/bisection alpha-choice section")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched section")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 3D solve section")
     ap.add_argument("--no-general", action="store_true", help="skip the general right-hand-side section")
     ap.add_argument("--no-operator", action="store_true", help="skip the 1D variable-coefficient section")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for counter calibration)")
     ap.add_argument("--alpha-train", type=int, default=20000)
     ap.add_argument("--alpha-test", type=int, default=2000)
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "WORKLOAD"),
+                    help="write profiles/<kernel>_<WORKLOAD>_traffic.json from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of this script with --copy-probe, then exit")
     args = ap.parse_args()
+    if args.traffic_summary:
+        write_traffic_summary(*args.traffic_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_2107_06381_amd import qbvm, workloads as W
+    from paper_2107_06381_amd import workloads as W
 
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
@@ -352,103 +543,58 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+        torch.cuda.empty_cache()
 
-    d, m, n, alpha = 2, 255, 256, 1e-4
-    inst = W.config_2d()
-    dev = torch.device("cuda:0")
-    g = torch.from_numpy(inst.g_delta).to(dev)
-    plan = qbvm.Plan(d, m, n, 1.0, 1.0)
-    tune = plan.autotune()  # kernel-variant choice, excluded from the timed region
-    y = torch.empty((n + 1, m, m), dtype=torch.float64, device=dev)
-    for _ in range(args.warmup):
-        plan.solve(alpha, qbvm.QBVM_PQ, g, y)
-    torch.cuda.synchronize()
-
-    # timed region: K solves on the current stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        plan.solve(alpha, qbvm.QBVM_PQ, g, y)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    unknowns = n * m ** d
-    value = unknowns / (ms * 1e-3) / 1e6
-
-    # parity of the benchmarked output on sampled levels (the oracle is test
-    # infrastructure; only the CPU-baseline leg and this sample check call it)
-    parity = None
-    cpu = None
-    if not args.no_cpu:
-        from oracle import qbvm_oracle as O
-        levels = [0, n // 2, n]
-        yc = O.closed_form(inst.g_delta, d, m, n, 1.0, 1.0, alpha, O.PQ, levels=levels)
-        yl = y[levels].cpu().numpy()
-        parity = float(max(np.linalg.norm(yl[i] - yc[i]) / np.linalg.norm(yc[i]) for i in range(3)))
-        cpu = cpu_baseline(inst, alpha, args.cpu_budget)
-
-    # per-kernel durations: HIP events around each launch on the plan's stream
-    qbvm.profile_reset()
-    qbvm.profile_enable(True)
-    for _ in range(args.steps):
-        plan.solve(alpha, qbvm.QBVM_PQ, g, y)
-    torch.cuda.synchronize()
-    rep = qbvm.profile_report()
-    qbvm.profile_enable(False)
-    kernels = {}
-    for k, r in rep.items():
-        avg_ms = r["total_ms"] / r["launches"]
-        kernels[k] = {"launches_per_step": r["launches"] / args.steps, "avg_us": round(avg_ms * 1e3, 2),
-                      "GBps": round(r["bytes"] / (r["total_ms"] * 1e-3) / 1e9, 1),
-                      "TFLOPs": round(r["flops"] / (r["total_ms"] * 1e-3) / 1e12, 2)}
-    dom = max(rep, key=lambda k: rep[k]["total_ms"])
-    r = rep[dom]
-    avg_s = r["total_ms"] / r["launches"] * 1e-3
-    bytes_per_launch = r["bytes"] / r["launches"]
-    achieved = bytes_per_launch / avg_s / 1e9
-    workload = "2d_m255_n256"
-    role_variant = {"dst_rows": "rows", "dst_cols": "cols", "time_spectral": "time"}.get(dom)
-    traffic = read_traffic(dom, workload, tune["variants"][role_variant]) if role_variant else None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
-    step_bytes = sum(v["bytes"] for v in rep.values()) / args.steps
-    del y
-    torch.cuda.empty_cache()
-    solve3d = None if args.no_3d else solve_3d_bench(5)
+    # headline: the largest single-GPU workload, 3D m=127, n=128 (N_t=129), T=0.5, alpha=1e-5
+    inst = W.config_3d()
+    head = solve_bench(inst, args.steps, args.warmup, "3d_m127_n128",
+                       parity_levels=None if args.no_cpu else [0, 1, 64, 128])
+    cpu = None if args.no_cpu else cpu_baseline(inst, inst.alpha, args.cpu_budget)
+    del inst
+    solve2d = None
+    if not args.no_2d:
+        i2 = W.config_2d()
+        r2 = solve_bench(i2, args.steps, args.warmup, "2d_m255_n256",
+                         parity_levels=None if args.no_cpu else [0, 128, 256])
+        solve2d = {"workload": "2D PinT-QBVM, m=255 (5-point), n=256 (N_t=257), T=1, alpha=1e-4, "
+                               "64 random sine modes, 0.5% noise, every level output",
+                   "ms_per_solve": round(r2["ms"], 5), "Munknowns_per_s": round(r2["value"], 1),
+                   "roofline": r2["roofline"], "step_hbm_roofline_frac": r2["step_hbm_roofline_frac"],
+                   "step_bytes_per_unknown": r2["step_bytes_per_unknown"], "kernels": r2["kernels"],
+                   "autotune": r2["autotune"], "parity_rel_err": r2["parity_rel_err"]}
     alpha = None if args.no_alpha else alpha_choice_bench(args.alpha_train, args.alpha_test, 200, 3000)
     batched = None if args.no_batched else batched_bench()
     general = None if args.no_general else general_rhs_bench()
     operator_1d = None if args.no_operator else operator_1d_bench()
+    n, m = 128, 127
     line = {
         "metric": "PinT solve Munknowns/s (n*m^d, FP64)",
-        "value": round(value, 2),
+        "value": round(head["value"], 2),
         "unit": "Munknowns/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 5),
+        "ms_per_step": round(head["ms"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "2D PinT-QBVM all-at-once solve, m=255 (5-point), n=256 (N_t=257), T=1, "
-                               "alpha=1e-4, 64 random sine modes, 0.5% noise, every level output",
-                   "unknowns_n_md": unknowns, "unknowns_true": (n + 1) * m ** d},
-        "roofline": roofline,
-        "step_hbm_roofline_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "kernels": kernels,
-        "autotune": tune,
-        "solve_3d": solve3d,
+        "config": {"workload": "3D PinT-QBVM all-at-once solve, m=127 (7-point), n=128 (N_t=129), T=0.5, "
+                               "alpha=1e-5, Gaussian bump, 0.1% noise, every level output",
+                   "unknowns_n_md": n * m ** 3, "unknowns_true": (n + 1) * m ** 3},
+        "roofline": head["roofline"],
+        "cpu_baseline": cpu,
+        "step_hbm_roofline_frac": head["step_hbm_roofline_frac"],
+        "step_bytes_per_unknown": head["step_bytes_per_unknown"],
+        "kernels": head["kernels"],
+        "autotune": head["autotune"],
+        "parity_rel_err": head["parity_rel_err"],
+        "solve_2d": solve2d,
         "alpha_choice": alpha,
         "batched": batched,
         "general_rhs": general,
         "operator_1d": operator_1d,
-        "parity_rel_err": parity,
-        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

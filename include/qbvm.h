@@ -111,9 +111,11 @@ typedef struct {
 
 /* ---------------------------------------------------------------- plans ---- */
 
-/* Create a plan for one grid, bound to hip_stream (a hipStream_t; NULL = the
- * default stream) on the current HIP device.  Builds the FFT factorisations
- * along time (length n+1) and for the sine transforms (length 2(m+1)), uploads
+/* Create a plan for one grid (the discretisation of Section 2), bound to hip_stream
+ * (a hipStream_t; NULL = the default stream) on the current HIP device.  Builds the
+ * FFT factorisations along time (length n+1, the diagonalisation of the
+ * omega-circulant time matrix in Section 3.3) and for the sine transforms (length
+ * 2(m+1), the eigenbasis of the Dirichlet stencil used in Step (b)), uploads
  * twiddle, Rader/Bluestein and eigenvalue tables, and allocates the workspace.
  * *out receives the plan; on error *out is NULL. */
 int qbvm_plan(qbvm_plan_t* out, const qbvm_grid* grid, void* hip_stream);

@@ -4,6 +4,7 @@ Tolerance: relative 2-norm 1e-8 on the full solution and, separately, on y^0 and
 y^N (the bar the design targets); measured errors are ~1e-13.
 """
 import math
+import os
 import sys
 
 import numpy as np
@@ -117,24 +118,31 @@ def test_config_2d_full():
     assert O.residual(y, inst.g_delta, 2, 255, 256, 1.0, 1.0, 1e-4, O.PQ) < 1e-8
 
 
-def test_config_3d_sampled_levels():
-    """3D, m=127, n=128, T=0.5, alpha=1e-5 (2.1 GB output), autotuned variants: levels 0, 1, 64, n
-    against the closed form."""
-    say("[case] config 3d")
+def test_config_3d_every_level():
+    """3D, m=127, n=128, T=0.5, alpha=1e-5 (2.1 GB output), autotuned variants (the bench's launch
+    configuration): every level against the closed form, in chunks of 16 levels."""
+    import scipy.fft
+    say("[case] config 3d, every level")
     inst = W.config_3d()
     m, n = 127, 128
     p = qbvm.Plan(3, m, n, 1.0, 0.5)
     say("variants", p.autotune()["variants"])
     y = p.solve(1e-5, 0, to_dev(inst.g_delta))
     torch.cuda.synchronize()
-    levels = [0, 1, 64, n]
-    yl = y[levels].cpu().numpy()
     assert bool(torch.isfinite(y).all())
-    del y
     p.close()
-    yc = O.closed_form(inst.g_delta, 3, m, n, 1.0, 0.5, 1e-5, O.PQ, levels=levels)
-    for i, t in enumerate(levels):
-        assert rel(yl[i], yc[i]) < TOL, t
+    worst = 0.0
+    with scipy.fft.set_workers(min(16, len(os.sched_getaffinity(0)))):
+        for c0 in range(0, n + 1, 16):
+            levels = list(range(c0, min(n + 1, c0 + 16)))
+            yl = y[levels].cpu().numpy()
+            yc = O.closed_form(inst.g_delta, 3, m, n, 1.0, 0.5, 1e-5, O.PQ, levels=levels)
+            for i, t in enumerate(levels):
+                e = rel(yl[i], yc[i])
+                worst = max(worst, e)
+                assert e < TOL, (t, e)
+    say("worst level rel err", worst)
+    del y
 
 
 @pytest.mark.parametrize("d,m,n,levels", [
@@ -463,6 +471,38 @@ def test_batched_matches_single_and_oracle():
     for i, (d, m, n) in enumerate(specs):
         yc = O.closed_form(ref[i], d, m, n, 1.0, 1.0, alphas2[i], variants[i])
         assert rel(ys[i].cpu().numpy(), yc) < TOL
+    qbvm.batched_cache_clear()
+
+
+def test_batched_workload_512_instances():
+    """The 512-instance batched workload (256 1D m in [63,1023] + 256 2D m in [63,255], n in
+    [64,512], alpha in [1e-6,1e-1]), every level of every instance: bitwise equal to its own
+    qbvm_solve, and levels 0, n/2 and n against the closed form."""
+    say("[case] batched workload, 512 instances")
+    insts = W.config_batched()
+    grids = [(i.d, i.m, i.n, i.L, i.T) for i in insts]
+    gs = [to_dev(i.g_delta) for i in insts]
+    ys = [torch.empty((i.n + 1,) + (i.m,) * i.d, dtype=torch.float64, device=DEV) for i in insts]
+    qbvm.solve_batched(grids, [i.alpha for i in insts], [0] * len(insts), gs, ys)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k, inst in enumerate(insts):
+        p = qbvm.Plan(*grids[k])
+        y1 = p.solve(inst.alpha, 0, gs[k])
+        torch.cuda.synchronize()
+        assert torch.equal(ys[k], y1), k
+        del y1
+        p.close()
+        lv = [0, inst.n // 2, inst.n]
+        yc = O.closed_form(inst.g_delta, inst.d, inst.m, inst.n, 1.0, 1.0, inst.alpha, O.PQ, levels=lv)
+        yl = ys[k][lv].cpu().numpy()
+        w_abs = omega_abs(inst.alpha, 0, 1.0 / inst.n)
+        for j, t in enumerate(lv):
+            # strongly damped levels: the attainable accuracy of Step (c) (see tests/parity_util.py)
+            ok, e = level_ok(yl[j], yc[j], yc[0], t, inst.n + 1, w_abs)
+            worst = max(worst, e)
+            assert ok, (k, t, e)
+    say("worst sampled-level rel err", worst)
     qbvm.batched_cache_clear()
 
 
