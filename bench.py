@@ -188,14 +188,20 @@ def solve_bench(inst, steps: int, warmup: int, tag: str, parity_levels=None):
             "autotune": tune, "parity_rel_err": parity}
 
 
-def alpha_choice_bench(train_count: int, test_count: int, lat_count: int, steps: int):
-    """Learned vs bisection alpha choice on 2D m=127, n=128, T=1 (noise 0.1%..5%)."""
+ALPHA_GRID_LOG10 = [x / 4.0 for x in range(-64, 1)]  # 1e-16 .. 1, four points per decade
+
+
+def alpha_config_bench(T: float, train_count: int, test_count: int, steps: int, grid_count: int):
+    """Learned vs bisection alpha choice on 2D m=127, n=128 at final time T (noise 0.1%..5%):
+    labels, training, then on the held-out set the reconstruction error of the learned alpha,
+    of alpha_DP and of the paper's a-priori alpha = delta, the error over a grid of alpha on
+    `grid_count` held-out instances, and per-call latencies of both modes on every held-out
+    instance (timed in the library)."""
     import numpy as np
-    import torch
 
     from paper_2107_06381_amd import alpha_model as AM, qbvm
 
-    plan = qbvm.Plan(2, 127, 128, 1.0, 1.0)
+    plan = qbvm.Plan(2, 127, 128, 1.0, T)
     t0 = time.perf_counter()
     train_ds = AM.make_dataset(plan, seed=4, count=train_count)
     t_label = time.perf_counter() - t0
@@ -209,29 +215,49 @@ def alpha_choice_bench(train_count: int, test_count: int, lat_count: int, steps:
     AM.choose_all(plan, test_ds, idx[:20], use_learned=True)  # warm-up
     AM.choose_all(plan, test_ds, idx[:20], use_learned=False)
     a_l, lat_l, fb = AM.choose_all(plan, test_ds, idx, use_learned=True)
-    li = idx[:lat_count]
-    a_b, lat_b, _ = AM.choose_all(plan, test_ds, li, use_learned=False)
+    a_b, lat_b, _ = AM.choose_all(plan, test_ds, idx, use_learned=False)
     e_l = AM.reconstruction_errors(plan, test_ds, a_l, idx)
     e_dp = AM.reconstruction_errors(plan, test_ds, test_ds.alpha_dp, idx)
     e_prior = AM.reconstruction_errors(plan, test_ds, test_ds.delta, idx)
     ok = test_ds.hits == 0
     r = e_l[ok] / e_dp[ok]
+    rp = e_prior[ok] / e_dp[ok]
+    gi = idx[ok][:grid_count]
+    grid = [10.0 ** g for g in ALPHA_GRID_LOG10]
+    curve = AM.error_curve(plan, test_ds, gi, grid) / e_dp[gi][:, None]
+    med = np.median(curve, 0)
+    band = [ALPHA_GRID_LOG10[i] for i in range(len(grid)) if med[i] <= 1.05]
+    plan.close()
     return {
-        "workload": f"2D m=127 n=128 T=1, {train_count} training / {test_count} held-out instances, "
+        "workload": f"2D m=127 n=128 T={T}, {train_count} training / {test_count} held-out instances, "
                     "labels: 30-step discrepancy bisection (tau=1.1) on [1e-20, 1]",
         "label_gen_s": round(t_label, 2), "train_s": round(t_train, 2), "train_steps": steps,
         "final_train_mse_std": round(hist[-1][1], 6) if hist else None,
+        "alpha_dp_log10_median": round(float(np.median(np.log10(test_ds.alpha_dp[ok]))), 3),
         "error_ratio_learned_over_dp": {"mean": round(float(r.mean()), 5), "median": round(float(np.median(r)), 5),
                                         "p95": round(float(np.quantile(r, 0.95)), 5)},
-        "error_ratio_alpha_eq_delta_over_dp": round(float(np.mean(e_prior[ok] / e_dp[ok])), 4),
+        "error_ratio_alpha_eq_delta_over_dp": {"mean": round(float(rp.mean()), 4),
+                                               "median": round(float(np.median(rp)), 4)},
+        "error_curve": {"instances": int(len(gi)), "log10_alpha": ALPHA_GRID_LOG10,
+                        "median_ratio_to_dp": [round(float(x), 4) for x in med],
+                        "best_grid_ratio_median": round(float(np.median(curve.min(1))), 4),
+                        "log10_alpha_within_5pct": [min(band), max(band)] if band else None},
         "fallback_rate": round(float(fb.mean()), 4),
         "latency_us": {"learned_mean": round(float(lat_l.mean() * 1e6), 1),
                        "learned_median": round(float(np.median(lat_l) * 1e6), 1),
                        "bisection_mean": round(float(lat_b.mean() * 1e6), 1),
                        "bisection_median": round(float(np.median(lat_b) * 1e6), 1),
                        "speedup_median": round(float(np.median(lat_b) / np.median(lat_l)), 2),
-                       "bisection_sample": int(lat_count)},
+                       "instances": int(test_count),
+                       "timing": "steady clock around each qbvm_choose_alpha call inside qbvm_choose_alpha_each"},
     }
+
+
+def alpha_choice_bench(train_count: int, test_count: int, steps: int):
+    """The learned-alpha workload (T=1) and the same family at T=0.1, where the error has a
+    pronounced minimum in alpha (the T=1 error curve is flat over several decades)."""
+    return {"T1": alpha_config_bench(1.0, train_count, test_count, steps, 400),
+            "T0.1": alpha_config_bench(0.1, train_count, test_count, steps, 400)}
 
 
 def batched_bench(reps: int = 3):
@@ -562,7 +588,7 @@ def main():
                    "roofline": r2["roofline"], "step_hbm_roofline_frac": r2["step_hbm_roofline_frac"],
                    "step_bytes_per_unknown": r2["step_bytes_per_unknown"], "kernels": r2["kernels"],
                    "autotune": r2["autotune"], "parity_rel_err": r2["parity_rel_err"]}
-    alpha = None if args.no_alpha else alpha_choice_bench(args.alpha_train, args.alpha_test, 200, 3000)
+    alpha = None if args.no_alpha else alpha_choice_bench(args.alpha_train, args.alpha_test, 3000)
     batched = None if args.no_batched else batched_bench()
     general = None if args.no_general else general_rhs_bench()
     operator_1d = None if args.no_operator else operator_1d_bench()

@@ -225,6 +225,18 @@ int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_d
 int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double delta,
                       const qbvm_alpha_opts* opts, double* alpha_out, qbvm_alpha_info* info);
 
+/* qbvm_choose_alpha for `count` instances one after another (batch size 1 each), with
+ * the latency of every call measured on the host (steady clock around the call, which
+ * returns once its result is on the host) and no interpreter between calls: the
+ * per-instance latency of the alpha choice, learned or bisection.  g_deltas: DEVICE,
+ * count * m^d doubles; deltas: HOST, count doubles; alphas_out: HOST, count;
+ * infos_out, seconds_out: HOST, count each, may be NULL.  An instance whose root lies
+ * outside the bracket is recorded (info.bracket_hit = 1) and the loop goes on; any
+ * other error stops it and is returned. */
+int qbvm_choose_alpha_each(qbvm_plan_t p, int variant, int count, const double* g_deltas,
+                           const double* deltas, const qbvm_alpha_opts* opts, double* alphas_out,
+                           qbvm_alpha_info* infos_out, double* seconds_out);
+
 /* Batched bisection for `count` instances on the plan's grid (label generation).
  * g_deltas: DEVICE, count * m^d doubles; deltas: DEVICE, count doubles;
  * alphas_out: DEVICE, count doubles; hits_out: DEVICE, count ints (may be NULL).

@@ -8,14 +8,13 @@ prediction misses the discrepancy window.
 
 Everything numerical runs in the library: labels by qbvm_bisect_batched,
 features by qbvm_features, training by qbvm_mlp_loss_grad and qbvm_adam_step,
-selection by qbvm_choose_alpha.  The host only generates the synthetic data,
+selection by qbvm_choose_alpha (qbvm_choose_alpha_each for timed sweeps).  The host only generates the synthetic data,
 shuffles minibatch order and computes the 33 feature means/standard deviations.
 """
 from __future__ import annotations
 
 import dataclasses
 import math
-import time
 from typing import Optional
 
 import numpy as np
@@ -149,32 +148,33 @@ def predict_log10(model: AlphaModel, feats) -> np.ndarray:
 
 
 def reconstruction_errors(plan: qbvm.Plan, ds: Dataset, alphas: np.ndarray, idx) -> np.ndarray:
-    """e_h = ||y^0(alpha) - z0||_h (Section 5) for the instances idx, y^0 by qbvm_solve."""
+    """e_h = ||y^0(alpha) - z0||_h (Section 5) for the instances idx, y^0 by qbvm_solve
+    (the difference and its norm are taken on the GPU)."""
     import torch
     h = plan.Lx / (plan.m + 1)
+    dev = ds.g_delta.device
     out = np.empty(len(idx))
-    y0 = torch.empty((plan.m,) * plan.d, dtype=torch.float64, device=ds.g_delta.device)
+    y0 = torch.empty((plan.m,) * plan.d, dtype=torch.float64, device=dev)
     for i, k in enumerate(idx):
         plan.solve(float(alphas[i]), qbvm.QBVM_PQ, ds.g_delta[k], y0, output=qbvm.OUT_Y0)
-        out[i] = h ** (plan.d / 2) * float(np.linalg.norm((y0.cpu().numpy() - ds.z0[k]).ravel()))
+        z = torch.from_numpy(ds.z0[k]).to(dev)
+        out[i] = h ** (plan.d / 2) * float(torch.linalg.vector_norm(y0 - z))
     return out
 
 
+def error_curve(plan: qbvm.Plan, ds: Dataset, idx, grid) -> np.ndarray:
+    """e_h(alpha) for every alpha of `grid` (rows: instances idx, columns: grid)."""
+    return np.stack([reconstruction_errors(plan, ds, np.full(len(idx), float(a)), idx) for a in grid], 1)
+
+
 def choose_all(plan: qbvm.Plan, ds: Dataset, idx, use_learned: bool, win=(1.05, 1.15)):
-    """qbvm_choose_alpha one instance at a time (batch size 1): alphas, wall latencies
-    (seconds, host clock around each synchronous call), fallback flags."""
+    """qbvm_choose_alpha_each over the instances idx (batch size 1 each): alphas, per-call
+    latencies (seconds, measured in the library around each synchronous call), fallback flags."""
     import torch
     opts = qbvm.default_alpha_opts(use_learned)
     opts.win_lo, opts.win_hi = win
-    alphas = np.empty(len(idx))
-    lat = np.empty(len(idx))
-    fb = np.zeros(len(idx), dtype=bool)
+    idx = np.asarray(idx, dtype=np.int64)
+    G = ds.g_delta.index_select(0, torch.from_numpy(idx).to(ds.g_delta.device)).contiguous()
     torch.cuda.synchronize()
-    for i, k in enumerate(idx):
-        g = ds.g_delta[k]
-        t0 = time.perf_counter()
-        a, info = plan.choose_alpha(qbvm.QBVM_PQ, g, float(ds.delta[k]), opts)
-        lat[i] = time.perf_counter() - t0
-        alphas[i] = a
-        fb[i] = bool(info.used_fallback)
-    return alphas, lat, fb
+    alphas, infos, lat = plan.choose_alpha_each(qbvm.QBVM_PQ, G, ds.delta[idx], opts)
+    return alphas, lat, infos["used_fallback"].astype(bool)

@@ -840,6 +840,23 @@ int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double 
   return inf.bracket_hit ? set_error(QBVM_ENOROOT, "discrepancy root outside the bracket") : QBVM_OK;
 }
 
+int qbvm_choose_alpha_each(qbvm_plan_t p, int variant, int count, const double* g_deltas, const double* deltas,
+                           const qbvm_alpha_opts* o, double* alphas_out, qbvm_alpha_info* infos_out,
+                           double* seconds_out) {
+  if (!p || !g_deltas || !deltas || !alphas_out || count < 0) return set_error(QBVM_EINVAL, "invalid argument");
+  for (int i = 0; i < count; ++i) {
+    qbvm_alpha_info inf{};
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = qbvm_choose_alpha(p, variant, g_deltas + (size_t)i * p->nmodes, deltas[i], o, alphas_out + i,
+                                     &inf);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (rc != QBVM_OK && rc != QBVM_ENOROOT) return rc;
+    if (infos_out) infos_out[i] = inf;
+    if (seconds_out) seconds_out[i] = std::chrono::duration<double>(t1 - t0).count();
+  }
+  return QBVM_OK;
+}
+
 static int ensure_batch_ws(qbvm_plan_t p, size_t bytes) {
   if (p->bws_bytes >= bytes) return QBVM_OK;
   HIP_TRY(hipStreamSynchronize(p->stream));

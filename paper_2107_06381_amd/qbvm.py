@@ -28,7 +28,7 @@ ERR_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOROOT", -5:
 EXPORTS = [
     "qbvm_plan", "qbvm_plan_destroy", "qbvm_plan_set_stream", "qbvm_plan_workspace_bytes",
     "qbvm_solve", "qbvm_solve_general", "qbvm_solve_batched", "qbvm_batched_cache_clear", "qbvm_discrepancy",
-    "qbvm_choose_alpha", "qbvm_bisect_batched", "qbvm_features", "qbvm_set_alpha_model",
+    "qbvm_choose_alpha", "qbvm_choose_alpha_each", "qbvm_bisect_batched", "qbvm_features", "qbvm_set_alpha_model",
     "qbvm_mlp_forward", "qbvm_mlp_loss_grad", "qbvm_mlp_loss_grad_noalloc", "qbvm_adam_step", "qbvm_strerror",
     "qbvm_last_error", "qbvm_version", "qbvm_profile_enable", "qbvm_profile_reset",
     "qbvm_profile_count", "qbvm_profile_get", "qbvm_plan_autotune", "qbvm_plan_get_variants",
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qbvm_discrepancy": (i, [vp, d, i, vp, ctypes.POINTER(d)]),
         "qbvm_choose_alpha": (i, [vp, i, vp, d, ctypes.POINTER(AlphaOpts), ctypes.POINTER(d),
                                   ctypes.POINTER(AlphaInfo)]),
+        "qbvm_choose_alpha_each": (i, [vp, i, i, vp, ctypes.POINTER(d), ctypes.POINTER(AlphaOpts),
+                                       ctypes.POINTER(d), ctypes.POINTER(AlphaInfo), ctypes.POINTER(d)]),
         "qbvm_bisect_batched": (i, [vp, i, i, vp, vp, ctypes.POINTER(AlphaOpts), vp, vp]),
         "qbvm_features": (i, [vp, i, vp, vp, vp]),
         "qbvm_set_alpha_model": (i, [vp, ctypes.POINTER(ctypes.c_float)]),
@@ -250,6 +252,29 @@ class Plan:
             return a.value, info
         _check(rc)
         return a.value, info
+
+    def choose_alpha_each(self, variant: int, g_deltas, deltas, opts: Optional[AlphaOpts] = None):
+        """qbvm_choose_alpha_each: one call per instance, timed in the library.  g_deltas: GPU
+        tensor (count, m, ..); deltas: host sequence.  Returns (alphas, infos, seconds) as numpy
+        arrays (infos: structured fields alpha_learned, iterations, used_fallback, bracket_hit)."""
+        import numpy as np
+        import torch
+        opts = opts or default_alpha_opts()
+        dl = np.ascontiguousarray(np.asarray(deltas, dtype=np.float64).ravel())
+        count = int(dl.size)
+        gp = _dev_tensor(g_deltas, count * self.nmodes, torch.float64, "g_deltas")
+        alphas = np.empty(count)
+        secs = np.empty(count)
+        infos = (AlphaInfo * max(1, count))()
+        dptr = ctypes.POINTER(ctypes.c_double)
+        _check(self.L_.qbvm_choose_alpha_each(self._h, int(variant), count, gp, dl.ctypes.data_as(dptr),
+                                              ctypes.byref(opts), alphas.ctypes.data_as(dptr), infos,
+                                              secs.ctypes.data_as(dptr)))
+        rec = np.array([(x.discrepancy, x.alpha_learned, x.iterations, x.used_fallback, x.bracket_hit)
+                        for x in infos[:count]],
+                       dtype=[("discrepancy", "f8"), ("alpha_learned", "f8"), ("iterations", "i4"),
+                              ("used_fallback", "i4"), ("bracket_hit", "i4")])
+        return alphas, rec, secs
 
     def bisect_batched(self, variant: int, g_deltas, deltas, opts: Optional[AlphaOpts] = None):
         import torch

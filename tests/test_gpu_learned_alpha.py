@@ -66,7 +66,7 @@ def test_prediction_accuracy(trained):
 def test_learned_choice_quality_latency_and_gain(trained):
     plan, model, ds, _ = trained
     plan.set_alpha_model(model.blob())
-    idx = np.arange(80)
+    idx = np.arange(200)
     a_l, lat_l, fb = AM.choose_all(plan, ds, idx, use_learned=True)
     a_b, lat_b, _ = AM.choose_all(plan, ds, idx, use_learned=False)
     # bisection-only must reproduce the batched labels
@@ -80,11 +80,52 @@ def test_learned_choice_quality_latency_and_gain(trained):
         f"bisection {np.median(lat_b) * 1e6:.0f} us; alpha=delta error ratio {np.mean(e_prior / e_b):.2f}")
     assert ratio.mean() <= 1.05
     assert fb.mean() < 0.5
-    # the gain over the method without the network: lower latency at matched error
-    assert np.median(lat_l) < np.median(lat_b)
-    # the paper's a-priori rule (alpha = delta) is reported, not asserted: on this
-    # data the error is flat over a wide range of alpha around alpha_DP
+    # the gain over the method without the network: >= 10x lower latency at matched error
+    # (per-call latencies measured in the library, qbvm_choose_alpha_each)
+    assert np.median(lat_b) >= 10.0 * np.median(lat_l)
+    # the paper's a-priori rule (alpha = delta) is reported, not asserted: at T = 1 the error
+    # is flat over several decades of alpha around alpha_DP (see the T = 0.1 test below)
     assert np.all(np.isfinite(e_prior))
+
+
+@pytest.fixture(scope="module")
+def trained_short_time():
+    """The same data family at T = 0.1, where the reconstruction error has a pronounced minimum
+    in alpha (about one decade around alpha_DP stays within 5% of its error)."""
+    say("[case] learned alpha at T=0.1: data + labels + training")
+    plan = qbvm.Plan(2, 127, 128, 1.0, 0.1)
+    train_ds = AM.make_dataset(plan, seed=4, count=6000)
+    model, hist = AM.train(train_ds, steps=2000, batch=256, lr=3e-3, log_every=500)
+    say("loss history", hist)
+    test_ds = AM.make_dataset(plan, seed=5, count=200, keep_z0=True)
+    return plan, model, test_ds
+
+
+def test_learned_choice_where_alpha_matters(trained_short_time):
+    """At T = 0.1 a misplaced alpha costs accuracy: alpha_DP is within a few percent of the best
+    alpha on a grid, the paper's a-priori alpha = delta is clearly worse, and the learned choice
+    must match alpha_DP's error within 5% on average (and beat alpha = delta) at >= 10x lower
+    latency than the bisection."""
+    plan, model, ds = trained_short_time
+    plan.set_alpha_model(model.blob())
+    idx = np.arange(200)
+    ok = ds.hits[idx] == 0
+    a_l, lat_l, fb = AM.choose_all(plan, ds, idx, use_learned=True)
+    _, lat_b, _ = AM.choose_all(plan, ds, idx, use_learned=False)
+    e_l = AM.reconstruction_errors(plan, ds, a_l, idx)[ok]
+    e_dp = AM.reconstruction_errors(plan, ds, ds.alpha_dp[idx], idx)[ok]
+    e_prior = AM.reconstruction_errors(plan, ds, ds.delta[idx], idx)[ok]
+    grid = [10.0 ** (x / 4.0) for x in range(-32, 1)]
+    curve = AM.error_curve(plan, ds, idx[ok][:40], grid) / e_dp[:40, None]
+    r, rp = e_l / e_dp, e_prior / e_dp
+    say(f"T=0.1: learned/DP mean {r.mean():.4f} (p95 {np.quantile(r, 0.95):.4f}); alpha=delta/DP mean "
+        f"{rp.mean():.4f}; best grid/DP median {np.median(curve.min(1)):.4f}; fallback {fb.mean():.3f}; "
+        f"latency median learned {np.median(lat_l) * 1e6:.1f} us, bisection {np.median(lat_b) * 1e6:.1f} us")
+    assert np.median(curve.min(1)) > 0.9       # alpha_DP is close to the best alpha on the grid
+    assert rp.mean() > 1.08                    # the a-priori rule loses accuracy here
+    assert r.mean() <= 1.05                    # the learned alpha keeps alpha_DP's accuracy
+    assert r.mean() < rp.mean()
+    assert np.median(lat_b) >= 10.0 * np.median(lat_l)
 
 
 def test_forced_window_miss_falls_back(trained):
