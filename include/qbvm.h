@@ -154,6 +154,16 @@ int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var
  * nothing changes.  Shapes that use the generic kernels accept only -1. */
 int qbvm_plan_set_variants(qbvm_plan_t p, int var_rows, int var_cols, int var_time, int var_general);
 
+/* Plane pass (an addition to the schedule of Section 3.3's Step (c) output): for d >= 2
+ * with m = 127 the x_2 and x_1 sine transforms of each level (and x_3 position) run in one
+ * kernel on the whole plane, which moves 16 bytes per unknown less than a columns pass
+ * followed by a rows pass.  On by default where the shape allows it.  on = 1 where it
+ * does not: QBVM_EUNSUPPORTED, nothing changes.  on = 0 selects the separate passes. */
+int qbvm_plan_set_plane(qbvm_plan_t p, int on);
+
+/* 1 if qbvm_solve of this plan uses the plane pass, 0 if not, negative on error. */
+int qbvm_plan_uses_plane(qbvm_plan_t p);
+
 /* -------------------------------------------------------------- solving ---- */
 
 /* Solve one PinT system (Sections 3.1-3.3).  g_delta: DEVICE, m^d doubles.

@@ -245,6 +245,7 @@ struct qbvm_plan_s {
   int S_time = 1, S_dst = 1;
   int var_rows = 5, var_cols = 6, var_time = 4;  // set per transform length in create_plan
   int var_gen = 1;                                // time kernel of the general right-hand side
+  bool plane = true;  // plane pass (x_2 and x_1 together) where the shape allows it
   double* mu1d = nullptr;
   double* ghat = nullptr;
   double* yrow = nullptr;
@@ -507,6 +508,17 @@ int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, in
       ProfScope ps("time_spectral", stream, 8.0 * nm * (1.0 + p->Nt),
                    0.5 * nm * (fft_flops(p->tfft->dev) + 28.0 * p->Nt), nc);
       HIP_TRY(launch_time(t.args, t.nwg, t.args.threads, t.lds, stream, nc));
+    }
+    if (p->plane && sched::use_plane(G)) {
+      const double elems = (double)p->Nt * p->nmodes;
+      for (const auto& L : sched::plane_pre_passes(G, W)) {
+        ProfScope ps("dst_cols", stream, 16.0 * elems, 0.5 * elems / p->m * fft_flops(p->sfft->dev), nc);
+        HIP_TRY(launch_dst(L.args, L.nwg, L.args.threads, L.lds, stream, nc, 2));
+      }
+      const PlaneArgs pa = sched::plane_args(G, W, y);
+      ProfScope ps("dst_plane", stream, 16.0 * elems, elems / p->m * fft_flops(p->sfft->dev), nc);
+      HIP_TRY(launch_plane(pa, stream, nc));
+      return QBVM_OK;
     }
     const auto passes = sched::padded_passes(G, W, y);
     for (size_t i = 0; i < passes.size(); ++i) {
@@ -1116,6 +1128,19 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
   if (ms_out)
     for (int i = 0; i < kAutotuneTimings; ++i) ms_out[i] = ms[i];
   return QBVM_OK;
+}
+
+extern "C" int qbvm_plan_set_plane(qbvm_plan_t p, int on) {
+  if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
+  if (on && !sched::use_plane(geom(p)))
+    return set_error(QBVM_EUNSUPPORTED, "the plane pass needs d >= 2, m = 127 and the padded pipeline");
+  p->plane = on != 0;
+  return QBVM_OK;
+}
+
+extern "C" int qbvm_plan_uses_plane(qbvm_plan_t p) {
+  if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
+  return p->plane && sched::use_plane(geom(p)) ? 1 : 0;
 }
 
 extern "C" int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var_time,

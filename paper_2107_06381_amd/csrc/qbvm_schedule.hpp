@@ -158,6 +158,37 @@ inline std::vector<Launch<DstArgs>> padded_passes(const Geom& g, double* W, doub
   return v;
 }
 
+// Plane pass (d >= 2, sine length 256, i.e. m = 127): after the time kernel, the x_3
+// sine pass runs in place on W (3D), then one kernel applies the x_2 and x_1 transforms
+// to every [m][P1] plane of W and writes y: 16 bytes per unknown fewer than a columns
+// pass and a rows pass.
+inline bool use_plane(const Geom& g) {
+  return use_padded(g) && g.sfft.p2 == 256 && p2sz::plane_valid(256) && g.m == 127 &&
+         padded_pitch(g.m) == p2sz::plane_pitch(256);
+}
+inline std::vector<Launch<DstArgs>> plane_pre_passes(const Geom& g, double* W) {
+  std::vector<Launch<DstArgs>> v;
+  if (g.d == 3) {
+    const int m = g.m;
+    const long long P1 = padded_pitch(m), ks = P1 * m;
+    v.push_back(dst_pass_custom(g, W, W, g.Nt, ks, 0, 0, ks, ks * m, (int)P1, m, g.var_cols));
+  }
+  return v;
+}
+inline PlaneArgs plane_args(const Geom& g, const double* W, double* y) {
+  PlaneArgs a{};
+  a.in = W;
+  a.out = y;
+  a.m = g.m;
+  a.in_pitch = (int)padded_pitch(g.m);
+  a.planes = (long long)g.Nt * (g.nmodes / ((long long)g.m * g.m));
+  a.in_plane = (long long)g.m * a.in_pitch;
+  a.out_plane = (long long)g.m * g.m;
+  a.scale = 0.5 * std::sqrt(2.0 / (g.m + 1));
+  a.fft = g.sfft;
+  return a;
+}
+
 // Spectral time kernel writing levels [lev_first, lev_first + lev_count) to y.
 inline Launch<TimeArgs> time_step(const Geom& g, SolveScalars sc, const double* alpha_dev, int variant,
                                   const double* ghat, double* y, int lev_first, int lev_count) {

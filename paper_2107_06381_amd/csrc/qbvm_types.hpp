@@ -114,6 +114,21 @@ struct DstArgs {
   FftPlanDev fft;
 };
 
+// Plane pass (d >= 2): the x_2 and x_1 sine transforms of every plane [m][in_pitch] of
+// `in` (planes in_plane apart; columns m .. in_pitch-1 are padding), written unpadded
+// to `out` (planes out_plane = m*m apart).
+struct PlaneArgs {
+  const double* in;
+  double* out;
+  long long planes;
+  long long in_plane;
+  long long out_plane;
+  int m;
+  int in_pitch;  // even
+  double scale;  // orthonormal DST-I factor of one transform, sqrt(2/(m+1)), halved (see k_dst)
+  FftPlanDev fft;  // length 2(m+1)
+};
+
 // 1D paper-order Step (b): complex Thomas per shift j.
 struct ThomasArgs {
   int Nt;

@@ -32,7 +32,7 @@ EXPORTS = [
     "qbvm_mlp_forward", "qbvm_mlp_loss_grad", "qbvm_mlp_loss_grad_noalloc", "qbvm_adam_step", "qbvm_strerror",
     "qbvm_last_error", "qbvm_version", "qbvm_profile_enable", "qbvm_profile_reset",
     "qbvm_profile_count", "qbvm_profile_get", "qbvm_plan_autotune", "qbvm_plan_get_variants",
-    "qbvm_plan_set_variants", "qbvm_plan_set_operator_1d",
+    "qbvm_plan_set_variants", "qbvm_plan_set_operator_1d", "qbvm_plan_set_plane", "qbvm_plan_uses_plane",
 ]
 
 
@@ -103,6 +103,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(i)]),
         "qbvm_plan_set_variants": (i, [vp, i, i, i, i]),
         "qbvm_plan_set_operator_1d": (i, [vp, vp, vp, vp]),
+        "qbvm_plan_set_plane": (i, [vp, i]),
+        "qbvm_plan_uses_plane": (i, [vp]),
         "qbvm_profile_enable": (None, [i]),
         "qbvm_profile_reset": (None, []),
         "qbvm_profile_count": (i, []),
@@ -206,6 +208,16 @@ class Plan:
     def set_variants(self, rows: int = -1, cols: int = -1, time: int = -1, general: int = -1):
         """Select kernel variants by hand (-1 keeps the current one)."""
         _check(self.L_.qbvm_plan_set_variants(self._h, int(rows), int(cols), int(time), int(general)))
+
+    def set_plane(self, on: bool):
+        """qbvm_plan_set_plane: the x_2/x_1 plane pass on (where the shape allows it) or off."""
+        _check(self.L_.qbvm_plan_set_plane(self._h, 1 if on else 0))
+
+    def uses_plane(self) -> bool:
+        rc = self.L_.qbvm_plan_uses_plane(self._h)
+        if rc < 0:
+            _check(rc)
+        return rc == 1
 
     def out_shape(self, output: int):
         sp = (self.m,) * self.d

@@ -34,3 +34,5 @@ inline double exp10(double x) { return std::pow(10.0, x); }
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))
 // every lane of the emulated wave holds the same value where the bodies use this
 #define __builtin_amdgcn_readfirstlane(x) (x)
+// the bodies' optimisation barrier, on a general-purpose register here
+#define QBVM_OPAQUE(x) asm volatile("" : "+r"(x))

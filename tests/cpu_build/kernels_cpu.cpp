@@ -2,7 +2,7 @@
 // host-side tests: indexing is checked by AddressSanitizer, results against the
 // oracle.  Usage:
 //   kernels_cpu fft   n S in.bin out.bin          (S signals, signal-major complex)
-//   kernels_cpu solve d m n L T alpha variant in.bin out.bin [var_rows var_cols var_time [padded]]
+//   kernels_cpu solve d m n L T alpha variant in.bin out.bin [var_rows var_cols var_time [padded [plane]]]
 //   kernels_cpu dst   d m batch in.bin out.bin [var_rows var_cols input]
 //   kernels_cpu general d m n L T alpha variant f.bin out.bin [padded var_gen]   (general right-hand side)
 //   kernels_cpu solveop m n L T alpha variant in.bin out.bin op.bin level   (1D, tridiagonal operator;
@@ -444,7 +444,7 @@ int main(int argc, char** argv) {
     write_file(argv[9], y.data(), ny * sizeof(double));
     return 0;
   }
-  if (cmd == "solve" && (argc == 11 || argc == 14 || argc == 15)) {
+  if (cmd == "solve" && (argc == 11 || argc == 14 || argc == 15 || argc == 16)) {
     const int d = atoi(argv[2]), m = atoi(argv[3]), n = atoi(argv[4]);
     const double L = atof(argv[5]), T = atof(argv[6]), alpha = atof(argv[7]);
     const int variant = atoi(argv[8]);
@@ -468,7 +468,9 @@ int main(int argc, char** argv) {
     const size_t ny = (size_t)g.Nt * g.nmodes;
     double* y = new double[ny];
     const SolveScalars sc = sched::host_scalars(alpha, variant, g.tau);
-    const bool padded = sched::use_padded(g) && !(argc == 15 && atoi(argv[14]) == 0);
+    const bool padded = sched::use_padded(g) && !(argc >= 15 && atoi(argv[14]) == 0);
+    const bool want_plane = argc == 16 && atoi(argv[15]) != 0;
+    if (want_plane && !(padded && sched::use_plane(g))) return 19;
     if (padded) {
       double* gh = new double[g.nmodes];
       double* W = new double[sched::padded_elems(g)];
@@ -480,8 +482,19 @@ int main(int argc, char** argv) {
       auto t = sched::time_step_padded(g, sc, nullptr, variant, gh, W);
       t.args.tabs = tabs.data();
       run_time_fast(t);
-      for (const auto& Lz : sched::padded_passes(g, W, y)) {
-        P2_SWITCH(Lz.args.fft.p2, dst_p2_n, Lz)
+      if (want_plane) {
+        for (const auto& Lz : sched::plane_pre_passes(g, W)) {
+          P2_SWITCH(Lz.args.fft.p2, dst_p2_n, Lz)
+        }
+        const PlaneArgs pa = sched::plane_args(g, W, y);
+        for (size_t q = 0; q < (size_t)g.Nt * g.nmodes; ++q) y[q] = std::nan("");  // every output written
+        const long long G = pa.planes < 3 ? pa.planes : 3;  // a few workgroups, several planes each
+        run_grid(G, p2sz::kPlaneT, p2sz::plane_lds(256),
+                 [&](long long wg, c64* l) { dst_plane_p2_body<256>(pa, wg, G, l); });
+      } else {
+        for (const auto& Lz : sched::padded_passes(g, W, y)) {
+          P2_SWITCH(Lz.args.fft.p2, dst_p2_n, Lz)
+        }
       }
       delete[] gh;
       delete[] W;

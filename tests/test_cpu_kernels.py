@@ -125,6 +125,24 @@ def test_solve_schedule_vs_oracle(exe, tmp_path, case, kv):
     assert ok, r
 
 
+@pytest.mark.parametrize("d,m,n,alpha,variant,plane", [(2, 127, 63, 1e-4, 0, 1), (2, 127, 128, 1e-3, 1, 1),
+                                                        (2, 127, 63, 1e-4, 0, 0)])
+def test_plane_pass_vs_oracle(exe, tmp_path, d, m, n, alpha, variant, plane):
+    """The plane pass (x_2 and x_1 sine transforms of each level in one kernel; padded
+    pipeline, sine length 256) against the closed form, and the separate passes it replaces;
+    the output is preset to NaN, so every value must be written."""
+    L, T = 1.0, 0.9
+    g = np.random.default_rng(5).standard_normal((m,) * d)
+    fi, fo = tmp_path / "i.bin", tmp_path / "o.bin"
+    g.tofile(fi)
+    _run(exe, ["solve", d, m, n, repr(L), repr(T), repr(alpha), variant, fi, fo, 1, 1, 1, 1, plane], tmp_path)
+    y = np.fromfile(fo).reshape((n + 1,) + (m,) * d)
+    assert not np.isnan(y).any()
+    yc = O.closed_form(g, d, m, n, L, T, alpha, variant)
+    assert np.linalg.norm(y - yc) / np.linalg.norm(yc) < 1e-12
+    assert np.linalg.norm(y[0] - yc[0]) / np.linalg.norm(yc[0]) < 1e-12
+
+
 GENERAL_CASES = [
     # generic engine, sine passes in y: Stockham, Rader (N_t = 17), Good-Thomas size 129, N_t = 2
     (1, 17, 12, 1e-3, 0, 0, 0), (2, 15, 16, 1e-4, 1, 0, 0), (2, 20, 11, 1e-2, 0, 0, 0), (3, 6, 7, 1e-5, 0, 0, 0),

@@ -126,10 +126,18 @@ def test_config_3d_every_level():
     inst = W.config_3d()
     m, n = 127, 128
     p = qbvm.Plan(3, m, n, 1.0, 0.5)
-    say("variants", p.autotune()["variants"])
+    say("variants", p.autotune()["variants"], "plane pass", p.uses_plane())
+    assert p.uses_plane()
     y = p.solve(1e-5, 0, to_dev(inst.g_delta))
     torch.cuda.synchronize()
     assert bool(torch.isfinite(y).all())
+    p.set_plane(False)  # the separate x_2 and x_1 passes: same values to rounding
+    y2 = p.solve(1e-5, 0, to_dev(inst.g_delta))
+    torch.cuda.synchronize()
+    diff = float(torch.linalg.vector_norm(y2 - y) / torch.linalg.vector_norm(y))
+    say("plane vs separate passes", diff)
+    assert diff < 1e-13
+    del y2
     p.close()
     worst = 0.0
     with scipy.fft.set_workers(min(16, len(os.sched_getaffinity(0)))):
@@ -143,6 +151,38 @@ def test_config_3d_every_level():
                 assert e < TOL, (t, e)
     say("worst level rel err", worst)
     del y
+
+
+@pytest.mark.parametrize("n,alpha,variant", [(128, 1e-4, 0), (127, 1e-2, 1), (63, 1e-6, 0)])
+def test_plane_pass_2d_vs_oracle(n, alpha, variant):
+    """2D m = 127 (sine length 256): the plane pass does both sine transforms of each level;
+    every level against the closed form, on and off."""
+    say(f"[case] plane pass 2d m=127 n={n}")
+    m = 127
+    g = np.random.default_rng(n).standard_normal((m, m))
+    p = qbvm.Plan(2, m, n, 1.0, 1.0)
+    assert p.uses_plane()
+    y = p.solve(alpha, variant, to_dev(g)).cpu().numpy()
+    p.set_plane(False)
+    assert not p.uses_plane()
+    y2 = p.solve(alpha, variant, to_dev(g)).cpu().numpy()
+    p.close()
+    yc = O.closed_form(g, 2, m, n, 1.0, 1.0, alpha, variant)
+    w = omega_abs(alpha, variant, 1.0 / n)
+    for yy in (y, y2):
+        assert rel(yy, yc) < TOL
+        for t in range(n + 1):
+            ok, e = level_ok(yy[t], yc[t], yc[0], t, n + 1, w)
+            assert ok, (t, e)
+
+
+def test_plane_pass_refused_where_unsupported():
+    p = qbvm.Plan(2, 63, 64, 1.0, 1.0)
+    assert not p.uses_plane()
+    with pytest.raises(qbvm.QbvmError) as e:
+        p.set_plane(True)
+    assert e.value.code == -5
+    p.close()
 
 
 @pytest.mark.parametrize("d,m,n,levels", [
