@@ -137,9 +137,10 @@ long long qbvm_plan_workspace_bytes(qbvm_plan_t p);
  * cached per (device, kernel role, transform length) and used as the defaults of
  * later plans.  The plan's current variant is kept unless another is more than 3%
  * faster.  Synchronous; allocates and frees (n+1) m^d doubles of scratch.
- * ms_out (HOST, may be NULL) receives 26 timings in milliseconds (-1 where not
+ * ms_out (HOST, may be NULL) receives 30 timings in milliseconds (-1 where not
  * applicable): rows variants 0, 1, 3, 4, 5, 6, 7; columns variants 0, 1, 3, 4, 5,
- * 6, 7; time variants 0..5; general right-hand-side time variants 0..5. */
+ * 6, 7; time variants 0..5; general right-hand-side time variants 0..5; the x_2 and x_1
+ * passes that the plane pass replaces (sum); plane-pass variants 0..2. */
 int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out);
 
 /* The kernel variants a plan uses (HOST outputs, each may be NULL): sine rows, sine
@@ -154,15 +155,18 @@ int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var
  * nothing changes.  Shapes that use the generic kernels accept only -1. */
 int qbvm_plan_set_variants(qbvm_plan_t p, int var_rows, int var_cols, int var_time, int var_general);
 
-/* Plane pass (an addition to the schedule of Section 3.3's Step (c) output): for d >= 2
- * with m = 127 the x_2 and x_1 sine transforms of each level (and x_3 position) run in one
- * kernel on the whole plane, which moves 16 bytes per unknown less than a columns pass
- * followed by a rows pass.  On by default where the shape allows it.  on = 1 where it
- * does not: QBVM_EUNSUPPORTED, nothing changes.  on = 0 selects the separate passes. */
-int qbvm_plan_set_plane(qbvm_plan_t p, int on);
+/* Plane pass (an addition to the output schedule of Step (c)): for d >= 2 with m = 127 the
+ * x_2 and x_1 sine transforms of each level (and x_3 position) run in one kernel on the
+ * whole plane, which moves 16 bytes per unknown less than a columns pass followed by a
+ * rows pass.  On by default (variant 0) where the shape allows it; qbvm_plan_autotune
+ * times its variants (0: 16 values per lane, 512 lanes; 1: 8 values per lane, 1024 lanes;
+ * 2: as 0, loads issued earlier) against the separate passes and keeps the fastest.
+ * variant < 0 selects the separate passes.  A variant >= 0 where the shape does not allow
+ * the plane pass: QBVM_EUNSUPPORTED; an unknown variant: QBVM_EINVAL; nothing changes. */
+int qbvm_plan_set_plane(qbvm_plan_t p, int variant);
 
-/* 1 if qbvm_solve of this plan uses the plane pass, 0 if not, negative on error. */
-int qbvm_plan_uses_plane(qbvm_plan_t p);
+/* *variant (HOST) receives the plane-pass variant qbvm_solve uses, or -1 (separate passes). */
+int qbvm_plan_get_plane(qbvm_plan_t p, int* variant);
 
 /* -------------------------------------------------------------- solving ---- */
 

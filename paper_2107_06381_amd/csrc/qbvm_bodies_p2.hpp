@@ -186,37 +186,43 @@ __device__ __forceinline__ void dst_cols_p2_body(const DstArgs& a, long long fir
 // N = 2(m+1): two real lines a, b packed as a + i b, odd extension, length-N DFT, line a
 // from -Im and line b from Re of outputs 1..m (as in k_dst).  The transforms of
 // different axes commute, and the plane is the smallest unit that both need whole.
-// 512 lanes, E = 16 (N/16 lanes per signal, SR signals per round, one LDS exchange per
-// transform): the column pairs run in rounds (SigFast: lanes of a wave on consecutive
+// E values per lane (N/E lanes per signal, SR signals per round; E = 16: one LDS exchange
+// per transform): the column pairs run in rounds (SigFast: lanes of a wave on consecutive
 // pairs, coalesced 16-byte loads) and each lane keeps its outputs 1..m in registers, so
 // the whole transformed plane is held by the workgroup; then for each round of row pairs
 // the rows it needs go through LDS (transposed, [x_2][k_1] doubles), are read back along
 // the rows (PosFast) and transformed, and the results are stored along the rows of y.
 // One LDS region carries every exchange and these rows in turn; the twiddle table
 // follows it.  Persistent: workgroup `first` takes planes first, first + step, ...
-template <int N>
+template <int N, int V>
 __device__ __forceinline__ void dst_plane_p2_body(const PlaneArgs& a, long long first, long long step, c64* lds) {
-  constexpr int E = p2sz::kPlaneE;
-  constexpr int T = p2sz::kPlaneT;
-  constexpr int SR = p2sz::plane_SR(N);
-  constexpr int R = p2sz::plane_rounds(N);
+  constexpr int E = p2sz::plane_E(V);
+  constexpr int T = p2sz::plane_T(V);
+  constexpr int SR = p2sz::plane_SR(N, V);
+  constexpr int R = p2sz::plane_rounds(N, V);
   constexpr int U = N / E;  // lanes per signal
   using LC = P2Layout<N, E, SR, true>;
   using LR = P2Layout<N, E, SR, false, true, 1>;
-  static_assert(LC::T == T && LR::T == T, "plane pass: 512 lanes");
+  static_assert(LC::T == T && LR::T == T, "plane pass: lanes");
   static_assert(R * SR * 4 == N, "plane pass: whole rounds of pairs");
-  // Input and output slot e of lane u hold position u + U e (last radix = E), so slots
-  // e < E/2 hold outputs 0..N/2-1 (the others are mirror images).  Row round j takes the
-  // rows k - 1 of outputs k in [N/2 j/R, N/2 (j+1)/R): slots [E/2 j/R, E/2 (j+1)/R).
-  static_assert(P2Radices<N, E>::R[P2Radices<N, E>::K - 1] == E, "outputs u + U e");
+  static_assert(P2Radices<N, E>::R[0] == E, "input slot e of lane u holds position u + U e");
+  // Output slot e of lane u holds position u + U (e/RL) + (N/RL) (e%RL) (last radix RL), so
+  // the outputs below N/2 (the useful ones, 1..m; the others are mirror images) are
+  // u + U h, h < E/2, in slot RL (h % D) + h / D with D = E/RL.
+  constexpr int RL = P2Radices<N, E>::R[P2Radices<N, E>::K - 1];
+  constexpr int D = E / RL;
+  static_assert(D * RL == E && N / RL == U * D, "plane pass: output layout");
   constexpr int H = E / 2;
-  constexpr int HJ = H / R;        // slots per lane and column round that one row round takes
-  constexpr int RJ = U * HJ;       // rows per row round (local rows 0 .. RJ-1)
-  static_assert(H % R == 0 && RJ == 2 * SR, "row rounds: one row pair per signal");
+  // Row round j takes rows RJ j - 1 + (0 .. RJ-1), i.e. outputs [RJ j, RJ (j+1)): the HJ
+  // useful slots h = HJ j + (0 .. HJ-1) of every lane.
+  constexpr int HJ = H / R;
+  constexpr int RJ = U * HJ;
+  static_assert(HJ * R == H && RJ == 2 * SR, "plane pass: row rounds tile the useful outputs");
+  auto slot = [](int h) { return RL * (h % D) + h / D; };
   c64* buf = lds;
   double* plane = reinterpret_cast<double*>(lds);
   const int t = threadIdx.x;
-  const auto tw = p2_twiddles<N, 1, E>(a.fft, lds + p2sz::plane_region_elems(N), t, T);
+  const auto tw = p2_twiddles<N, 1, E>(a.fft, lds + p2sz::plane_region_elems(N, V), t, T);
   __syncthreads();
   const int m = a.m, PL = a.in_pitch;
   const double scale = a.scale;
@@ -234,26 +240,59 @@ __device__ __forceinline__ void dst_plane_p2_body(const PlaneArgs& a, long long 
     // ---- x_2 transforms: column pairs (2c, 2c+1), c = r SR + sc; every pair read is in
     // the padded row (2c + 1 < in_pitch), a missing second column is zeroed
     c64 keep[R][H];
+    if constexpr (p2sz::plane_preload(V)) {
+      c64 v[R][E];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      int tt = t;
-      QBVM_OPAQUE(tt);
-      const int sc = LC::sig(tt), uc = LC::lane(tt);
-      const int col = 2 * (r * SR + sc);
-      const double mb = col + 1 < m ? 1.0 : 0.0;
-      c64 v[E];
+      for (int r = 0; r < R; ++r) {
+        int tt = t;
+        QBVM_OPAQUE(tt);
+        const int sc = LC::sig(tt), uc = LC::lane(tt);
+        const int col = 2 * (r * SR + sc);
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        double sg;
-        const int i = ext(uc + U * e, sg);
-        const c64 w = *reinterpret_cast<const c64*>(src + (long long)i * PL + col);
-        v[e] = {sg * w.re, (mb * sg) * w.im};
+        for (int e = 0; e < E; ++e) {
+          double sg;
+          const int i = ext(uc + U * e, sg);
+          v[r][e] = *reinterpret_cast<const c64*>(src + (long long)i * PL + col);
+        }
       }
-      p2_fft<N, E, LC>(v, sc, uc, buf, tw);
 #pragma unroll
-      for (int h = 0; h < H; ++h) keep[r][h] = v[h];
+      for (int r = 0; r < R; ++r) {
+        int tt = t;
+        QBVM_OPAQUE(tt);
+        const int sc = LC::sig(tt), uc = LC::lane(tt);
+        const double mb = 2 * (r * SR + sc) + 1 < m ? 1.0 : 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          double sg;
+          (void)ext(uc + U * e, sg);
+          v[r][e] = {sg * v[r][e].re, (mb * sg) * v[r][e].im};
+        }
+        p2_fft<N, E, LC>(v[r], sc, uc, buf, tw);
+#pragma unroll
+        for (int h = 0; h < H; ++h) keep[r][h] = v[r][slot(h)];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        int tt = t;
+        QBVM_OPAQUE(tt);
+        const int sc = LC::sig(tt), uc = LC::lane(tt);
+        const int col = 2 * (r * SR + sc);
+        const double mb = col + 1 < m ? 1.0 : 0.0;
+        c64 v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          double sg;
+          const int i = ext(uc + U * e, sg);
+          const c64 w = *reinterpret_cast<const c64*>(src + (long long)i * PL + col);
+          v[e] = {sg * w.re, (mb * sg) * w.im};
+        }
+        p2_fft<N, E, LC>(v, sc, uc, buf, tw);
+#pragma unroll
+        for (int h = 0; h < H; ++h) keep[r][h] = v[slot(h)];
+      }
     }
-    // ---- x_1 transforms, round j: rows N/2 j/R - 1 + (0 .. RJ-1) through LDS as [row][k_1]
+    // ---- x_1 transforms, round j: rows RJ j - 1 + (0 .. RJ-1) through LDS as [row][k_1]
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       int tt = t;
@@ -264,11 +303,9 @@ __device__ __forceinline__ void dst_plane_p2_body(const PlaneArgs& a, long long 
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int h = 0; h < HJ; ++h) {
-          const int e = j * HJ + h;  // output k = uc + U e, local row k - j RJ
+        for (int h = 0; h < HJ; ++h)  // output k = uc + U (HJ j + h), local row k - RJ j
           *reinterpret_cast<c64*>(plane + (size_t)(uc + U * h) * PL + 2 * (r * SR + sc)) =
-              c64{-keep[r][e].im * scale, keep[r][e].re * scale};
-        }
+              c64{-keep[r][HJ * j + h].im * scale, keep[r][HJ * j + h].re * scale};
       __syncthreads();
       const int row = RJ * j - 1 + 2 * sr;  // row pair (row, row + 1), local rows 2 sr, 2 sr + 1
       const double ma = (row >= 0 && row < m) ? 1.0 : 0.0, mb = (row + 1 < m) ? 1.0 : 0.0;
@@ -282,11 +319,12 @@ __device__ __forceinline__ void dst_plane_p2_body(const PlaneArgs& a, long long 
       __syncthreads();  // the rows are read before the exchange reuses the region
       p2_fft<N, E, LR>(w, sr, ur, buf, tw);
 #pragma unroll
-      for (int e = 0; e < H; ++e) {
-        const int k = ur + U * e;  // output k of the row pair = y[row][k - 1]
+      for (int h = 0; h < H; ++h) {
+        const int k = ur + U * h;  // output k of the row pair = y[row][k - 1]
+        const c64 x = w[slot(h)];
         if (k >= 1) {
-          if (ma != 0.0) dst[(long long)row * m + k - 1] = -w[e].im * scale;
-          if (mb != 0.0) dst[(long long)(row + 1) * m + k - 1] = w[e].re * scale;
+          if (ma != 0.0) dst[(long long)row * m + k - 1] = -x.im * scale;
+          if (mb != 0.0) dst[(long long)(row + 1) * m + k - 1] = x.re * scale;
         }
       }
     }

@@ -246,6 +246,7 @@ struct qbvm_plan_s {
   int var_rows = 5, var_cols = 6, var_time = 4;  // set per transform length in create_plan
   int var_gen = 1;                                // time kernel of the general right-hand side
   bool plane = true;  // plane pass (x_2 and x_1 together) where the shape allows it
+  int var_plane = 0;  // plane-pass variant
   double* mu1d = nullptr;
   double* ghat = nullptr;
   double* yrow = nullptr;
@@ -517,7 +518,7 @@ int enqueue_full(const qbvm_plan_s* p, double alpha, const double* alpha_dev, in
       }
       const PlaneArgs pa = sched::plane_args(G, W, y);
       ProfScope ps("dst_plane", stream, 16.0 * elems, elems / p->m * fft_flops(p->sfft->dev), nc);
-      HIP_TRY(launch_plane(pa, stream, nc));
+      HIP_TRY(launch_plane(pa, p->var_plane, stream, nc));
       return QBVM_OK;
     }
     const auto passes = sched::padded_passes(G, W, y);
@@ -1017,8 +1018,9 @@ int time_min_ms(hipStream_t s, F launch, double* out_ms) {
 }  // namespace
 
 // rows variants 0, 1, 3 .. 7; columns the same; time variants 0 .. kTimeVariants2 - 1;
-// general right-hand-side time variants 0 .. kTimeVariants2 - 1
-constexpr int kAutotuneTimings = 14 + 2 * p2sz::kTimeVariants2;
+// general right-hand-side time variants 0 .. kTimeVariants2 - 1; separate x_2 + x_1 passes;
+// plane-pass variants 0 .. kPlaneVariants - 1
+constexpr int kAutotuneTimings = 14 + 2 * p2sz::kTimeVariants2 + 1 + p2sz::kPlaneVariants;
 constexpr double kKeepMargin = 1.03;
 
 extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
@@ -1061,6 +1063,45 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
       int& cur = role == 0 ? p->var_rows : p->var_cols;
       const double tc = p2sz::dst_valid(Ns, cur) ? ms[role * 7 + (cur < 2 ? cur : cur - 1)] : -1.0;
       if (bestv >= 0 && !(tc > 0 && tc <= kKeepMargin * best)) cur = bestv;
+    }
+  }
+  if (p->W && sched::use_plane(geom(p))) {
+    // plane-pass variants against the x_2 columns pass plus the x_1 rows pass they replace
+    const sched::Geom G = geom(p);
+    const auto passes = sched::padded_passes(G, p->W, scratch);
+    double sep = 0.0;
+    for (size_t i = passes.size() - 2; i < passes.size(); ++i) {
+      const auto& L = passes[i];
+      const bool rows = i + 1 == passes.size();
+      double t = 0;
+      const int rc = time_min_ms(p->stream, [&]() -> int {
+        HIP_TRY(launch_dst(L.args, L.nwg, L.args.threads, L.lds, p->stream, nullptr, rows ? 1 : 2));
+        return QBVM_OK;
+      }, &t);
+      if (rc) return rc;
+      sep += t;
+    }
+    ms[kAutotuneTimings - p2sz::kPlaneVariants - 1] = sep;
+    double best = 1e30;
+    int bestv = -1;
+    const PlaneArgs pa = sched::plane_args(G, p->W, scratch);
+    for (int V = 0; V < p2sz::kPlaneVariants; ++V) {
+      double t = 0;
+      const int rc = time_min_ms(p->stream, [&]() -> int {
+        HIP_TRY(launch_plane(pa, V, p->stream, nullptr));
+        return QBVM_OK;
+      }, &t);
+      if (rc) return rc;
+      ms[kAutotuneTimings - p2sz::kPlaneVariants + V] = t;
+      if (t < best) {
+        best = t;
+        bestv = V;
+      }
+    }
+    const double tcur = p->plane ? ms[kAutotuneTimings - p2sz::kPlaneVariants + p->var_plane] : sep;
+    if (!(tcur <= kKeepMargin * std::min(best, sep))) {
+      p->plane = best < sep;
+      if (p->plane) p->var_plane = bestv;
     }
   }
   const bool gt = p->tfft->dev.gtA != 0;
@@ -1130,17 +1171,24 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
   return QBVM_OK;
 }
 
-extern "C" int qbvm_plan_set_plane(qbvm_plan_t p, int on) {
+extern "C" int qbvm_plan_set_plane(qbvm_plan_t p, int variant) {
   if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
-  if (on && !sched::use_plane(geom(p)))
+  if (variant < 0) {
+    p->plane = false;
+    return QBVM_OK;
+  }
+  if (variant >= p2sz::kPlaneVariants) return set_error(QBVM_EINVAL, "no such plane-pass variant");
+  if (!sched::use_plane(geom(p)))
     return set_error(QBVM_EUNSUPPORTED, "the plane pass needs d >= 2, m = 127 and the padded pipeline");
-  p->plane = on != 0;
+  p->plane = true;
+  p->var_plane = variant;
   return QBVM_OK;
 }
 
-extern "C" int qbvm_plan_uses_plane(qbvm_plan_t p) {
-  if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
-  return p->plane && sched::use_plane(geom(p)) ? 1 : 0;
+extern "C" int qbvm_plan_get_plane(qbvm_plan_t p, int* variant) {
+  if (!p || !variant) return set_error(QBVM_EINVAL, "NULL argument");
+  *variant = p->plane && sched::use_plane(geom(p)) ? p->var_plane : -1;
+  return QBVM_OK;
 }
 
 extern "C" int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var_time,

@@ -25,7 +25,7 @@ hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds
 hipError_t launch_time_general(const TimeArgs& a, long long nwg, size_t lds, hipStream_t s);
 hipError_t launch_tab_job(const TabJob& t, hipStream_t s);
 // plane pass (qbvm_plane.hip): x_2 and x_1 transforms of every plane, sine length 256
-hipError_t launch_plane(const PlaneArgs& a, hipStream_t s, NodeCtx* nc = nullptr);
+hipError_t launch_plane(const PlaneArgs& a, int var, hipStream_t s, NodeCtx* nc = nullptr);
 hipError_t launch_thomas(const ThomasArgs& a, long long nwg, size_t lds, hipStream_t s, NodeCtx* nc = nullptr);
 hipError_t launch_time1d(const Time1dArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,
                          NodeCtx* nc = nullptr);

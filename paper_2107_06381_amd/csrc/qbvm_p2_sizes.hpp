@@ -109,25 +109,30 @@ constexpr size_t gt_lds(int A, int B, int V) {
   return sizeof(c64) * ((size_t)(2 * gt_KC(V) + 1) * A * gt_S(V) + 2 * (size_t)A * B);
 }
 
-// Plane pass (x_2 and x_1 sine transforms of one [m][P1] plane per iteration): sine
-// length N = 2(m+1) with E = 16 values per lane (one exchange per transform) and 512
-// lanes, so N/16 lanes per signal and SR = 8192/N signals per round; the N/4 column (row)
-// pairs of a plane take N/(4 SR) rounds.  One LDS region serves the exchanges of a round (columns: padded
-// [position][signal]; rows: XOR-mapped [signal][position]) and, between them, the rows
-// of the transposed plane that the next round of row pairs reads; the twiddle table
-// follows it.
-constexpr int kPlaneT = 512;
-constexpr int kPlaneE = 16;
-constexpr int plane_SR(int N) { return kPlaneT / (N / kPlaneE); }
-constexpr int plane_rounds(int N) { return (N / 4 + plane_SR(N) - 1) / plane_SR(N); }
+// Plane pass (x_2 and x_1 sine transforms of one [m][P1] plane per iteration), variants:
+//   0: E = 16, 512 lanes;  1: E = 8, 1024 lanes;  2: as 0, the column loads of both rounds
+//   issued before the first transform.
+// With sine length N = 2(m+1), N/E lanes carry a signal and SR = T E/N signals run per
+// round; the N/4 column (row) pairs of a plane take N/(4 SR) rounds.  One LDS region
+// serves the exchanges of a round (columns: padded [position][signal]; rows: XOR-mapped
+// [signal][position]) and, between them, the 2 SR rows of the transposed plane that the
+// next round of row pairs reads; the twiddle table follows it.
+constexpr int kPlaneVariants = 3;
+constexpr int plane_T(int V) { return V == 1 ? 1024 : 512; }
+constexpr int plane_E(int V) { return V == 1 ? 8 : 16; }
+constexpr bool plane_preload(int V) { return V == 2; }
+constexpr int plane_SR(int N, int V) { return plane_T(V) * plane_E(V) / N; }
+constexpr int plane_rounds(int N, int V) { return (N / 4 + plane_SR(N, V) - 1) / plane_SR(N, V); }
 constexpr size_t cmax(size_t x, size_t y) { return x > y ? x : y; }
 constexpr int plane_pitch(int N) { return (N / 2 - 1 + 63) / 64 * 64; }  // P1 of m = N/2 - 1
-constexpr size_t plane_region_elems(int N) {  // in c64 units
-  return cmax(cmax((size_t)(N + N / first_radix(N, kPlaneE)) * plane_SR(N), (size_t)N * plane_SR(N)),
-              (size_t)(N / 2 / plane_rounds(N)) * plane_pitch(N) / 2);
+constexpr size_t plane_region_elems(int N, int V) {  // in c64 units
+  return cmax(cmax((size_t)(N + N / first_radix(N, plane_E(V))) * plane_SR(N, V), (size_t)N * plane_SR(N, V)),
+              (size_t)2 * plane_SR(N, V) * plane_pitch(N) / 2);
 }
-constexpr size_t plane_lds(int N) { return sizeof(c64) * (plane_region_elems(N) + (size_t)N); }
-constexpr bool plane_valid(int N) { return N == 256 && plane_lds(N) <= 160 * 1024; }
+constexpr size_t plane_lds(int N, int V) { return sizeof(c64) * (plane_region_elems(N, V) + (size_t)N); }
+constexpr bool plane_valid(int N, int V) {
+  return N == 256 && V >= 0 && V < kPlaneVariants && plane_lds(N, V) <= 160 * 1024;
+}
 
 }  // namespace p2sz
 }  // namespace qbvm

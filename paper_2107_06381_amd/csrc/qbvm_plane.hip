@@ -12,15 +12,15 @@
 
 namespace qbvm {
 
-template <int N>
-__global__ __launch_bounds__(p2sz::kPlaneT) void k_dst_plane_p2(PlaneArgs a) {
+template <int N, int V>
+__global__ __launch_bounds__(p2sz::plane_T(V)) void k_dst_plane_p2(PlaneArgs a) {
   extern __shared__ c64 lds[];
-  dst_plane_p2_body<N>(a, blockIdx.x, gridDim.x, lds);
+  dst_plane_p2_body<N, V>(a, blockIdx.x, gridDim.x, lds);
 }
 
 // Resident workgroups of the plane kernel on the current device (one per CU at its LDS
 // size), cached per device; the dynamic-LDS limit is raised once per device.
-static hipError_t plane_grid(const void* f, size_t lds, long long planes, long long* nwg) {
+static hipError_t plane_grid(const void* f, int threads, size_t lds, long long planes, long long* nwg) {
   static std::mutex mu;
   static std::map<std::tuple<const void*, int>, long long> cap_of;
   int dev = 0;
@@ -37,7 +37,7 @@ static hipError_t plane_grid(const void* f, size_t lds, long long planes, long l
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, p2sz::kPlaneT, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, threads, lds);
     if (e != hipSuccess) return e;
     it = cap_of.emplace(std::make_tuple(f, dev), (long long)(per < 1 ? 1 : per) * (cus < 1 ? 1 : cus)).first;
   }
@@ -45,20 +45,24 @@ static hipError_t plane_grid(const void* f, size_t lds, long long planes, long l
   return hipSuccess;
 }
 
-hipError_t launch_plane(const PlaneArgs& a, hipStream_t s, NodeCtx* nc) {
-  if (a.fft.p2 != 256 || !p2sz::plane_valid(256) || a.in_pitch != p2sz::plane_pitch(256) || a.m != 127)
+hipError_t launch_plane(const PlaneArgs& a, int var, hipStream_t s, NodeCtx* nc) {
+  if (a.fft.p2 != 256 || !p2sz::plane_valid(256, var) || a.in_pitch != p2sz::plane_pitch(256) || a.m != 127)
     return hipErrorInvalidValue;
-  const void* f = (const void*)&k_dst_plane_p2<256>;
-  const size_t lds = p2sz::plane_lds(256);
+  static const void* fns[p2sz::kPlaneVariants] = {(const void*)&k_dst_plane_p2<256, 0>,
+                                                  (const void*)&k_dst_plane_p2<256, 1>,
+                                                  (const void*)&k_dst_plane_p2<256, 2>};
+  const void* f = fns[var];
+  const int threads = p2sz::plane_T(var);
+  const size_t lds = p2sz::plane_lds(256, var);
   long long nwg = 0;
-  hipError_t e = plane_grid(f, lds, a.planes, &nwg);
+  hipError_t e = plane_grid(f, threads, lds, a.planes, &nwg);
   if (e != hipSuccess || nwg < 1) return e != hipSuccess ? e : hipErrorInvalidValue;
   void* args[] = {const_cast<PlaneArgs*>(&a)};
-  if (!nc) return hipLaunchKernel(f, dim3((unsigned)nwg), dim3(p2sz::kPlaneT), args, lds, s);
+  if (!nc) return hipLaunchKernel(f, dim3((unsigned)nwg), dim3(threads), args, lds, s);
   hipKernelNodeParams p{};
   p.func = const_cast<void*>(f);
   p.gridDim = dim3((unsigned)nwg);
-  p.blockDim = dim3(p2sz::kPlaneT);
+  p.blockDim = dim3(threads);
   p.sharedMemBytes = (unsigned)lds;
   p.kernelParams = args;
   p.extra = nullptr;

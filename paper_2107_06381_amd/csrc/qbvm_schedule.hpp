@@ -163,7 +163,7 @@ inline std::vector<Launch<DstArgs>> padded_passes(const Geom& g, double* W, doub
 // to every [m][P1] plane of W and writes y: 16 bytes per unknown fewer than a columns
 // pass and a rows pass.
 inline bool use_plane(const Geom& g) {
-  return use_padded(g) && g.sfft.p2 == 256 && p2sz::plane_valid(256) && g.m == 127 &&
+  return use_padded(g) && g.sfft.p2 == 256 && p2sz::plane_valid(256, 0) && g.m == 127 &&
          padded_pitch(g.m) == p2sz::plane_pitch(256);
 }
 inline std::vector<Launch<DstArgs>> plane_pre_passes(const Geom& g, double* W) {

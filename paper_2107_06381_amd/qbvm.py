@@ -32,7 +32,7 @@ EXPORTS = [
     "qbvm_mlp_forward", "qbvm_mlp_loss_grad", "qbvm_mlp_loss_grad_noalloc", "qbvm_adam_step", "qbvm_strerror",
     "qbvm_last_error", "qbvm_version", "qbvm_profile_enable", "qbvm_profile_reset",
     "qbvm_profile_count", "qbvm_profile_get", "qbvm_plan_autotune", "qbvm_plan_get_variants",
-    "qbvm_plan_set_variants", "qbvm_plan_set_operator_1d", "qbvm_plan_set_plane", "qbvm_plan_uses_plane",
+    "qbvm_plan_set_variants", "qbvm_plan_set_operator_1d", "qbvm_plan_set_plane", "qbvm_plan_get_plane",
 ]
 
 
@@ -104,7 +104,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qbvm_plan_set_variants": (i, [vp, i, i, i, i]),
         "qbvm_plan_set_operator_1d": (i, [vp, vp, vp, vp]),
         "qbvm_plan_set_plane": (i, [vp, i]),
-        "qbvm_plan_uses_plane": (i, [vp]),
+        "qbvm_plan_get_plane": (i, [vp, ctypes.POINTER(i)]),
         "qbvm_profile_enable": (None, [i]),
         "qbvm_profile_reset": (None, []),
         "qbvm_profile_count": (i, []),
@@ -181,11 +181,12 @@ class Plan:
 
     def autotune(self) -> dict:
         """Time the kernel variants on this plan's shape and keep the fastest."""
-        ms = (ctypes.c_double * 26)()
+        ms = (ctypes.c_double * 30)()
         _check(self.L_.qbvm_plan_autotune(self._h, ms))
         v = [round(x, 5) for x in ms]
         return {"ms_rows_v0134567": v[0:7], "ms_cols_v0134567": v[7:14], "ms_time_v012345": v[14:20],
-                "ms_general_v012345": v[20:26], "variants": self.variants()}
+                "ms_general_v012345": v[20:26], "ms_separate_x2_x1": v[26], "ms_plane_v012": v[27:30],
+                "variants": self.variants(), "plane_variant": self.plane_variant()}
 
     def variants(self):
         r, c, t, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
@@ -209,15 +210,18 @@ class Plan:
         """Select kernel variants by hand (-1 keeps the current one)."""
         _check(self.L_.qbvm_plan_set_variants(self._h, int(rows), int(cols), int(time), int(general)))
 
-    def set_plane(self, on: bool):
-        """qbvm_plan_set_plane: the x_2/x_1 plane pass on (where the shape allows it) or off."""
-        _check(self.L_.qbvm_plan_set_plane(self._h, 1 if on else 0))
+    def set_plane(self, on: bool, variant: int = 0):
+        """qbvm_plan_set_plane: the x_2/x_1 plane pass (this variant) on, or off."""
+        _check(self.L_.qbvm_plan_set_plane(self._h, int(variant) if on else -1))
+
+    def plane_variant(self) -> int:
+        """Plane-pass variant qbvm_solve uses, -1 for the separate passes."""
+        v = ctypes.c_int()
+        _check(self.L_.qbvm_plan_get_plane(self._h, ctypes.byref(v)))
+        return v.value
 
     def uses_plane(self) -> bool:
-        rc = self.L_.qbvm_plan_uses_plane(self._h)
-        if rc < 0:
-            _check(rc)
-        return rc == 1
+        return self.plane_variant() >= 0
 
     def out_shape(self, output: int):
         sp = (self.m,) * self.d

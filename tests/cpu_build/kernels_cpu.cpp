@@ -3,6 +3,7 @@
 // oracle.  Usage:
 //   kernels_cpu fft   n S in.bin out.bin          (S signals, signal-major complex)
 //   kernels_cpu solve d m n L T alpha variant in.bin out.bin [var_rows var_cols var_time [padded [plane]]]
+//       (plane: 0 = separate x_2 / x_1 passes, v + 1 = plane-pass variant v)
 //   kernels_cpu dst   d m batch in.bin out.bin [var_rows var_cols input]
 //   kernels_cpu general d m n L T alpha variant f.bin out.bin [padded var_gen]   (general right-hand side)
 //   kernels_cpu solveop m n L T alpha variant in.bin out.bin op.bin level   (1D, tridiagonal operator;
@@ -14,6 +15,7 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "../../paper_2107_06381_amd/csrc/qbvm_bodies_p2.hpp"
@@ -470,6 +472,8 @@ int main(int argc, char** argv) {
     const SolveScalars sc = sched::host_scalars(alpha, variant, g.tau);
     const bool padded = sched::use_padded(g) && !(argc >= 15 && atoi(argv[14]) == 0);
     const bool want_plane = argc == 16 && atoi(argv[15]) != 0;
+    const int pvar = want_plane ? atoi(argv[15]) - 1 : 0;  // plane argument: variant + 1
+    if (want_plane && !p2sz::plane_valid(256, pvar)) return 20;
     if (want_plane && !(padded && sched::use_plane(g))) return 19;
     if (padded) {
       double* gh = new double[g.nmodes];
@@ -489,8 +493,14 @@ int main(int argc, char** argv) {
         const PlaneArgs pa = sched::plane_args(g, W, y);
         for (size_t q = 0; q < (size_t)g.Nt * g.nmodes; ++q) y[q] = std::nan("");  // every output written
         const long long G = pa.planes < 3 ? pa.planes : 3;  // a few workgroups, several planes each
-        run_grid(G, p2sz::kPlaneT, p2sz::plane_lds(256),
-                 [&](long long wg, c64* l) { dst_plane_p2_body<256>(pa, wg, G, l); });
+        auto run_plane = [&](auto vc) {
+          constexpr int PV = decltype(vc)::value;
+          run_grid(G, p2sz::plane_T(PV), p2sz::plane_lds(256, PV),
+                   [&](long long wg, c64* l) { dst_plane_p2_body<256, PV>(pa, wg, G, l); });
+        };
+        if (pvar == 0) run_plane(std::integral_constant<int, 0>{});
+        else if (pvar == 1) run_plane(std::integral_constant<int, 1>{});
+        else run_plane(std::integral_constant<int, 2>{});
       } else {
         for (const auto& Lz : sched::padded_passes(g, W, y)) {
           P2_SWITCH(Lz.args.fft.p2, dst_p2_n, Lz)

@@ -125,12 +125,12 @@ def test_solve_schedule_vs_oracle(exe, tmp_path, case, kv):
     assert ok, r
 
 
-@pytest.mark.parametrize("d,m,n,alpha,variant,plane", [(2, 127, 63, 1e-4, 0, 1), (2, 127, 128, 1e-3, 1, 1),
-                                                        (2, 127, 63, 1e-4, 0, 0)])
+@pytest.mark.parametrize("d,m,n,alpha,variant,plane", [(2, 127, 63, 1e-4, 0, 1), (2, 127, 128, 1e-3, 1, 2),
+                                                        (2, 127, 63, 1e-5, 0, 3), (2, 127, 63, 1e-4, 0, 0)])
 def test_plane_pass_vs_oracle(exe, tmp_path, d, m, n, alpha, variant, plane):
     """The plane pass (x_2 and x_1 sine transforms of each level in one kernel; padded
-    pipeline, sine length 256) against the closed form, and the separate passes it replaces;
-    the output is preset to NaN, so every value must be written."""
+    pipeline, sine length 256; plane = variant + 1) against the closed form, and the separate
+    passes it replaces (plane = 0); the output is preset to NaN, so every value must be written."""
     L, T = 1.0, 0.9
     g = np.random.default_rng(5).standard_normal((m,) * d)
     fi, fo = tmp_path / "i.bin", tmp_path / "o.bin"

@@ -126,18 +126,21 @@ def test_config_3d_every_level():
     inst = W.config_3d()
     m, n = 127, 128
     p = qbvm.Plan(3, m, n, 1.0, 0.5)
-    say("variants", p.autotune()["variants"], "plane pass", p.uses_plane())
-    assert p.uses_plane()
+    tune = p.autotune()
+    say("variants", tune["variants"], "plane pass", tune["plane_variant"], tune["ms_separate_x2_x1"], tune["ms_plane_v012"])
     y = p.solve(1e-5, 0, to_dev(inst.g_delta))
     torch.cuda.synchronize()
     assert bool(torch.isfinite(y).all())
-    p.set_plane(False)  # the separate x_2 and x_1 passes: same values to rounding
-    y2 = p.solve(1e-5, 0, to_dev(inst.g_delta))
-    torch.cuda.synchronize()
-    diff = float(torch.linalg.vector_norm(y2 - y) / torch.linalg.vector_norm(y))
-    say("plane vs separate passes", diff)
-    assert diff < 1e-13
-    del y2
+    # the other schedules (separate x_2 and x_1 passes, every plane-pass variant): same
+    # values to rounding
+    for v in [-1, 0, 1, 2]:
+        p.set_plane(v >= 0, max(v, 0))
+        y2 = p.solve(1e-5, 0, to_dev(inst.g_delta))
+        torch.cuda.synchronize()
+        diff = float(torch.linalg.vector_norm(y2 - y) / torch.linalg.vector_norm(y))
+        say("schedule", v, "vs autotuned", diff)
+        assert diff < 1e-13
+        del y2
     p.close()
     worst = 0.0
     with scipy.fft.set_workers(min(16, len(os.sched_getaffinity(0)))):
@@ -153,15 +156,16 @@ def test_config_3d_every_level():
     del y
 
 
-@pytest.mark.parametrize("n,alpha,variant", [(128, 1e-4, 0), (127, 1e-2, 1), (63, 1e-6, 0)])
-def test_plane_pass_2d_vs_oracle(n, alpha, variant):
+@pytest.mark.parametrize("n,alpha,variant,pv", [(128, 1e-4, 0, 0), (127, 1e-2, 1, 1), (63, 1e-6, 0, 2)])
+def test_plane_pass_2d_vs_oracle(n, alpha, variant, pv):
     """2D m = 127 (sine length 256): the plane pass does both sine transforms of each level;
-    every level against the closed form, on and off."""
-    say(f"[case] plane pass 2d m=127 n={n}")
+    every level against the closed form, with plane-pass variant pv and with the separate passes."""
+    say(f"[case] plane pass 2d m=127 n={n} variant {pv}")
     m = 127
     g = np.random.default_rng(n).standard_normal((m, m))
     p = qbvm.Plan(2, m, n, 1.0, 1.0)
-    assert p.uses_plane()
+    p.set_plane(True, pv)
+    assert p.plane_variant() == pv
     y = p.solve(alpha, variant, to_dev(g)).cpu().numpy()
     p.set_plane(False)
     assert not p.uses_plane()
