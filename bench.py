@@ -170,7 +170,8 @@ def solve_bench(inst, steps: int, warmup: int, tag: str, parity_levels=None):
     bytes_per_launch = r["bytes"] / r["launches"]
     achieved = bytes_per_launch / avg_s / 1e9
     role = ROLE_OF_KERNEL.get(dom)
-    traffic = read_traffic(dom, tag, tune["variants"][role]) if role else None
+    var = tune["plane_variant"] if dom == "dst_plane" else (tune["variants"][role] if role else None)
+    traffic = read_traffic(dom, tag, var) if var is not None else None
     step_bytes = sum(v["bytes"] for v in rep.values()) / steps
     numel = y.numel()
     del y
@@ -458,6 +459,9 @@ def _kernel_role(name: str, w: dict):
         if var == 2 and ("rows" in mm.group(1) or "false" in name):
             return ("dst_input", var)
         return ("dst_" + mm.group(1), var)
+    mm = re.search(r"k_dst_plane_p2<(\d+), (\d+)>", name)
+    if mm and int(mm.group(1)) == n:
+        return ("dst_plane", int(mm.group(2)))
     if w["time_prefix"] in name:
         mm = re.search(r"k_time_(?:gt<\d+, \d+|p2<\d+), (\d+)", name)
         if mm:

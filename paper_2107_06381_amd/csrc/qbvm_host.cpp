@@ -1044,7 +1044,9 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
         sched::Geom G = geom(p);
         G.var_rows = G.var_cols = V;
         const bool pad = p->W != nullptr;
-        const auto passes = pad ? sched::padded_passes(G, p->W, scratch) : sched::dst_passes(G, scratch, scratch, p->Nt, false);
+        auto passes = pad ? sched::padded_passes(G, p->W, scratch) : sched::dst_passes(G, scratch, scratch, p->Nt, false);
+        // 3D with the plane pass: the only columns pass is the x_3 pass (stride P1 m)
+        if (pad && role == 1 && p->d == 3 && sched::use_plane(G)) passes = sched::plane_pre_passes(G, p->W);
         const auto& L = pad ? passes[role == 0 ? passes.size() - 1 : 0] : passes[role == 0 ? 0 : 1];
         double t = 0;
         const int rc = time_min_ms(p->stream, [&]() -> int {

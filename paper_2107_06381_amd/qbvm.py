@@ -70,6 +70,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} not found: build it with `python -m paper_2107_06381_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded, so both share
+    # one runtime (a second copy of the runtime in the process would not see the device)
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
     sig = {
