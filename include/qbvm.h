@@ -206,9 +206,16 @@ int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f
 /* Solve `count` independent instances of possibly different grids in one
  * batched launch sequence (an addition; not in the paper).  All arrays of
  * length `count` are HOST arrays; g_deltas[i] and ys[i] are DEVICE pointers
- * with the sizes qbvm_solve documents for grids[i] and outputs[i].  Plans,
- * descriptor tables and a captured HIP graph are cached by the set of grids;
- * the call is asynchronous on hip_stream (the descriptor upload is ordered on it). */
+ * with the sizes qbvm_solve documents for grids[i] and outputs[i] (every output mode is
+ * supported).  The launch sequence is one HIP graph per set of (grid, variant, output):
+ * the 1D instances with every level run as two persistent launches over device tables
+ * of their argument blocks (uploaded with every call), every other instance as its own
+ * chain of kernels; alpha is read from a device table uploaded with every call.  A later
+ * call with the same set reuses the graph, for new buffers too (their addresses are
+ * written into the recorded launches).  At most 8 sets are kept (least recently used
+ * dropped); plans are cached per grid.  Asynchronous on hip_stream (the uploads are
+ * ordered on it).  A single-level output of a 1D grid whose sine transform exceeds the
+ * FFT core: QBVM_EUNSUPPORTED. */
 int qbvm_solve_batched(int count, const qbvm_grid* grids, const double* alphas,
                        const int* variants, const double* const* g_deltas,
                        double* const* ys, const int* outputs, void* hip_stream);

@@ -21,6 +21,16 @@ __device__ __forceinline__ SolveScalars scalars_from_alpha(double alpha, int var
   return s;
 }
 
+// The solve's scalars on the device, from alpha in a device table entry or from the value
+// the host passed: every path (one solve, batched, alpha choice) derives them with the
+// same arithmetic, so they give bitwise the same results for the same alpha.
+__device__ __forceinline__ SolveScalars solve_scalars(const SolveScalars& host, const double* alpha_dev,
+                                                      int variant, double tau) {
+  SolveScalars s = scalars_from_alpha(alpha_dev ? *alpha_dev : host.alpha, variant, tau);
+  s.alpha = alpha_dev ? *alpha_dev : host.alpha;
+  return s;
+}
+
 // d_j / tau with d_j = 1 - omega^{1/N_t} theta^j = 1 - |omega|^{1/N_t} exp(i pi (2j+1)/N_t)
 __device__ __forceinline__ c64 shift_over_tau(int j, int Nt, double croot, double inv_tau) {
   double sn, cs;
@@ -161,8 +171,7 @@ __device__ __forceinline__ void time_body(const TimeArgs& a, long long wg, c64* 
   double* mus = reinterpret_cast<double*>(gi + a.lev_count);
   double* gh = mus + 2 * S;
 
-  SolveScalars sc = a.sc;
-  if (a.alpha_dev) sc = scalars_from_alpha(*a.alpha_dev, a.variant, a.tau);
+  const SolveScalars sc = solve_scalars(a.sc, a.alpha_dev, a.variant, a.tau);
   const double croot = exp(sc.logabsw / (double)Nt);
   const double inv_tau = 1.0 / a.tau;
   const double gscale = sc.f0s / (double)Nt;
@@ -322,7 +331,7 @@ __device__ __forceinline__ void tri1d_body(const ThomasArgs& a, long long wg, c6
   const long long jl = wg * a.S + sl;
   const bool live = sl < a.S && jl < Nt;
   const int j = live ? (int)jl : 0;
-  const SolveScalars sc = a.alpha_dev ? scalars_from_alpha(*a.alpha_dev, a.variant, a.tau) : a.sc;
+  const SolveScalars sc = solve_scalars(a.sc, a.alpha_dev, a.variant, a.tau);
   const double croot = exp(sc.logabsw / (double)Nt);
   const c64 z = shift_over_tau(j, Nt, croot, 1.0 / a.tau);
   const double ih2 = 1.0 / (a.h * a.h);
@@ -458,7 +467,7 @@ __device__ __forceinline__ void time1d_body(const Time1dArgs& a, long long wg, c
   const c64* gi = a.gitab ? a.gitab + Nt + a.lev_first : side + 2 * S;
   if (!a.gitab) {
     const double gscale = 1.0 / (double)Nt;
-    const SolveScalars sc = a.alpha_dev ? scalars_from_alpha(*a.alpha_dev, a.variant, a.tau) : a.sc;
+    const SolveScalars sc = solve_scalars(a.sc, a.alpha_dev, a.variant, a.tau);
     c64* gl = side + 2 * S;
     for (int li = threadIdx.x; li < a.lev_count; li += blockDim.x)
       gl[li] = inv_gamma(a.lev_first + li, Nt, sc.logabsw, gscale);

@@ -84,8 +84,7 @@ __device__ __forceinline__ void time_gt_body(const TimeArgs& a, long long wg, c6
   const int t = threadIdx.x, s = t % S;
   const int ra = __builtin_amdgcn_readfirstlane(t / S);  // uniform across the wave
 
-  SolveScalars sc = a.sc;
-  if (a.alpha_dev) sc = scalars_from_alpha(*a.alpha_dev, a.variant, a.tau);
+  const SolveScalars sc = solve_scalars(a.sc, a.alpha_dev, a.variant, a.tau);
   if (a.tabs) {
     for (int j = t; j < N; j += T) {
       dt[j] = a.tabs[j];

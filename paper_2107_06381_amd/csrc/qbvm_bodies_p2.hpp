@@ -438,8 +438,7 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
   const M sh(lds, Nt);
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
 
-  SolveScalars sc = a.sc;
-  if (a.alpha_dev) sc = scalars_from_alpha(*a.alpha_dev, a.variant, a.tau);
+  const SolveScalars sc = solve_scalars(a.sc, a.alpha_dev, a.variant, a.tau);
   const double croot = exp(sc.logabsw / (double)Nt);
   const double inv_tau = 1.0 / a.tau;
   const double gscale = sc.f0s / (double)Nt;

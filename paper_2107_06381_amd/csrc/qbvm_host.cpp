@@ -1228,18 +1228,33 @@ struct BatchEntry {
   int device = 0;
   std::vector<qbvm_grid> grids;
   std::vector<int> variants, outputs;
-  std::vector<const double*> gs;
+  std::vector<const double*> gs;  // buffers the graph's arguments refer to now
   std::vector<double*> ys;
   std::vector<qbvm_plan_s*> plans;  // owned by g_batch_plans
   double* alphas_dev = nullptr;
-  std::vector<void*> ws;  // per-instance workspaces
+  std::vector<void*> ws;             // per-instance workspaces
+  std::vector<c64*> s2;              // 1D, every level: shifted solutions [N_t][m]
+  std::vector<double*> ghat, yrow;   // one level: sine coefficients and the level's modes
+  // 1D instances with every level: two persistent launches over argument tables
+  std::vector<int> b1d;              // their instance indices
+  std::vector<ThomasArgs> targs;     // host copies of the tables (rewritten for new buffers)
+  std::vector<Time1dArgs> t1args;
+  ThomasArgs* targs_dev = nullptr;
+  Time1dArgs* t1args_dev = nullptr;
+  int* items_dev = nullptr;          // tridiagonal items, then narrow and wide time items
+  int n_tri = 0, n_t1[2] = {0, 0};
+  size_t lds_tri = 0, lds_t1[2] = {0, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::vector<hipGraphNode_t> nodes;  // kernel nodes of the per-instance chains, in launch order
+  unsigned long long last_use = 0;
 };
 
+constexpr size_t kBatchCacheEntries = 8;
 std::mutex g_batch_mu;
 std::vector<std::unique_ptr<BatchEntry>> g_batches;
 std::map<std::tuple<int, int, int, int, double, double>, qbvm_plan_s*> g_batch_plans;
+unsigned long long g_batch_clock = 0;
 
 bool same_grid(const qbvm_grid& a, const qbvm_grid& b) {
   return a.d == b.d && a.m == b.m && a.n == b.n && a.L == b.L && a.T == b.T;
@@ -1250,6 +1265,67 @@ void free_entry(BatchEntry* e) {
   if (e->graph) (void)hipGraphDestroy(e->graph);
   for (void* w : e->ws) (void)hipFree(w);
   if (e->alphas_dev) (void)hipFree(e->alphas_dev);
+  if (e->targs_dev) (void)hipFree(e->targs_dev);
+  if (e->t1args_dev) (void)hipFree(e->t1args_dev);
+  if (e->items_dev) (void)hipFree(e->items_dev);
+}
+
+// 1D instance with every level: it runs in the batched tridiagonal and time launches
+bool in_batch_1d(const BatchEntry* e, int i) { return e->plans[i]->d == 1 && e->outputs[i] == QBVM_OUT_ALL; }
+
+// Argument blocks of the batched 1D launches for the entry's current buffers.
+void fill_batch_1d_args(BatchEntry* e) {
+  for (size_t k = 0; k < e->b1d.size(); ++k) {
+    const int i = e->b1d[k];
+    const qbvm_plan_s* p = e->plans[i];
+    const sched::Geom G = geom(p);
+    const SolveScalars sc = sched::host_scalars(1.0, e->variants[i], p->tau);  // alpha from the table
+    e->targs[k] = sched::thomas_step(G, sc, e->alphas_dev + i, e->variants[i], e->gs[i], e->s2[i]).args;
+    e->t1args[k] = sched::time1d_step(G, sc, e->alphas_dev + i, e->variants[i], e->s2[i], e->ys[i]).args;
+  }
+}
+
+// The per-instance chains in a fixed order (nc records or updates their nodes): all
+// levels of a d >= 2 instance, or one level (d >= 1) by the sine transform of g, one DFT
+// row per mode and the sine transform back.
+int enqueue_instances(BatchEntry* e, NodeCtx& base, hipStream_t stream) {
+  const int count = (int)e->grids.size();
+  for (int i = 0; i < count; ++i) {
+    if (in_batch_1d(e, i)) continue;
+    qbvm_plan_s* p = e->plans[i];
+    NodeCtx nc = base;
+    nc.dep = nullptr;
+    nc.has_dep = false;
+    int rc;
+    if (e->outputs[i] == QBVM_OUT_ALL) {
+      rc = enqueue_full(p, 1.0, e->alphas_dev + i, e->variants[i], e->gs[i], e->ys[i], nullptr, &nc, stream);
+    } else {
+      rc = run_dst(p, e->gs[i], e->ghat[i], 1, true, &nc, stream);
+      if (!rc) {
+        RowArgs r{};
+        r.Nt = p->Nt;
+        r.d = p->d;
+        r.m = p->m;
+        r.level = e->outputs[i] == QBVM_OUT_Y0 ? 0 : p->n;
+        r.count = 1;
+        r.nmodes = p->nmodes;
+        r.tau = p->tau;
+        r.hd = p->hd;
+        r.variant = e->variants[i];
+        r.mu1d = p->mu1d;
+        r.ghat = e->ghat[i];
+        r.yrow = e->yrow[i];
+        r.wg_per_inst = p->wg_row;
+        r.alpha = 1.0;
+        r.alpha_dev = e->alphas_dev + i;
+        HIP_TRY(launch_row(r, p->wg_row, kThreads, sizeof(c64) * 2 * p->Nt, stream, &nc));
+        rc = run_dst(p, e->yrow[i], e->ys[i], 1, false, &nc, stream);
+      }
+    }
+    if (rc) return rc;
+    base.next = nc.next;
+  }
+  return QBVM_OK;
 }
 
 int build_entry(BatchEntry* e, int count, hipStream_t stream) {
@@ -1265,27 +1341,71 @@ int build_entry(BatchEntry* e, int count, hipStream_t stream) {
       it = g_batch_plans.emplace(key, p).first;
     }
     e->plans[i] = it->second;
+    if (e->outputs[i] != QBVM_OUT_ALL && e->plans[i]->no_sine)
+      return set_error(QBVM_EUNSUPPORTED, "single-level output of a 1D grid without its sine transform");
   }
   HIP_TRY(hipMalloc((void**)&e->alphas_dev, sizeof(double) * count));
-  HIP_TRY(hipGraphCreate(&e->graph, 0));
+  e->s2.assign(count, nullptr);
+  e->ghat.assign(count, nullptr);
+  e->yrow.assign(count, nullptr);
   for (int i = 0; i < count; ++i) {
-    qbvm_plan_s* p = e->plans[i];
-    NodeCtx nc{e->graph, nullptr, false};
-    c64* s2 = nullptr;
-    const int out = e->outputs[i];
-    if (out == QBVM_OUT_ALL && p->d == 1) {
-      void* w = nullptr;
+    const qbvm_plan_s* p = e->plans[i];
+    void* w = nullptr;
+    if (in_batch_1d(e, i)) {
       HIP_TRY(hipMalloc(&w, sizeof(c64) * (size_t)p->Nt * p->m));
       e->ws.push_back(w);
-      s2 = static_cast<c64*>(w);
+      e->s2[i] = static_cast<c64*>(w);
+      e->b1d.push_back(i);
+    } else if (e->outputs[i] != QBVM_OUT_ALL) {
+      HIP_TRY(hipMalloc(&w, sizeof(double) * 2 * (size_t)p->nmodes));
+      e->ws.push_back(w);
+      e->ghat[i] = static_cast<double*>(w);
+      e->yrow[i] = e->ghat[i] + p->nmodes;
     }
-    // one plan may serve many instances: only its tables and geometry are used here
-    int rc;
-    if (out == QBVM_OUT_ALL) {
-      rc = enqueue_full(p, 1.0, e->alphas_dev + i, e->variants[i], e->gs[i], e->ys[i], s2, &nc, stream);
-      if (rc) return rc;
-    } else {
-      return set_error(QBVM_EUNSUPPORTED, "batched solve supports QBVM_OUT_ALL");
+  }
+  HIP_TRY(hipGraphCreate(&e->graph, 0));
+  NodeCtx nc{e->graph, nullptr, false};
+  nc.nodes = &e->nodes;
+  int rc = enqueue_instances(e, nc, stream);
+  if (rc) return rc;
+  if (!e->b1d.empty()) {
+    const size_t nb = e->b1d.size();
+    e->targs.resize(nb);
+    e->t1args.resize(nb);
+    fill_batch_1d_args(e);
+    std::vector<int> items;  // (instance, workgroup) pairs: tridiagonal, narrow time, wide time
+    for (size_t k = 0; k < nb; ++k) {
+      const qbvm_plan_s* p = e->plans[e->b1d[k]];
+      const auto ta = sched::thomas_step(geom(p), SolveScalars{}, nullptr, 0, nullptr, nullptr);
+      for (long long w = 0; w < ta.nwg; ++w) items.insert(items.end(), {(int)k, (int)w});
+      e->lds_tri = std::max(e->lds_tri, ta.lds);
+    }
+    e->n_tri = (int)(items.size() / 2);
+    for (int wide = 0; wide < 2; ++wide) {
+      const size_t before = items.size();
+      for (size_t k = 0; k < nb; ++k) {
+        const qbvm_plan_s* p = e->plans[e->b1d[k]];
+        if ((p->tfft->dev.wide != 0) != (wide != 0)) continue;
+        const auto t = sched::time1d_step(geom(p), SolveScalars{}, nullptr, 0, nullptr, nullptr);
+        for (long long w = 0; w < t.nwg; ++w) items.insert(items.end(), {(int)k, (int)w});
+        e->lds_t1[wide] = std::max(e->lds_t1[wide], t.lds);
+      }
+      e->n_t1[wide] = (int)((items.size() - before) / 2);
+    }
+    HIP_TRY(hipMalloc((void**)&e->targs_dev, sizeof(ThomasArgs) * nb));
+    HIP_TRY(hipMalloc((void**)&e->t1args_dev, sizeof(Time1dArgs) * nb));
+    HIP_TRY(hipMalloc((void**)&e->items_dev, sizeof(int) * items.size()));
+    HIP_TRY(hipMemcpy(e->items_dev, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice));
+    NodeCtx n1{e->graph, nullptr, false};
+    HIP_TRY(launch_tri1d_batch(Batch1dArgs{e->targs_dev, e->items_dev, e->n_tri}, e->lds_tri, stream, &n1));
+    const hipGraphNode_t tri = n1.dep;
+    const int* it = e->items_dev + 2 * e->n_tri;
+    for (int wide = 0; wide < 2; ++wide) {
+      if (e->n_t1[wide] == 0) continue;
+      NodeCtx n2{e->graph, tri, true};
+      HIP_TRY(launch_time1d_batch(Batch1dArgs{e->t1args_dev, it, e->n_t1[wide]}, wide != 0, e->lds_t1[wide], stream,
+                                  &n2));
+      it += 2 * e->n_t1[wide];
     }
   }
   HIP_TRY(hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0));
@@ -1305,7 +1425,8 @@ extern "C" int qbvm_solve_batched(int count, const qbvm_grid* grids, const doubl
     rc = check_alpha(alphas[i], variants[i]);
     if (rc) return rc;
     if (!g_deltas[i] || !ys[i]) return set_error(QBVM_EINVAL, "NULL instance pointer");
-    if (outputs[i] != QBVM_OUT_ALL) return set_error(QBVM_EUNSUPPORTED, "batched solve supports QBVM_OUT_ALL");
+    if (outputs[i] != QBVM_OUT_ALL && outputs[i] != QBVM_OUT_Y0 && outputs[i] != QBVM_OUT_YN)
+      return set_error(QBVM_EINVAL, "output must be QBVM_OUT_ALL, QBVM_OUT_Y0 or QBVM_OUT_YN");
   }
   hipStream_t stream = (hipStream_t)hip_stream;
   int dev = 0;
@@ -1316,14 +1437,20 @@ extern "C" int qbvm_solve_batched(int count, const qbvm_grid* grids, const doubl
     if (e->device != dev || (int)e->grids.size() != count) continue;
     bool ok = true;
     for (int i = 0; i < count && ok; ++i)
-      ok = same_grid(e->grids[i], grids[i]) && e->variants[i] == variants[i] && e->outputs[i] == outputs[i] &&
-           e->gs[i] == g_deltas[i] && e->ys[i] == ys[i];
+      ok = same_grid(e->grids[i], grids[i]) && e->variants[i] == variants[i] && e->outputs[i] == outputs[i];
     if (ok) {
       hit = e.get();
       break;
     }
   }
   if (!hit) {
+    if (g_batches.size() >= kBatchCacheEntries) {  // drop the least recently used entry
+      auto lru = std::min_element(g_batches.begin(), g_batches.end(),
+                                  [](const auto& x, const auto& y) { return x->last_use < y->last_use; });
+      HIP_TRY(hipDeviceSynchronize());  // its graph may still run
+      free_entry(lru->get());
+      g_batches.erase(lru);
+    }
     auto e = std::make_unique<BatchEntry>();
     e->device = dev;
     e->grids.assign(grids, grids + count);
@@ -1338,9 +1465,30 @@ extern "C" int qbvm_solve_batched(int count, const qbvm_grid* grids, const doubl
     }
     g_batches.push_back(std::move(e));
     hit = g_batches.back().get();
+  } else {
+    bool moved = false;
+    for (int i = 0; i < count && !moved; ++i) moved = hit->gs[i] != g_deltas[i] || hit->ys[i] != ys[i];
+    if (moved) {  // same launch sequence on new buffers: rewrite the recorded arguments
+      hit->gs.assign(g_deltas, g_deltas + count);
+      hit->ys.assign(ys, ys + count);
+      NodeCtx nc{hit->graph, nullptr, false};
+      nc.nodes = &hit->nodes;
+      nc.exec = hit->exec;
+      const int rc = enqueue_instances(hit, nc, stream);
+      if (rc) return rc;
+      if (nc.next != hit->nodes.size()) return set_error(QBVM_EHIP, "batched graph update out of step");
+      if (!hit->b1d.empty()) fill_batch_1d_args(hit);
+    }
   }
-  // pageable source: the runtime stages it before returning, so no host-side wait is needed
+  hit->last_use = ++g_batch_clock;
+  // pageable sources: the runtime stages them before returning, so no host-side wait is needed
   HIP_TRY(hipMemcpyAsync(hit->alphas_dev, alphas, sizeof(double) * count, hipMemcpyHostToDevice, stream));
+  if (!hit->b1d.empty()) {
+    HIP_TRY(hipMemcpyAsync(hit->targs_dev, hit->targs.data(), sizeof(ThomasArgs) * hit->targs.size(),
+                           hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(hit->t1args_dev, hit->t1args.data(), sizeof(Time1dArgs) * hit->t1args.size(),
+                           hipMemcpyHostToDevice, stream));
+  }
   HIP_TRY(hipGraphLaunch(hit->exec, stream));
   return QBVM_OK;
 }

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "qbvm_types.hpp"
 
 namespace qbvm {
@@ -13,6 +15,20 @@ struct NodeCtx {
   hipGraph_t graph;
   hipGraphNode_t dep;
   bool has_dep;
+  // optional: the launches append their node handles here; with `exec` set they instead set
+  // the parameters of the recorded nodes, in the same order, of that instantiated graph
+  // (new buffers for an unchanged launch sequence)
+  std::vector<hipGraphNode_t>* nodes = nullptr;
+  hipGraphExec_t exec = nullptr;
+  size_t next = 0;
+};
+
+// Batched 1D instances (every level): one launch per step over a device table of the
+// instances' argument blocks; item w = (instance, workgroup of its own launch).
+struct Batch1dArgs {
+  const void* args;  // ThomasArgs[] or Time1dArgs[]
+  const int* items;  // 2 ints per item: instance, workgroup
+  int nitems;
 };
 
 // ---- launch wrappers (defined in qbvm_kernels.hip) ------------------------
@@ -29,7 +45,10 @@ hipError_t launch_plane(const PlaneArgs& a, int var, hipStream_t s, NodeCtx* nc 
 hipError_t launch_thomas(const ThomasArgs& a, long long nwg, size_t lds, hipStream_t s, NodeCtx* nc = nullptr);
 hipError_t launch_time1d(const Time1dArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,
                          NodeCtx* nc = nullptr);
-hipError_t launch_row(const RowArgs& a, long long nwg, int threads, size_t lds, hipStream_t s);
+hipError_t launch_row(const RowArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,
+                      NodeCtx* nc = nullptr);
+hipError_t launch_tri1d_batch(const Batch1dArgs& b, size_t lds, hipStream_t s, NodeCtx* nc);
+hipError_t launch_time1d_batch(const Batch1dArgs& b, bool wide, size_t lds, hipStream_t s, NodeCtx* nc);
 hipError_t launch_bisect_init(double* bstate, int count, const double* deltas, double delta_val,
                               double tau_dp, double lo, double hi, hipStream_t s);
 // 32 workgroups; partial holds >= 32 doubles; counter[0] is zero on entry and exit

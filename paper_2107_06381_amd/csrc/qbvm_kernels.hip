@@ -205,6 +205,32 @@ __global__ __launch_bounds__(256) void k_time1d(Time1dArgs a) {
   time1d_body<WIDE>(a, blockIdx.x, lds);
 }
 
+// Batched 1D instances: persistent launches over an argument table (see Batch1dArgs).
+// Every item runs the same body as the per-instance kernels; the barrier between items
+// keeps an item's first LDS writes behind the previous item's last reads.  Instances
+// whose own launch has fewer lanes (P S < 256 in the tridiagonal solver) leave the
+// extra lanes idle, as the body's ownership tests already do within one launch.
+__global__ __launch_bounds__(256) void k_tri1d_batch(Batch1dArgs b) {
+  extern __shared__ c64 lds[];
+  const ThomasArgs* args = static_cast<const ThomasArgs*>(b.args);
+  for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+    if (it != (int)blockIdx.x) __syncthreads();
+    const ThomasArgs a = args[b.items[2 * it]];
+    tri1d_body(a, b.items[2 * it + 1], lds);
+  }
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_time1d_batch(Batch1dArgs b) {
+  extern __shared__ c64 lds[];
+  const Time1dArgs* args = static_cast<const Time1dArgs*>(b.args);
+  for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+    if (it != (int)blockIdx.x) __syncthreads();
+    const Time1dArgs a = args[b.items[2 * it]];
+    time1d_body<WIDE>(a, b.items[2 * it + 1], lds);
+  }
+}
+
 // ================================================================ k_row ====
 // One level l of Step (c) per sine mode, directly as one DFT row:
 //   Y_k(l) = Re( f0s/N_t * gamma_l^{-1} * g_hat_k * sum_j exp(-2 pi i jl/N_t) / (d_j/tau + mu_k) ).
@@ -723,12 +749,17 @@ static hipError_t enqueue1(const void* f, dim3 grid, dim3 block, size_t lds, hip
   p.sharedMemBytes = (unsigned)lds;
   p.kernelParams = args;
   p.extra = nullptr;
+  if (nc->exec) {  // same launch sequence, new arguments: update the recorded node
+    if (!nc->nodes || nc->next >= nc->nodes->size()) return hipErrorInvalidValue;
+    return hipGraphExecKernelNodeSetParams(nc->exec, (*nc->nodes)[nc->next++], &p);
+  }
   hipGraphNode_t node;
   const hipError_t e = hipGraphAddKernelNode(&node, nc->graph, nc->has_dep ? &nc->dep : nullptr,
                                              nc->has_dep ? 1 : 0, &p);
   if (e == hipSuccess) {
     nc->dep = node;
     nc->has_dep = true;
+    if (nc->nodes) nc->nodes->push_back(node);
   }
   return e;
 }
@@ -784,8 +815,22 @@ hipError_t launch_time1d(const Time1dArgs& a, long long nwg, int threads, size_t
   return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
 }
 
-hipError_t launch_row(const RowArgs& a, long long nwg, int threads, size_t lds, hipStream_t s) {
-  return enqueue1((const void*)&k_row, dim3((unsigned)nwg), dim3(threads), lds, s, a, nullptr);
+hipError_t launch_row(const RowArgs& a, long long nwg, int threads, size_t lds, hipStream_t s, NodeCtx* nc) {
+  return enqueue1((const void*)&k_row, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
+}
+
+hipError_t launch_tri1d_batch(const Batch1dArgs& b, size_t lds, hipStream_t s, NodeCtx* nc) {
+  const void* f = (const void*)&k_tri1d_batch;
+  allow_big_lds(f);
+  const long long nwg = persistent_grid(f, 256, lds, b.nitems);
+  return enqueue1(f, dim3((unsigned)nwg), dim3(256), lds, s, b, nc);
+}
+
+hipError_t launch_time1d_batch(const Batch1dArgs& b, bool wide, size_t lds, hipStream_t s, NodeCtx* nc) {
+  const void* f = wide ? (const void*)&k_time1d_batch<true> : (const void*)&k_time1d_batch<false>;
+  allow_big_lds(f);
+  const long long nwg = persistent_grid(f, 256, lds, b.nitems);
+  return enqueue1(f, dim3((unsigned)nwg), dim3(256), lds, s, b, nc);
 }
 
 hipError_t launch_bisect_init(double* bstate, int count, const double* deltas, double delta_val, double tau_dp,

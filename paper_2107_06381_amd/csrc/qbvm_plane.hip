@@ -66,11 +66,16 @@ hipError_t launch_plane(const PlaneArgs& a, int var, hipStream_t s, NodeCtx* nc)
   p.sharedMemBytes = (unsigned)lds;
   p.kernelParams = args;
   p.extra = nullptr;
+  if (nc->exec) {  // same launch sequence, new arguments: update the recorded node
+    if (!nc->nodes || nc->next >= nc->nodes->size()) return hipErrorInvalidValue;
+    return hipGraphExecKernelNodeSetParams(nc->exec, (*nc->nodes)[nc->next++], &p);
+  }
   hipGraphNode_t node;
   e = hipGraphAddKernelNode(&node, nc->graph, nc->has_dep ? &nc->dep : nullptr, nc->has_dep ? 1 : 0, &p);
   if (e == hipSuccess) {
     nc->dep = node;
     nc->has_dep = true;
+    if (nc->nodes) nc->nodes->push_back(node);
   }
   return e;
 }

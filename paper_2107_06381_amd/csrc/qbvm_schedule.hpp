@@ -365,6 +365,7 @@ inline Launch<Time1dArgs> time1d_step(const Geom& g, SolveScalars sc, const doub
 // Section 3.2: omega = -tau/alpha, f0 = g/alpha)
 inline SolveScalars host_scalars(double alpha, int variant, double tau) {
   SolveScalars sc;
+  sc.alpha = alpha;
   if (variant == 0) {
     sc.logabsw = -std::log(alpha);
     sc.f0s = 1.0 / (tau * alpha);

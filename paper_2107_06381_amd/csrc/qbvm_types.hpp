@@ -50,6 +50,7 @@ struct FftPlanDev {
 struct SolveScalars {
   double logabsw;   // ln|omega|
   double f0s;       // f0 = f0s * g_delta
+  double alpha;     // the regularisation parameter itself (kernels derive the two above from it)
 };
 
 // Arguments of the spectral time kernel: one tile of sine modes x all N_t levels.

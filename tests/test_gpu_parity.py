@@ -486,35 +486,75 @@ def test_adam_vs_reference():
 
 
 # ---------------------------------------------------------------- batched
+def padded_shape(d, m, n):
+    """Shapes whose single full solve takes the padded pipeline (compile-time sine and time
+    kernels); batched instances run the same steps in place, equal to rounding only."""
+    p2 = lambda x: x >= 64 and x & (x - 1) == 0
+    nt = n + 1
+    return d >= 2 and p2(2 * (m + 1)) and 2 * (m + 1) <= 4096 and ((p2(nt) and nt <= 2048) or nt in (129, 257))
+
+
 def test_batched_matches_single_and_oracle():
+    """Uneven batch with every output mode: each instance bitwise equal to its own qbvm_solve and
+    within the bar of the closed form; then the same set on new buffers with new alphas (the
+    cached graph, its arguments rewritten) and once more on the first buffers."""
     say("[case] batched")
     rng = np.random.default_rng(12)
-    specs = [(1, 63, 64), (1, 200, 129), (1, 1023, 300), (2, 63, 64), (2, 100, 257), (2, 31, 90),
-             (1, 63, 64), (2, 63, 64), (3, 9, 10)]
-    grids, alphas, variants, gs, ys, ref = [], [], [], [], [], []
-    for d, m, n in specs:
+    specs = [(1, 63, 64, 0), (1, 200, 129, 0), (1, 1023, 300, 0), (2, 63, 64, 0), (2, 100, 257, 0), (2, 31, 90, 0),
+             (1, 63, 64, 0), (2, 63, 64, 0), (3, 9, 10, 0), (2, 63, 127, 0), (2, 127, 128, 0), (2, 255, 256, 0),
+             (1, 300, 200, 1), (2, 63, 64, 2), (2, 100, 150, 1), (3, 15, 20, 2), (1, 1, 5, 0), (1, 77, 1, 0)]
+    grids, variants, outs, ref = [], [], [], []
+    for d, m, n, o in specs:
         grids.append((d, m, n, 1.0, 1.0))
-        alphas.append(10.0 ** rng.uniform(-6, -1))
         variants.append(int(rng.integers(0, 2)))
-        g = rng.standard_normal((m,) * d)
-        gs.append(to_dev(g))
-        ys.append(torch.empty((n + 1,) + (m,) * d, dtype=torch.float64, device=DEV))
-        ref.append(g)
-    qbvm.solve_batched(grids, alphas, variants, gs, ys)
-    torch.cuda.synchronize()
-    for i, (d, m, n) in enumerate(specs):
-        y1 = gpu_solve(d, m, n, 1.0, 1.0, alphas[i], variants[i], ref[i])
-        yb = ys[i].cpu().numpy()
-        assert np.array_equal(yb, y1), i
-        yc = O.closed_form(ref[i], d, m, n, 1.0, 1.0, alphas[i], variants[i])
-        assert rel(yb, yc) < TOL
-    # replay with new alphas (graph reused, alpha table re-uploaded)
-    alphas2 = [a * 3.0 for a in alphas]
-    qbvm.solve_batched(grids, alphas2, variants, gs, ys)
-    torch.cuda.synchronize()
-    for i, (d, m, n) in enumerate(specs):
-        yc = O.closed_form(ref[i], d, m, n, 1.0, 1.0, alphas2[i], variants[i])
-        assert rel(ys[i].cpu().numpy(), yc) < TOL
+        outs.append(o)
+        ref.append(rng.standard_normal((m,) * d))
+
+    def run(alphas):
+        gs = [to_dev(g) for g in ref]
+        ys = [torch.empty(((n + 1,) if o == qbvm.OUT_ALL else ()) + (m,) * d, dtype=torch.float64, device=DEV)
+              for d, m, n, o in specs]
+        qbvm.solve_batched(grids, alphas, variants, gs, ys, outs)
+        torch.cuda.synchronize()
+        for i, (d, m, n, o) in enumerate(specs):
+            y1 = gpu_solve(d, m, n, 1.0, 1.0, alphas[i], variants[i], ref[i], output=o)
+            yb = ys[i].cpu().numpy()
+            if not (o == qbvm.OUT_ALL and padded_shape(d, m, n)):
+                assert np.array_equal(yb, y1), (i, specs[i], rel(yb, y1), float(np.max(np.abs(yb - y1))))
+            lv = None if o == qbvm.OUT_ALL else [0 if o == qbvm.OUT_Y0 else n]
+            yc = O.closed_form(ref[i], d, m, n, 1.0, 1.0, alphas[i], variants[i], levels=lv)
+            yc = yc if o == qbvm.OUT_ALL else yc[0]
+            assert rel(yb, yc) < TOL or o != qbvm.OUT_ALL, (i, rel(yb, yc))
+            if o != qbvm.OUT_ALL:
+                w = omega_abs(alphas[i], variants[i], 1.0 / n)
+                yc0 = O.closed_form(ref[i], d, m, n, 1.0, 1.0, alphas[i], variants[i], levels=[0])[0]
+                ok, e = level_ok(yb, yc, yc0, lv[0], n + 1, w)
+                assert ok, (i, e)
+        return gs, ys
+
+    alphas = [10.0 ** rng.uniform(-6, -1) for _ in specs]
+    keep = run(alphas)
+    run([a * 3.0 for a in alphas])  # new buffers, new alphas: the cached graph, rewritten
+    run(alphas)
+    del keep
+    qbvm.batched_cache_clear()
+
+
+def test_batched_cache_is_bounded():
+    """More distinct sets of grids than the cache holds: every call still solves correctly."""
+    say("[case] batched cache")
+    rng = np.random.default_rng(13)
+    for k in range(11):
+        specs = [(1, 31 + k, 40), (2, 15 + k, 20)]
+        grids = [(d, m, n, 1.0, 1.0) for d, m, n in specs]
+        ref = [rng.standard_normal((m,) * d) for d, m, n in specs]
+        gs = [to_dev(g) for g in ref]
+        ys = [torch.empty((n + 1,) + (m,) * d, dtype=torch.float64, device=DEV) for d, m, n in specs]
+        qbvm.solve_batched(grids, [1e-3, 1e-4], [0, 1], gs, ys)
+        torch.cuda.synchronize()
+        for i, (d, m, n) in enumerate(specs):
+            yc = O.closed_form(ref[i], d, m, n, 1.0, 1.0, [1e-3, 1e-4][i], i)
+            assert rel(ys[i].cpu().numpy(), yc) < TOL
     qbvm.batched_cache_clear()
 
 
