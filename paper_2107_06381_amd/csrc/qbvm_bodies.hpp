@@ -85,6 +85,65 @@ __device__ __forceinline__ double mode_mu(long long k, int d, int m, const doubl
   return mu;
 }
 
+// Modes of a rank-one time tile and their data.  PAIR: 2S consecutive x_1 of one padded
+// row (each lane's two modes stored as one aligned 16-byte pair, a second mode past the row
+// end landing in the padding); else 2S consecutive flattened modes.  The eigenvalue of a
+// padded-row mode is mu(x_1) plus the eigenvalue of its row, taken with 32-bit index
+// arithmetic (row < m^(d-1) < 2^31).
+template <bool PAIR>
+struct TimeTileR {
+  long long ka, oa;
+  int row, c1;  // PAIR: padded row and first x_1 of the lane's pair
+  bool oka, okb;
+  __device__ __forceinline__ TimeTileR(const TimeArgs& a, long long wg, int S, int s) {
+    if constexpr (PAIR) {
+      const int w = (int)wg;
+      row = w / a.tiles_per_row;
+      c1 = (w - row * a.tiles_per_row) * 2 * S + 2 * s;
+      ka = (long long)row * a.m + c1;
+      oa = (long long)row * a.pitch + c1;
+      oka = c1 < a.m;
+      okb = c1 + 1 < a.m;
+    } else {
+      row = c1 = 0;
+      ka = wg * 2LL * S + 2 * s;
+      oa = ka;
+      oka = ka < a.nmodes;
+      okb = ka + 1 < a.nmodes;
+    }
+  }
+  // sine coefficients and eigenvalues of the lane's two modes (zero past the end)
+  __device__ __forceinline__ void fetch(const TimeArgs& a, double& ga, double& gb, double& mua,
+                                        double& mub) const {
+    ga = oka ? a.ghat[ka] : 0.0;
+    gb = okb ? a.ghat[ka + 1] : 0.0;
+    if constexpr (PAIR) {
+      double mrow = 0.0;
+      int r = row;
+      for (int i = 1; i < a.d; ++i) {
+        const int q = r / a.m;
+        mrow += a.mu1d[r - q * a.m];
+        r = q;
+      }
+      mua = oka ? a.mu1d[c1] + mrow : 0.0;
+      mub = okb ? a.mu1d[c1 + 1] + mrow : 0.0;
+    } else {
+      mua = oka ? mode_mu(ka, a.d, a.m, a.mu1d) : 0.0;
+      mub = okb ? mode_mu(ka + 1, a.d, a.m, a.mu1d) : 0.0;
+    }
+  }
+  // gamma_l^{-1} X_l to level l: real part -> first mode, imaginary part -> second
+  __device__ __forceinline__ void store(const TimeArgs& a, int l, c64 yv) const {
+    double* yl = a.y + (long long)l * a.ystride;
+    if constexpr (PAIR) {
+      if (oka) *reinterpret_cast<c64*>(yl + oa) = yv;
+    } else {
+      if (oka) yl[oa] = yv.re;
+      if (okb) yl[oa + 1] = yv.im;
+    }
+  }
+};
+
 // column c of a columns pass holds data (see DstArgs)
 __device__ __forceinline__ bool dst_col_ok(const DstArgs& a, long long c) {
   return c < a.inner && (a.colmod == 0 || (int)(c % a.colmod) < a.colvalid);

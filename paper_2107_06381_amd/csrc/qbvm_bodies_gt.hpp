@@ -66,6 +66,9 @@ constexpr int gt_chunk_slots(int ch) {
 
 // PAIR: levels in padded rows (pitch > 0), each lane's two modes stored as one
 // aligned 16-byte pair (a second mode past the row end lands in the padding).
+// One tile per workgroup (the row DFT keeps a lane's registers nearly full, and a tile
+// loop with the next tile's coefficients in flight spilled); the tile's coefficients are
+// requested before the tables are staged, so their latency overlaps that prologue.
 template <int A, int B, int S, int KC, bool PAIR>
 __device__ __forceinline__ void time_gt_body(const TimeArgs& a, long long wg, c64* lds) {
   constexpr int N = A * B;
@@ -77,12 +80,17 @@ __device__ __forceinline__ void time_gt_body(const TimeArgs& a, long long wg, c6
   static_assert(c2 > 0, "A and B must be coprime");
   constexpr int T = A * S;
   constexpr GtRoots<B> R{};
+  using Tile = TimeTileR<PAIR>;
   c64* dt = lds;
   c64* gi = dt + N;
   c64* Y = gi + N;  // [slot][a][s] for one chunk of outputs
   static_assert(S % 64 == 0, "one row index per wave");
   const int t = threadIdx.x, s = t % S;
   const int ra = __builtin_amdgcn_readfirstlane(t / S);  // uniform across the wave
+
+  const Tile tile(a, wg, S, s);
+  double ga, gb, mua, mub;
+  tile.fetch(a, ga, gb, mua, mub);
 
   const SolveScalars sc = solve_scalars(a.sc, a.alpha_dev, a.variant, a.tau);
   if (a.tabs) {
@@ -98,25 +106,6 @@ __device__ __forceinline__ void time_gt_body(const TimeArgs& a, long long wg, c6
     }
   }
   __syncthreads();
-
-  long long ka, oa;
-  bool oka, okb;
-  if (PAIR) {
-    const long long row = wg / a.tiles_per_row;
-    const int cc = (int)(wg - row * a.tiles_per_row) * 2 * S + 2 * s;
-    ka = row * a.m + cc;
-    oa = row * a.pitch + cc;
-    oka = cc < a.m;
-    okb = cc + 1 < a.m;
-  } else {
-    ka = wg * 2LL * S + 2 * s;
-    oa = ka;
-    oka = ka < a.nmodes;
-    okb = ka + 1 < a.nmodes;
-  }
-  const double ga = oka ? a.ghat[ka] : 0.0, gb = okb ? a.ghat[ka + 1] : 0.0;
-  const double mua = oka ? mode_mu(ka, a.d, a.m, a.mu1d) : 0.0;
-  const double mub = okb ? mode_mu(ka + 1, a.d, a.m, a.mu1d) : 0.0;
 
   // Steps (a)+(b) on row ra: x[ra, b] = u_{(B ra + A b) mod N}
   c64 v[B];
@@ -176,14 +165,7 @@ __device__ __forceinline__ void time_gt_body(const TimeArgs& a, long long wg, c6
 #pragma unroll
         for (int k1 = 0; k1 < A; ++k1) {
           const int l = (B * c1 * k1 + A * c2 * k2) % N;
-          const c64 yv = cmul(gi[l], w[k1]);
-          double* yl = a.y + (long long)l * a.ystride;
-          if constexpr (PAIR) {
-            if (oka) *reinterpret_cast<c64*>(yl + (unsigned)oa) = yv;  // offset within a level < 2^31
-          } else {
-            if (oka) yl[oa] = yv.re;
-            if (okb) yl[oa + 1] = yv.im;
-          }
+          tile.store(a, l, cmul(gi[l], w[k1]));
         }
       }
     }

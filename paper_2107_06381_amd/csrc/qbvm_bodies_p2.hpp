@@ -429,14 +429,24 @@ struct TimeTile {
 };
 
 // Spectral time kernel, every level written.  RADER: N_t = N + 1 prime; else N_t = N.
-template <int N, int E, int S, bool RADER, bool PAD = true>
-__device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c64* lds) {
+// Persistent: workgroup `first` takes tiles first, first + step, ... < a.ntiles; the
+// per-solve tables are loaded once, and the sine coefficients and eigenvalues of the
+// next tile are loaded while the current one is transformed.
+template <int N, int E, int S, bool RADER, bool PAD, bool PAIR>
+__device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long first, long long step, c64* lds) {
   static_assert(S >= 1, "time kernel needs N <= 2048");
   using L = P2Layout<N, E, S, true, PAD>;
   using M = TimeLds<N, E, L, RADER>;
+  using Tile = TimeTileR<PAIR>;
+  const long long ntiles = a.ntiles;
+  if (first >= ntiles) return;  // whole workgroup, before any barrier
   const int Nt = a.Nt;
   const M sh(lds, Nt);
   const int t = threadIdx.x, s = L::sig(t), u = L::lane(t);
+
+  long long wg = first;
+  double ga, gb, mua, mub;
+  Tile(a, wg, S, s).fetch(a, ga, gb, mua, mub);
 
   const SolveScalars sc = solve_scalars(a.sc, a.alpha_dev, a.variant, a.tau);
   const double croot = exp(sc.logabsw / (double)Nt);
@@ -457,20 +467,28 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long wg, c6
   const auto tw = p2_twiddles<N, M::TWM, E>(a.fft, sh.twl, t, L::T, u);
   __syncthreads();
 
-  const TimeTile tile(a, wg, S, s);
-  const double ga = tile.oka ? a.ghat[tile.ka] : 0.0, gb = tile.okb ? a.ghat[tile.ka + 1] : 0.0;
-  const double mua = tile.oka ? mode_mu(tile.ka, a.d, a.m, a.mu1d) : 0.0;
-  const double mub = tile.okb ? mode_mu(tile.ka + 1, a.d, a.m, a.mu1d) : 0.0;
-  // Steps (a)+(b): u_j = g_a/(d_j/tau + mu_a) + i g_b/(d_j/tau + mu_b)
-  auto input = [&](int j, int) -> c64 {
-    const c64 z = sh.dt[j];
-    const double xa = z.re + mua, xb = z.re + mub;
-    const double ia = ga * recip_nr(xa * xa + z.im * z.im);
-    const double ib = gb * recip_nr(xb * xb + z.im * z.im);
-    return {ia * xa + ib * z.im, ib * xb - ia * z.im};
-  };
-  auto emit = [&](int l, c64 X, int) { tile.store(a, l, cmul(sh.gi[l], X)); };
-  p2_time_dft<N, E, L, RADER>(input, emit, s, u, sh.buf, tw, sh.ks, sh.gfw, sh.gbw);
+  for (;;) {
+    const Tile tile(a, wg, S, s);
+    const long long nx = wg + step;
+    double nga = 0.0, ngb = 0.0, nmua = 0.0, nmub = 0.0;
+    if (nx < ntiles) Tile(a, nx, S, s).fetch(a, nga, ngb, nmua, nmub);
+    // Steps (a)+(b): u_j = g_a/(d_j/tau + mu_a) + i g_b/(d_j/tau + mu_b)
+    auto input = [&](int j, int) -> c64 {
+      const c64 z = sh.dt[j];
+      const double xa = z.re + mua, xb = z.re + mub;
+      const double ia = ga * recip_nr(xa * xa + z.im * z.im);
+      const double ib = gb * recip_nr(xb * xb + z.im * z.im);
+      return {ia * xa + ib * z.im, ib * xb - ia * z.im};
+    };
+    auto emit = [&](int l, c64 X, int) { tile.store(a, l, cmul(sh.gi[l], X)); };
+    p2_time_dft<N, E, L, RADER>(input, emit, s, u, sh.buf, tw, sh.ks, sh.gfw, sh.gbw);
+    if (nx >= ntiles) break;
+    wg = nx;
+    ga = nga;
+    gb = ngb;
+    mua = nmua;
+    mub = nmub;
+  }
 }
 
 // Time kernel of the general right-hand side on the compile-time engine.  Per signal

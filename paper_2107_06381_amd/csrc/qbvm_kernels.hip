@@ -65,10 +65,12 @@ __global__ __launch_bounds__(p2sz::dst_T(N, V)) void k_dst_cols_p2(DstArgs a) {
       a, xcd_contiguous(blockIdx.x, gridDim.x), gridDim.x, lds);
 }
 
-template <int N, int V, bool RADER>
+// Persistent over the tiles (a.ntiles); PAIR: modes in padded rows, 16-byte pair stores.
+template <int N, int V, bool RADER, bool PAIR>
 __global__ __launch_bounds__(p2sz::time_T(V)) void k_time_p2(TimeArgs a) {
   extern __shared__ c64 lds[];
-  time_p2_body<N, p2sz::time_E(V), p2sz::time_S(N, V), RADER, p2sz::time_pad(V)>(a, blockIdx.x, lds);
+  time_p2_body<N, p2sz::time_E(V), p2sz::time_S(N, V), RADER, p2sz::time_pad(V), PAIR>(a, blockIdx.x, gridDim.x,
+                                                                                       lds);
 }
 
 // two waves per SIMD: the lane's B-point row stays in registers
@@ -111,23 +113,29 @@ static const void* dst_fn_n(int V, bool cols, bool vec2) {
   }
 }
 
+// a Rader length N + 1 is prime only at N = 256 in this range
 template <int N, int V>
-static const void* time_fn_nv(bool rader) {
-  if constexpr (p2sz::time_valid(N, V))
-    return rader ? (const void*)&k_time_p2<N, V, true> : (const void*)&k_time_p2<N, V, false>;
-  else
+static const void* time_fn_nv(bool rader, bool pair) {
+  if constexpr (p2sz::time_valid(N, V)) {
+    if constexpr (N == 256) {
+      if (rader) return pair ? (const void*)&k_time_p2<N, V, true, true> : (const void*)&k_time_p2<N, V, true, false>;
+    }
+    if (rader) return nullptr;
+    return pair ? (const void*)&k_time_p2<N, V, false, true> : (const void*)&k_time_p2<N, V, false, false>;
+  } else {
     return nullptr;
+  }
 }
 
 template <int N>
-static const void* time_fn_n(int V, bool rader) {
+static const void* time_fn_n(int V, bool rader, bool pair) {
   switch (V) {
-    case 0: return time_fn_nv<N, 0>(rader);
-    case 1: return time_fn_nv<N, 1>(rader);
-    case 2: return time_fn_nv<N, 2>(rader);
-    case 3: return time_fn_nv<N, 3>(rader);
-    case 4: return time_fn_nv<N, 4>(rader);
-    case 5: return time_fn_nv<N, 5>(rader);
+    case 0: return time_fn_nv<N, 0>(rader, pair);
+    case 1: return time_fn_nv<N, 1>(rader, pair);
+    case 2: return time_fn_nv<N, 2>(rader, pair);
+    case 3: return time_fn_nv<N, 3>(rader, pair);
+    case 4: return time_fn_nv<N, 4>(rader, pair);
+    case 5: return time_fn_nv<N, 5>(rader, pair);
     default: return nullptr;
   }
 }
@@ -178,7 +186,7 @@ static const void* general_fn_n(int V, bool rader) {
 
 static const void* dst_p2_fn(int N, int V, bool cols, bool vec2) { QBVM_P2_SWITCH(N, dst_fn_n, V, cols, vec2) }
 static const void* general_p2_fn(int N, int V, bool rader) { QBVM_P2_SWITCH(N, general_fn_n, V, rader) }
-static const void* time_p2_fn(int N, int V, bool rader) { QBVM_P2_SWITCH(N, time_fn_n, V, rader) }
+static const void* time_p2_fn(int N, int V, bool rader, bool pair) { QBVM_P2_SWITCH(N, time_fn_n, V, rader, pair) }
 
 // ROLE only separates the kernel symbols (0: transform of g_delta, 1: rows of the
 // levels, 2: strided columns of the levels) so per-kernel profiles stay apart.
@@ -781,9 +789,14 @@ hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, 
 
 hipError_t launch_time(const TimeArgs& a, long long nwg, int threads, size_t lds, hipStream_t s, NodeCtx* nc) {
   const void* f = a.fft.wide ? (const void*)&k_time<true> : (const void*)&k_time<false>;
-  if (a.fft.p2) {
-    f = time_p2_fn(a.fft.p2, a.var, a.fft.kind == kRader);
+  if (a.pitch > 0 && nwg >= (1LL << 31)) return hipErrorInvalidValue;  // 32-bit tile index
+  if (a.fft.p2) {  // persistent over a.ntiles tiles
+    f = time_p2_fn(a.fft.p2, a.var, a.fft.kind == kRader, a.pitch > 0);
     if (!f) return hipErrorInvalidValue;
+    allow_big_lds(f);
+    TimeArgs b = a;
+    b.ntiles = nwg;
+    return enqueue1(f, dim3((unsigned)persistent_grid(f, threads, lds, nwg)), dim3(threads), lds, s, b, nc);
   } else if (a.fft.gtA) {
     f = time_gt_fn(a.fft.gtA, a.fft.gtB, a.var, a.pitch > 0);
     if (!f) return hipErrorInvalidValue;

@@ -75,6 +75,7 @@ struct TimeArgs {
   int var;      // power-of-two kernel variant
   long long pitch;   // > 0: y rows of m modes padded to this pitch (tiles never straddle rows)
   int tiles_per_row;
+  long long ntiles;  // tiles of the launch (set at launch; persistent kernels stride over them)
   const c64* tabs;   // optional: [N_t] d_j/tau then [N_t] f0s/N_t gamma_l^{-1} for this solve
   const double* fgen; // general right-hand side in the sine basis, levels ystride apart (general solve)
   FftPlanDev fft;

@@ -186,8 +186,22 @@ static void time_p2_nv(const Launch<TimeArgs>& t) {
     const TimeArgs& A = t.args;
     constexpr int E = p2sz::time_E(V), S = p2sz::time_S(N, V);
     constexpr bool PAD = p2sz::time_pad(V);
-    if (A.fft.kind == kRader) run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_p2_body<N, E, S, true, PAD>(A, wg, l); });
-    else run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_p2_body<N, E, S, false, PAD>(A, wg, l); });
+    // persistent body on a small grid, so every workgroup walks several tiles
+    TimeArgs B = A;
+    B.ntiles = t.nwg;
+    const long long G = t.nwg < 3 ? t.nwg : 3;
+    auto run = [&](auto rader, auto pair) {
+      run_grid(G, A.threads, t.lds, [&](long long wg, c64* l) {
+        time_p2_body<N, E, S, decltype(rader)::value, PAD, decltype(pair)::value>(B, wg, G, l);
+      });
+    };
+    if (A.fft.kind == kRader) {
+      if (A.pitch > 0) run(std::true_type{}, std::true_type{});
+      else run(std::true_type{}, std::false_type{});
+    } else {
+      if (A.pitch > 0) run(std::false_type{}, std::true_type{});
+      else run(std::false_type{}, std::false_type{});
+    }
   } else {
     exit(13);
   }
@@ -221,10 +235,16 @@ static void time_p2_n(const Launch<TimeArgs>& t) {
 static void run_time_fast(const Launch<TimeArgs>& t) {
   const TimeArgs& A = t.args;
   if (A.fft.gtA == 3 && A.fft.gtB == 43) {
-    if (A.var == 0 && A.pitch > 0) run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, p2sz::gt_S(0), p2sz::gt_KC(0), true>(A, wg, l); });
-    else if (A.var == 0) run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, p2sz::gt_S(0), p2sz::gt_KC(0), false>(A, wg, l); });
-    else if (A.pitch > 0) run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, p2sz::gt_S(1), p2sz::gt_KC(1), true>(A, wg, l); });
-    else run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) { time_gt_body<3, 43, p2sz::gt_S(1), p2sz::gt_KC(1), false>(A, wg, l); });
+    auto run = [&](auto v, auto pair) {
+      constexpr int V = decltype(v)::value;
+      run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) {
+        time_gt_body<3, 43, p2sz::gt_S(V), p2sz::gt_KC(V), decltype(pair)::value>(A, wg, l);
+      });
+    };
+    if (A.var == 0 && A.pitch > 0) run(std::integral_constant<int, 0>{}, std::true_type{});
+    else if (A.var == 0) run(std::integral_constant<int, 0>{}, std::false_type{});
+    else if (A.pitch > 0) run(std::integral_constant<int, 1>{}, std::true_type{});
+    else run(std::integral_constant<int, 1>{}, std::false_type{});
     return;
   }
   if (!A.fft.p2) exit(15);
