@@ -24,9 +24,12 @@ What is computed, and from which passage:
   dense form for tiny sizes (``pint_three_step``), with the explicit
   omega-circulant eigen-decomposition C = V D V^{-1}, V = Gamma^{-1} F^*.
 * The residual of the all-at-once rows, matrix free (``residual``).
-* The same rows in 1D with a general tridiagonal spatial matrix A in place of
-  -Lap_h (Section 3.3: the operator enters only Step (b)): ``solve_splu_operator``
-  (SuperLU) and ``closed_form_operator`` (eigenbasis of A).
+* The same rows with another spatial matrix A in place of -Lap_h (Section 3.3: the
+  operator enters only Step (b)): a general tridiagonal A in 1D, and in 2D the
+  variable-coefficient diffusion -div(kappa grad u) in conservative five-point form
+  (``diffusion_matrix_2d``); solved by ``solve_splu_operator`` (SuperLU) and
+  ``closed_form_operator`` (eigenbasis of A), with the matrix-free residual
+  ``residual_operator`` for sizes beyond either.
 * Discrepancy-principle quantities and the bisection used to label alpha, the
   spectral features of g_delta (``discrepancy``, ``bisect_alpha``, ``features``);
   these are additions not taken from the paper, see their docstrings.
@@ -303,6 +306,51 @@ def closed_form_operator(g_delta, A, n: int, T: float, alpha: float, variant: in
     y0 = fh / ((1.0 / tau + lam) - (omega / tau) * r ** n)
     modes = y0[:, None] * r[:, None] ** np.arange(n + 1)[None, :]   # [mode][t] = r^t y^0
     return np.ascontiguousarray(np.real(U @ modes).T)
+
+
+def diffusion_matrix_2d(kx, ky, L: float) -> sp.csr_matrix:
+    """-div(kappa grad u) on the m x m interior grid with zero Dirichlet data, in the
+    conservative five-point form with kappa at the cell faces (kx: (m, m+1) faces
+    between x_1 neighbours, ky: (m+1, m) faces between x_2 neighbours; node (j, i) is
+    x_1 = (i+1) h, x_2 = (j+1) h, flattened x_1 fastest):
+        (A u)_{j,i} = [kx_{j,i} (u_{j,i} - u_{j,i-1}) + kx_{j,i+1} (u_{j,i} - u_{j,i+1})
+                     + ky_{j,i} (u_{j,i} - u_{j-1,i}) + ky_{j+1,i} (u_{j,i} - u_{j+1,i})] / h^2,
+    u = 0 outside the grid.  kappa = 1 gives -Lap_h.  Written out one node at a time."""
+    kx = np.asarray(kx, float)
+    ky = np.asarray(ky, float)
+    m = kx.shape[0]
+    if kx.shape != (m, m + 1) or ky.shape != (m + 1, m):
+        raise ValueError("kx must be (m, m+1) and ky (m+1, m)")
+    ih2 = 1.0 / (L / (m + 1)) ** 2
+    rows, cols, vals = [], [], []
+    for j in range(m):
+        for i in range(m):
+            p = j * m + i
+            rows.append(p)
+            cols.append(p)
+            vals.append((kx[j, i] + kx[j, i + 1] + ky[j, i] + ky[j + 1, i]) * ih2)
+            for (jj, ii, kap) in ((j, i - 1, kx[j, i]), (j, i + 1, kx[j, i + 1]),
+                                  (j - 1, i, ky[j, i]), (j + 1, i, ky[j + 1, i])):
+                if 0 <= jj < m and 0 <= ii < m:
+                    rows.append(p)
+                    cols.append(jj * m + ii)
+                    vals.append(-kap * ih2)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(m * m, m * m))
+
+
+def residual_operator(y, g_delta, A, n: int, T: float, alpha: float, variant: int) -> float:
+    """||f - M y|| / ||f|| for the rows of Sections 3.1/3.2 with the operator A, applied
+    level by level (M never formed): t = 0: (I/tau + A) y^0 - (omega/tau) y^N;
+    t >= 1: (I/tau + A) y^t - y^{t-1}/tau.  y: (n+1, m^d) levels."""
+    tau = T / n
+    omega, scale = omega_and_scale(alpha, variant, tau)
+    Y = np.asarray(y, float).reshape(n + 1, -1)
+    R = Y / tau + (A @ Y.T).T
+    R[0] -= (omega / tau) * Y[n]
+    R[1:] -= Y[:-1] / tau
+    f0 = scale * np.ravel(np.asarray(g_delta, float))
+    R[0] -= f0
+    return float(np.linalg.norm(R) / np.linalg.norm(f0))
 
 
 def pint_three_step(g_delta, d, m, n, L, T, alpha, variant):

@@ -188,6 +188,37 @@ def diffusion_operator_1d(m: int, rng: np.random.Generator, L: float = 1.0, cont
     return np.ascontiguousarray(lower), np.ascontiguousarray(diag), np.ascontiguousarray(upper)
 
 
+def diffusion_coefficients_2d(m: int, rng: np.random.Generator, L: float = 1.0, contrast: float = 4.0):
+    """Input data for a 2D problem with the operator -div(kappa grad u): kappa at the cell
+    faces of the m x m interior grid (Dirichlet boundary), as two arrays
+      kx[j][i], i = 0..m: kappa at (x_1, x_2) = ((i + 1/2) h, (j + 1) h), the face between
+                          x_1 nodes i - 1 and i (shape (m, m + 1));
+      ky[j][i], j = 0..m: kappa at ((i + 1) h, (j + 1/2) h), between x_2 nodes j - 1 and j
+                          (shape (m + 1, m)).
+    kappa is smooth and positive: log kappa is a sum of random low sine modes
+    sin(k_1 pi x_1) sin(k_2 pi x_2), k_1, k_2 <= 3, scaled so that max/min of kappa over
+    the faces is `contrast`, with geometric mean 1 over the faces."""
+    h = L / (m + 1)
+    k = np.arange(1, 4)
+    c = rng.standard_normal((3, 3)) / np.add.outer(k, k)
+
+    def logk(x1, x2):
+        return np.einsum("ab,a...,b...->...", c, np.sin(np.multiply.outer(k, np.pi * x1 / L)),
+                         np.sin(np.multiply.outer(k, np.pi * x2 / L)))
+
+    nodes = (np.arange(m) + 1.0) * h
+    half = (np.arange(m + 1) + 0.5) * h
+    lx = logk(*np.meshgrid(half, nodes, indexing="xy"))   # (m, m+1): rows x_2, columns x_1
+    ly = logk(*np.meshgrid(nodes, half, indexing="xy"))   # (m+1, m)
+    allv = np.concatenate([lx.ravel(), ly.ravel()])
+    span = float(np.ptp(allv))
+    scale = (np.log(contrast) / span) if span > 0 else 0.0
+    mean = float(allv.mean()) * scale
+    kx = np.exp(lx * scale - mean)
+    ky = np.exp(ly * scale - mean)
+    return np.ascontiguousarray(kx), np.ascontiguousarray(ky)
+
+
 def config_1d(seed: int = 0, m: int = 127, n: int = 128, alpha: float = 1e-3,
               eps: float = 0.01) -> Instance:
     """1D, (0,1), z0 = sin(pi x) + 0.5 sin(3 pi x), T=1, 1% relative Gaussian noise."""

@@ -416,6 +416,88 @@ def test_operator_dirichlet_stencil_is_the_sine_form():
         assert np.linalg.norm(ye - ys) <= 1e-10 * np.linalg.norm(ys)
 
 
+# --------------------------------------------------------------------------
+# another spatial operator (2D): -div(kappa grad u) with kappa at the cell faces
+# --------------------------------------------------------------------------
+def test_diffusion_2d_unit_kappa_is_the_laplacian():
+    m, L = 9, 1.3
+    A = O.diffusion_matrix_2d(np.ones((m, m + 1)), np.ones((m + 1, m)), L)
+    assert np.array_equal(A.toarray(), -O.laplacian_matrix(2, m, L).toarray())
+
+
+def test_diffusion_2d_exact_on_quadratics():
+    """The conservative form with kappa at face midpoints is exact for a linear kappa
+    and a quadratic u: -div(kappa grad u) = -(4 kappa + 2 b x_1 + 2 c x_2) for
+    u = x_1^2 + x_2^2, kappa = a + b x_1 + c x_2, at nodes whose neighbours are all
+    interior (the others see the zero Dirichlet data instead of u)."""
+    m, L = 12, 1.0
+    h = L / (m + 1)
+    a, b, c = 1.5, 0.7, -0.4
+    nodes = (np.arange(m) + 1.0) * h
+    half = (np.arange(m + 1) + 0.5) * h
+    X1x, X2x = np.meshgrid(half, nodes, indexing="xy")
+    X1y, X2y = np.meshgrid(nodes, half, indexing="xy")
+    A = O.diffusion_matrix_2d(a + b * X1x + c * X2x, a + b * X1y + c * X2y, L)
+    X1, X2 = np.meshgrid(nodes, nodes, indexing="xy")
+    u = X1 ** 2 + X2 ** 2
+    exact = -(4.0 * (a + b * X1 + c * X2) + 2.0 * b * X1 + 2.0 * c * X2)
+    got = (A @ u.ravel()).reshape(m, m)
+    inner = (slice(1, m - 1), slice(1, m - 1))
+    assert np.allclose(got[inner], exact[inner], rtol=1e-11, atol=1e-9)
+
+
+def test_diffusion_2d_spectrum_between_kappa_bounds():
+    """u^T A u = sum over faces of kappa (difference)^2 / h^2, so the eigenvalues of A lie
+    between kappa_min and kappa_max times those of -Lap_h (Rayleigh quotients); A is
+    symmetric positive definite."""
+    from paper_2107_06381_amd import workloads as W
+    m, L = 15, 1.0
+    kx, ky = W.diffusion_coefficients_2d(m, np.random.default_rng(3), L, contrast=6.0)
+    A = O.diffusion_matrix_2d(kx, ky, L).toarray()
+    assert np.array_equal(A, A.T)
+    lam = np.linalg.eigvalsh(A)
+    mu = np.sort(O.stencil_eigenvalues(2, m, L).ravel())
+    kmin, kmax = min(kx.min(), ky.min()), max(kx.max(), ky.max())
+    assert lam[0] >= kmin * mu[0] * (1 - 1e-12) and lam[-1] <= kmax * mu[-1] * (1 + 1e-12)
+    assert lam[0] > 0
+
+
+@pytest.mark.parametrize("m,n,alpha,variant", [(9, 8, 1e-3, 0), (14, 11, 1e-5, 1), (6, 1, 0.2, 0)])
+def test_diffusion_2d_splu_vs_eigenbasis(m, n, alpha, variant):
+    """Two independent routes to the all-at-once solution with the 2D operator: SuperLU
+    on the assembled rows and the closed form in the eigenbasis of A (LAPACK eigh);
+    the matrix-free residual of the rows vanishes for both."""
+    from paper_2107_06381_amd import workloads as W
+    rng = np.random.default_rng(m * 13 + n)
+    kx, ky = W.diffusion_coefficients_2d(m, rng)
+    A = O.diffusion_matrix_2d(kx, ky, 1.0)
+    g = rng.standard_normal((m, m))
+    ys = O.solve_splu_operator(g, A, n, 0.8, alpha, variant)
+    yc = O.closed_form_operator(g, A, n, 0.8, alpha, variant)
+    assert np.linalg.norm(ys - yc) <= 1e-9 * np.linalg.norm(ys)
+    assert O.residual_operator(ys, g, A, n, 0.8, alpha, variant) < 1e-11
+    assert O.residual_operator(yc, g, A, n, 0.8, alpha, variant) < 1e-9
+
+
+def test_residual_operator_detects_a_wrong_level():
+    m, n, alpha = 7, 5, 1e-3
+    A = O.diffusion_matrix_2d(np.ones((m, m + 1)), np.ones((m + 1, m)), 1.0)
+    g = np.random.default_rng(2).standard_normal((m, m))
+    y = O.solve_splu_operator(g, A, n, 1.0, alpha, O.PQ)
+    assert O.residual_operator(y, g, A, n, 1.0, alpha, O.PQ) < 1e-12
+    y[3] *= 1.0 + 1e-3
+    assert O.residual_operator(y, g, A, n, 1.0, alpha, O.PQ) > 1e-9
+
+
+def test_diffusion_coefficients_input():
+    from paper_2107_06381_amd import workloads as W
+    kx, ky = W.diffusion_coefficients_2d(20, np.random.default_rng(8), contrast=5.0)
+    allv = np.concatenate([kx.ravel(), ky.ravel()])
+    assert kx.shape == (20, 21) and ky.shape == (21, 20)
+    assert np.all(allv > 0) and abs(allv.max() / allv.min() - 5.0) < 1e-9
+    assert abs(np.log(allv).mean()) < 1e-12
+
+
 def test_diffusion_operator_input():
     from paper_2107_06381_amd import workloads as W
     lo, di, up = W.diffusion_operator_1d(50, np.random.default_rng(1))
