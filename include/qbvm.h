@@ -47,6 +47,7 @@ extern "C" {
 #define QBVM_ENOROOT      -4  /* discrepancy principle has no root in the bracket */
 #define QBVM_EUNSUPPORTED -5  /* size outside what the kernels support */
 #define QBVM_ENOMODEL     -6  /* learned alpha requested but no model was set */
+#define QBVM_ENOCONV      -7  /* an iterative Step (b) stopped short of its tolerance */
 
 /* Regularisation variant: PinT-QBVM (Section 3.1) or PinT-MQBVM (Section 3.2). */
 #define QBVM_PQ 0
@@ -189,6 +190,35 @@ int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta,
  * qbvm_bisect_batched return QBVM_EUNSUPPORTED (they work in the sine basis).
  * QBVM_EINVAL for d > 1 or non-finite entries. */
 int qbvm_plan_set_operator_1d(qbvm_plan_t p, const double* lower, const double* diag, const double* upper);
+
+/* Another spatial operator in 2D (Section 3.3: the operator enters only Step (b)):
+ * every later qbvm_solve on this (d = 2) plan uses A = -div(kappa grad u) in place of
+ * -Lap_h, in conservative five-point form with kappa at the cell faces and zero
+ * Dirichlet data:
+ *   (A u)_{j,i} = [kx[j][i] (u_{j,i} - u_{j,i-1}) + kx[j][i+1] (u_{j,i} - u_{j,i+1})
+ *                + ky[j][i] (u_{j,i} - u_{j-1,i}) + ky[j+1][i] (u_{j,i} - u_{j+1,i})] / h^2,
+ * node (j, i) at x_1 = (i+1) h, x_2 = (j+1) h, u = 0 outside the grid.  kx: HOST, m rows
+ * of m+1 faces between x_1 neighbours; ky: HOST, m+1 rows of m faces between x_2
+ * neighbours; both row-major, positive and finite, copied.  kappa = 1 is -Lap_h.
+ * Step (b) then solves the shifted systems (d_j/tau I + A) w_j = f0 for
+ * j < ceil(N_t/2) (the rest are their complex conjugates) by batched conjugate
+ * orthogonal conjugate gradients preconditioned with d_j/tau I + kbar (-Lap_h), kbar =
+ * (min + max)/2 of kappa, which the sine transform diagonalises; a system stops when
+ * its residual falls to tol |f0| (0 < tol < 1), all stop after max_iter iterations
+ * (>= 1).  Such solves are synchronous on the plan's stream (the host checks
+ * convergence once per iteration) and return QBVM_ENOCONV, with y written, if some
+ * system did not converge; qbvm_plan_operator_stats reports the last one.  The
+ * plan allocates 12 (ceil(N_t/2)) m^2 doubles of workspace here.  kx == NULL restores
+ * the Dirichlet stencil.  While the operator is set, qbvm_solve_general,
+ * qbvm_discrepancy, qbvm_choose_alpha and qbvm_bisect_batched return
+ * QBVM_EUNSUPPORTED.  QBVM_EINVAL for d != 2, NULL ky, a non-positive or
+ * non-finite coefficient, tol or max_iter out of range. */
+int qbvm_plan_set_operator_2d(qbvm_plan_t p, const double* kx, const double* ky, double tol, int max_iter);
+
+/* Statistics of the last 2D-operator solve (HOST outputs, each may be NULL): iterations
+ * taken, the largest relative residual |r_j|/|f0| over the systems, and the number of
+ * systems that stopped on a breakdown (a zero bilinear form) before converging. */
+int qbvm_plan_operator_stats(qbvm_plan_t p, int* iterations, double* max_rel_residual, int* breakdowns);
 
 /* Solve the all-at-once system of Sections 3.1/3.2 for a general right-hand side (an
  * addition beyond the paper's data: source terms, or one application of the PinT

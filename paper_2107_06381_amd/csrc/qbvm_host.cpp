@@ -255,6 +255,18 @@ struct qbvm_plan_s {
   c64* tabs = nullptr;  // per-solve time-transform tables, 3 N_t
   double* op = nullptr;  // 1D spatial operator: [m-1] lower, [m] diagonal, [m-1] upper (3m doubles)
   bool has_op = false;
+  // 2D operator -div(kappa grad u): Step (b) by batched preconditioned COCG
+  bool op2 = false;
+  double* kx = nullptr;  // [m][m+1]
+  double* ky = nullptr;  // [m+1][m]
+  double kbar = 1.0, kry_tol = 1e-12;
+  int kry_maxit = 200;
+  int kry_H = 0, kry_nblk = 0;
+  double* kry = nullptr;       // x, r, z, p, p', q: 6 vectors of 2 H m^2 doubles
+  double* kry_part = nullptr;  // [3][H][nblk] complex partial sums
+  double* kry_sys = nullptr;   // [H][8] per-system scalars
+  int kry_iters = 0, kry_breakdowns = 0;
+  double kry_relres = 0.0;
   bool no_sine = false;  // 1D only: the sine transform of length 2(m+1) exceeds the FFT core
   double* partial = nullptr;
   unsigned* counter = nullptr;
@@ -605,6 +617,112 @@ int enqueue_row(const qbvm_plan_s* p, int count, const double* ghat, int level, 
   return QBVM_OK;
 }
 
+// Full or single-level solve with the 2D operator -div(kappa grad u): Step (a) is the
+// broadcast of f0 (rank one), Step (b) the batched preconditioned COCG over the shifts
+// j < H (w_{N_t-1-j} = conj w_j: A, f0 real, d_{N_t-1-j} = conj d_j), Step (c) the
+// inverse time transform per pair of points.  g is f0 up to the factor f0s, which the
+// per-solve gamma table carries.  Synchronous.
+int op2_solve(qbvm_plan_s* p, double alpha, int variant, const double* g, double* y, int lev_first,
+              int lev_count) {
+  const int H = p->kry_H, Nt = p->Nt;
+  const long long M = (long long)p->m * p->m;
+  const size_t V = 2 * (size_t)H * (size_t)M;
+  std::vector<double> gh((size_t)M);
+  HIP_TRY(hipMemcpyAsync(gh.data(), g, sizeof(double) * (size_t)M, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  double gn2 = 0.0;
+  for (double v : gh) gn2 += v * v;
+  if (!std::isfinite(gn2)) return set_error(QBVM_EINVAL, "g_delta is not finite");
+  p->kry_iters = 0;
+  p->kry_relres = 0.0;
+  p->kry_breakdowns = 0;
+  if (gn2 == 0.0) {
+    HIP_TRY(hipMemsetAsync(y, 0, sizeof(double) * (size_t)lev_count * (size_t)M, p->stream));
+    return QBVM_OK;
+  }
+  HIP_TRY(launch_tab_job(TabJob{p->tabs, Nt, variant, p->tau, alpha, nullptr, 0}, p->stream));
+  KrylovArgs a{};
+  a.m = p->m;
+  a.H = H;
+  a.nblk = p->kry_nblk;
+  a.ppt = kKryPointsPerLane;
+  a.M = M;
+  a.ih2 = 1.0 / (p->h * p->h);
+  a.kbar = p->kbar;
+  a.tol2 = p->kry_tol * p->kry_tol * gn2;
+  a.kx = p->kx;
+  a.ky = p->ky;
+  a.mu1d = p->mu1d;
+  a.shift = p->tabs;
+  a.g = g;
+  a.x = p->kry;
+  a.r = p->kry + V;
+  a.z = p->kry + 2 * V;
+  double* pbuf[2] = {p->kry + 3 * V, p->kry + 4 * V};
+  a.q = p->kry + 5 * V;
+  a.part = p->kry_part;
+  a.sys = p->kry_sys;
+  // z = P^{-1} r: sine transform, division by s_j + kbar mu_k (with the partial sums of
+  // r^T z), inverse sine transform (the orthonormal transform is its own inverse)
+  auto precond = [&]() -> int {
+    int rc = run_dst(p, a.r, a.z, 2LL * H, false);
+    if (rc) return rc;
+    HIP_TRY(launch_krylov(a, kKryPrecond, p->stream));
+    return run_dst(p, a.z, a.z, 2LL * H, false);
+  };
+  a.init = 1;
+  a.pin = a.z;  // first direction p = z (beta = 0)
+  a.pout = pbuf[0];
+  HIP_TRY(launch_krylov(a, kKryInit, p->stream));
+  int rc = precond();
+  if (rc) return rc;
+  HIP_TRY(launch_krylov(a, kKryScalars, p->stream));
+  a.init = 0;
+  std::vector<double> sys((size_t)H * 8);
+  int active = H;
+  for (int it = 1; it <= p->kry_maxit && active > 0; ++it) {
+    HIP_TRY(launch_krylov(a, kKryApply, p->stream));
+    HIP_TRY(launch_krylov(a, kKryUpdate, p->stream));
+    rc = precond();
+    if (rc) return rc;
+    HIP_TRY(launch_krylov(a, kKryScalars, p->stream));
+    HIP_TRY(hipMemcpyAsync(sys.data(), a.sys, sizeof(double) * sys.size(), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->kry_iters = it;
+    active = 0;
+    for (int j = 0; j < H; ++j) active += sys[(size_t)j * 8 + 7] == 1.0;
+    a.pin = a.pout;
+    a.pout = a.pout == pbuf[0] ? pbuf[1] : pbuf[0];
+  }
+  double worst = 0.0;
+  int breakdowns = 0;
+  for (int j = 0; j < H; ++j) {
+    worst = std::max(worst, std::sqrt(sys[(size_t)j * 8 + 6] / gn2));
+    breakdowns += sys[(size_t)j * 8 + 7] == -1.0;
+  }
+  p->kry_relres = worst;
+  p->kry_breakdowns = breakdowns;
+  KryTimeArgs t{};
+  t.Nt = Nt;
+  t.H = H;
+  t.S = p->S_time;
+  t.lev_first = lev_first;
+  t.lev_count = lev_count;
+  t.M = M;
+  t.w = a.x;
+  t.gi = p->tabs + Nt;
+  t.y = y;
+  t.fft = p->tfft->dev;
+  const long long nwg = (M + 2LL * t.S - 1) / (2LL * t.S);
+  const size_t lds = sizeof(c64) * ((size_t)t.S * t.fft.nc + 2 * (size_t)t.S);
+  HIP_TRY(launch_kry_time(t, nwg, lds, p->stream));
+  if (active > 0 || worst > p->kry_tol)
+    return set_error(QBVM_ENOCONV, "2D operator: " + std::to_string(active) + " of " + std::to_string(H) +
+                                       " shifted systems above tolerance after " + std::to_string(p->kry_iters) +
+                                       " iterations (" + std::to_string(breakdowns) + " breakdowns)");
+  return QBVM_OK;
+}
+
 // Wait until the final row kernel has posted sequence number seq in the mailbox
 // (polling coherent host memory instead of a copy and a stream synchronisation);
 // after 0.2 s of polling fall back to synchronising the stream.
@@ -639,6 +757,7 @@ const char* qbvm_strerror(int code) {
     case QBVM_ENOROOT: return "discrepancy principle has no root in the bracket";
     case QBVM_EUNSUPPORTED: return "unsupported size";
     case QBVM_ENOMODEL: return "no learned-alpha model attached to the plan";
+    case QBVM_ENOCONV: return "iterative Step (b) did not reach its tolerance";
     default: return "unknown error";
   }
 }
@@ -671,6 +790,9 @@ int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta, 
   if (rc) return rc;
   if (output != QBVM_OUT_ALL && output != QBVM_OUT_Y0 && output != QBVM_OUT_YN)
     return set_error(QBVM_EINVAL, "output must be QBVM_OUT_ALL, QBVM_OUT_Y0 or QBVM_OUT_YN");
+  if (p->op2)
+    return op2_solve(p, alpha, variant, g_delta, y, output == QBVM_OUT_YN ? p->n : 0,
+                     output == QBVM_OUT_ALL ? p->Nt : 1);
   if (output == QBVM_OUT_ALL)
     return enqueue_full(p, alpha, nullptr, variant, g_delta, y, p->s2, nullptr, p->stream, p->W);
   const int level = output == QBVM_OUT_Y0 ? 0 : p->n;
@@ -725,9 +847,59 @@ int qbvm_plan_set_operator_1d(qbvm_plan_t p, const double* lower, const double* 
   return QBVM_OK;
 }
 
+int qbvm_plan_set_operator_2d(qbvm_plan_t p, const double* kx, const double* ky, double tol, int max_iter) {
+  if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
+  if (!kx) {
+    p->op2 = false;
+    return QBVM_OK;
+  }
+  if (p->d != 2) return set_error(QBVM_EINVAL, "a 2D operator can be set on 2D plans only");
+  if (!ky) return set_error(QBVM_EINVAL, "ky is NULL");
+  if (!(tol > 0.0 && tol < 1.0)) return set_error(QBVM_EINVAL, "tol must lie in (0, 1)");
+  if (max_iter < 1) return set_error(QBVM_EINVAL, "max_iter must be >= 1");
+  const int m = p->m;
+  const size_t nf = (size_t)m * (m + 1);
+  double lo = INFINITY, hi = 0.0;
+  for (size_t i = 0; i < nf; ++i) {
+    for (double v : {kx[i], ky[i]}) {
+      if (!(v > 0.0) || !std::isfinite(v)) return set_error(QBVM_EINVAL, "kappa must be positive and finite");
+      lo = std::min(lo, v);
+      hi = std::max(hi, v);
+    }
+  }
+  const int H = (p->Nt + 1) / 2;
+  const long long M = (long long)m * m;
+  const int nblk = (int)((M + (long long)kKryPointsPerLane * kKryThreads - 1) / ((long long)kKryPointsPerLane * kKryThreads));
+  HIP_TRY(hipStreamSynchronize(p->stream));  // solves in flight may still read the old operator
+  if (!p->kx) {
+    HIP_TRY(dalloc(p, &p->kx, nf));
+    HIP_TRY(dalloc(p, &p->ky, nf));
+    HIP_TRY(dalloc(p, &p->kry, 12 * (size_t)H * (size_t)M));
+    HIP_TRY(dalloc(p, &p->kry_part, 3 * 2 * (size_t)H * (size_t)nblk));
+    HIP_TRY(dalloc(p, &p->kry_sys, 8 * (size_t)H));
+  }
+  HIP_TRY(hipMemcpy(p->kx, kx, sizeof(double) * nf, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->ky, ky, sizeof(double) * nf, hipMemcpyHostToDevice));
+  p->kbar = 0.5 * (lo + hi);
+  p->kry_tol = tol;
+  p->kry_maxit = max_iter;
+  p->kry_H = H;
+  p->kry_nblk = nblk;
+  p->op2 = true;
+  return QBVM_OK;
+}
+
+int qbvm_plan_operator_stats(qbvm_plan_t p, int* iterations, double* max_rel_residual, int* breakdowns) {
+  if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
+  if (iterations) *iterations = p->kry_iters;
+  if (max_rel_residual) *max_rel_residual = p->kry_relres;
+  if (breakdowns) *breakdowns = p->kry_breakdowns;
+  return QBVM_OK;
+}
+
 int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f, double* y) {
   if (!p || !f || !y) return set_error(QBVM_EINVAL, "NULL argument");
-  if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "general right-hand side with a spatial operator set");
+  if (p->has_op || p->op2) return set_error(QBVM_EUNSUPPORTED, "general right-hand side with a spatial operator set");
   if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_alpha(alpha, variant);
   if (rc) return rc;
@@ -760,7 +932,7 @@ int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f
 
 int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_delta, double* D_out) {
   if (!p || !g_delta || !D_out) return set_error(QBVM_EINVAL, "NULL argument");
-  if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "discrepancy with a spatial operator set");
+  if (p->has_op || p->op2) return set_error(QBVM_EUNSUPPORTED, "discrepancy with a spatial operator set");
   if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_alpha(alpha, variant);
   if (rc) return rc;
@@ -805,7 +977,7 @@ static int check_opts(const qbvm_alpha_opts* o) {
 int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double delta, const qbvm_alpha_opts* o,
                       double* alpha_out, qbvm_alpha_info* info) {
   if (!p || !g_delta || !alpha_out) return set_error(QBVM_EINVAL, "NULL argument");
-  if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
+  if (p->has_op || p->op2) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
   if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_opts(o);
   if (rc) return rc;
@@ -884,7 +1056,7 @@ static int ensure_batch_ws(qbvm_plan_t p, size_t bytes) {
 int qbvm_bisect_batched(qbvm_plan_t p, int variant, int count, const double* g_deltas, const double* deltas,
                         const qbvm_alpha_opts* o, double* alphas_out, int* hits_out) {
   if (!p || !g_deltas || !deltas || !alphas_out) return set_error(QBVM_EINVAL, "NULL argument");
-  if (p->has_op) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
+  if (p->has_op || p->op2) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
   if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_opts(o);
   if (rc) return rc;

@@ -31,6 +31,11 @@ struct Batch1dArgs {
   int nitems;
 };
 
+// ---- 2D variable-coefficient Step (b) and its Step (c) (qbvm_krylov.hip) ----
+enum KryStep { kKryInit = 0, kKryApply, kKryUpdate, kKryPrecond, kKryScalars };
+hipError_t launch_krylov(const KrylovArgs& a, int step, hipStream_t s);
+hipError_t launch_kry_time(const KryTimeArgs& a, long long nwg, size_t lds, hipStream_t s);
+
 // ---- launch wrappers (defined in qbvm_kernels.hip) ------------------------
 void upload_radix_roots(const c64* roots, int count);  // constant-memory roots per device
 hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,

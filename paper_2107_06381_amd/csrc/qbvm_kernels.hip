@@ -21,6 +21,7 @@
 #include "qbvm_bodies.hpp"
 #include "qbvm_bodies_p2.hpp"
 #include "qbvm_bodies_gt.hpp"
+#include "qbvm_bodies_krylov.hpp"
 #include "qbvm_p2_sizes.hpp"
 
 #include <cmath>
@@ -811,6 +812,22 @@ hipError_t launch_time_general(const TimeArgs& a, long long nwg, size_t lds, hip
     if (!f) return hipErrorInvalidValue;
   }
   return enqueue1(f, dim3((unsigned)nwg), dim3(a.threads), lds, s, a, nullptr);
+}
+
+// Step (c) of the 2D variable-coefficient path (runtime engine, any N_t)
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_kry_time(KryTimeArgs a) {
+  extern __shared__ c64 lds[];
+  kry_time_body<WIDE>(a, blockIdx.x, lds);
+}
+
+hipError_t launch_kry_time(const KryTimeArgs& a, long long nwg, size_t lds, hipStream_t s) {
+  if (a.S < 1 || a.lev_first < 0 || a.lev_count < 1 || a.lev_first + a.lev_count > a.Nt || nwg * 2LL * a.S < a.M)
+    return hipErrorInvalidValue;
+  const void* f = a.fft.wide ? (const void*)&k_kry_time<true> : (const void*)&k_kry_time<false>;
+  allow_big_lds(f);
+  void* args[] = {const_cast<KryTimeArgs*>(&a)};
+  return hipLaunchKernel(f, dim3((unsigned)nwg), dim3(256), args, lds, s);
 }
 
 hipError_t launch_tab_job(const TabJob& t, hipStream_t s) {

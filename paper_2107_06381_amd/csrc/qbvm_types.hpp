@@ -152,6 +152,53 @@ struct ThomasArgs {
   const double* op_up;
 };
 
+// 2D Step (b) with the operator A = -div(kappa grad u) (five-point conservative form,
+// kappa at the cell faces): the shifted systems (s_j I + A) w_j = g, s_j = d_j/tau, for
+// j < H = ceil(N_t/2) (the others are their conjugates), by batched conjugate orthogonal
+// conjugate gradients preconditioned with the constant-coefficient solve
+// (s_j I + kbar (-Lap_h))^{-1} in the sine basis.  Complex vectors are [2][H][M] doubles
+// (real block, then imaginary block), M = m*m points, x_1 fastest.
+constexpr int kKryThreads = 256;       // lanes per workgroup of the Krylov kernels
+constexpr int kKryPointsPerLane = 4;   // points per lane (workgroup: 1024 points of one system)
+struct KrylovArgs {
+  int m;
+  int H;
+  int nblk;       // workgroups per system
+  int ppt;        // points per lane
+  long long M;
+  double ih2;     // 1/h^2
+  double kbar;    // preconditioner coefficient
+  double tol2;    // converged when |r_j|^2 <= tol2
+  int init;       // scalars kernel: first call (no residual partial sums yet)
+  const double* kx;    // [m][m+1] faces between x_1 neighbours
+  const double* ky;    // [m+1][m] faces between x_2 neighbours
+  const double* mu1d;  // eigenvalues of the 1D Dirichlet stencil
+  const c64* shift;    // [N_t] d_j/tau (per-solve table)
+  const double* g;     // right-hand side, M
+  double* x;
+  double* r;
+  double* z;
+  const double* pin;   // search direction of the previous iteration
+  double* pout;        // search direction of this iteration
+  double* q;
+  double* part;        // [3][H][nblk][2] partial sums: sigma, |r|^2, rho
+  double* sys;         // [H][8] per-system scalars (see qbvm_bodies_krylov.hpp)
+};
+
+// Step (c) for the 2D operator path: y_l = Re(gamma_l^{-1}/N_t sum_j theta^{-jl} w_j) per
+// point, w_j for j >= H taken as conj(w_{N_t-1-j}); two points share one transform.
+struct KryTimeArgs {
+  int Nt;
+  int H;
+  int S;
+  int lev_first, lev_count;
+  long long M;
+  const double* w;     // [2][H][M]
+  const c64* gi;       // [N_t] f0s/N_t gamma_l^{-1} (per-solve table)
+  double* y;           // lev_count levels of M
+  FftPlanDev fft;      // length N_t (runtime engine)
+};
+
 // 1D Step (c) from the Thomas output: inverse DFT per spatial point.
 struct Time1dArgs {
   int Nt;

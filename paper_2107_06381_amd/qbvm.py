@@ -22,7 +22,7 @@ MODEL_FLOATS = 6469
 NFEAT = 33
 
 ERR_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOROOT", -5: "EUNSUPPORTED",
-             -6: "ENOMODEL"}
+             -6: "ENOMODEL", -7: "ENOCONV"}
 
 # every symbol include/qbvm.h declares
 EXPORTS = [
@@ -33,6 +33,7 @@ EXPORTS = [
     "qbvm_last_error", "qbvm_version", "qbvm_profile_enable", "qbvm_profile_reset",
     "qbvm_profile_count", "qbvm_profile_get", "qbvm_plan_autotune", "qbvm_plan_get_variants",
     "qbvm_plan_set_variants", "qbvm_plan_set_operator_1d", "qbvm_plan_set_plane", "qbvm_plan_get_plane",
+    "qbvm_plan_set_operator_2d", "qbvm_plan_operator_stats",
 ]
 
 
@@ -106,6 +107,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(i)]),
         "qbvm_plan_set_variants": (i, [vp, i, i, i, i]),
         "qbvm_plan_set_operator_1d": (i, [vp, vp, vp, vp]),
+        "qbvm_plan_set_operator_2d": (i, [vp, vp, vp, d, i]),
+        "qbvm_plan_operator_stats": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(d), ctypes.POINTER(i)]),
         "qbvm_plan_set_plane": (i, [vp, i]),
         "qbvm_plan_get_plane": (i, [vp, ctypes.POINTER(i)]),
         "qbvm_profile_enable": (None, [i]),
@@ -208,6 +211,27 @@ class Plan:
             raise ValueError("operator diagonals must have m-1, m, m-1 entries")
         ptr = [a.ctypes.data if a.size else None for a in arrs]
         _check(self.L_.qbvm_plan_set_operator_1d(self._h, *ptr))
+
+    def set_operator_2d(self, kx=None, ky=None, tol: float = 1e-12, max_iter: int = 200):
+        """-div(kappa grad u) in place of -Lap_h (2D), kappa at the cell faces: kx (m, m+1),
+        ky (m+1, m); kx=None restores -Lap_h (qbvm_plan_set_operator_2d)."""
+        import numpy as np
+        if kx is None:
+            _check(self.L_.qbvm_plan_set_operator_2d(self._h, None, None, 0.0, 0))
+            return
+        kx = np.ascontiguousarray(kx, dtype=np.float64)
+        ky = np.ascontiguousarray(ky, dtype=np.float64)
+        if kx.shape != (self.m, self.m + 1) or ky.shape != (self.m + 1, self.m):
+            raise ValueError("kx must be (m, m+1) and ky (m+1, m)")
+        _check(self.L_.qbvm_plan_set_operator_2d(self._h, kx.ctypes.data, ky.ctypes.data, float(tol),
+                                                 int(max_iter)))
+
+    def operator_stats(self) -> dict:
+        """Iterations, largest relative residual and breakdowns of the last 2D-operator solve."""
+        it, br = ctypes.c_int(), ctypes.c_int()
+        rr = ctypes.c_double()
+        _check(self.L_.qbvm_plan_operator_stats(self._h, ctypes.byref(it), ctypes.byref(rr), ctypes.byref(br)))
+        return {"iterations": it.value, "max_rel_residual": rr.value, "breakdowns": br.value}
 
     def set_variants(self, rows: int = -1, cols: int = -1, time: int = -1, general: int = -1):
         """Select kernel variants by hand (-1 keeps the current one)."""
