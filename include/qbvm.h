@@ -212,7 +212,8 @@ int qbvm_plan_set_operator_1d(qbvm_plan_t p, const double* lower, const double* 
  * the Dirichlet stencil.  While the operator is set, qbvm_solve_general,
  * qbvm_discrepancy, qbvm_choose_alpha and qbvm_bisect_batched return
  * QBVM_EUNSUPPORTED.  QBVM_EINVAL for d != 2, NULL ky, a non-positive or
- * non-finite coefficient, tol or max_iter out of range. */
+ * non-finite coefficient, tol or max_iter out of range; QBVM_EUNSUPPORTED for m > 4480
+ * (the operator kernel keeps a workgroup's 1024 points and a grid row either side in LDS). */
 int qbvm_plan_set_operator_2d(qbvm_plan_t p, const double* kx, const double* ky, double tol, int max_iter);
 
 /* Statistics of the last 2D-operator solve (HOST outputs, each may be NULL): iterations

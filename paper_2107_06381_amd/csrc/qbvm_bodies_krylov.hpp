@@ -74,29 +74,32 @@ __device__ __forceinline__ void kry_init_body(const KrylovArgs& a, long long wg)
   if (b == 0 && threadIdx.x < kSysStride) a.sys[(size_t)j * kSysStride + threadIdx.x] = threadIdx.x == kSysState ? 1.0 : 0.0;
 }
 
-// p = z + beta p_in at point (i, k) of system j (zero outside the grid)
-__device__ __forceinline__ c64 kry_dir(const KrylovArgs& a, int j, int i, int k, c64 beta) {
-  if (i < 0 || i >= a.m || k < 0 || k >= a.m) return {0.0, 0.0};
-  const long long pt = (long long)k * a.m + i;
-  return cadd(kry_load(a.z, a, j, pt), cmul(beta, kry_load(a.pin, a, j, pt)));
-}
-
-// New direction p (stored), q = (s_j I + A) p, partial sums of p^T q (slot block 0).
-__device__ __forceinline__ void kry_apply_body(const KrylovArgs& a, long long wg, c64* red) {
+// New direction p = z + beta p_in (stored), q = (s_j I + A) p, partial sums of p^T q
+// (slot block 0).  The workgroup's points [base, base + TP) and one grid row on either
+// side are formed once into LDS (pl, TP + 2m entries), the stencil reads them there.
+__device__ __forceinline__ void kry_apply_body(const KrylovArgs& a, long long wg, c64* red, c64* pl) {
   const int j = (int)(wg / a.nblk), b = (int)(wg - (long long)j * a.nblk);
   const double* sy = a.sys + (size_t)j * kSysStride;
   if (sy[kSysState] != 1.0) return;  // the whole workgroup: j is uniform
   const c64 beta = {sy[kSysBeta], sy[kSysBeta + 1]};
   const c64 s = a.shift[j];
-  const long long base = (long long)b * a.ppt * kKryThreads;
+  const long long TP = (long long)a.ppt * kKryThreads;
+  const long long base = (long long)b * TP;
+  const long long lo = base - a.m;  // pl[e] holds point lo + e
+  const long long hi = base + TP + a.m < a.M ? base + TP + a.m : a.M;
+  for (long long pt = (lo > 0 ? lo : 0) + threadIdx.x; pt < hi; pt += kKryThreads)
+    pl[pt - lo] = cadd(kry_load(a.z, a, j, pt), cmul(beta, kry_load(a.pin, a, j, pt)));
+  __syncthreads();
   c64 acc = {0.0, 0.0};
+  const c64 zero = {0.0, 0.0};
   for (int kk = 0; kk < a.ppt; ++kk) {
     const long long pt = base + (long long)kk * kKryThreads + threadIdx.x;
     if (pt < a.M) {
       const int k = (int)(pt / a.m), i = (int)(pt - (long long)k * a.m);
-      const c64 pc = kry_dir(a, j, i, k, beta);
-      const c64 pw = kry_dir(a, j, i - 1, k, beta), pe = kry_dir(a, j, i + 1, k, beta);
-      const c64 ps = kry_dir(a, j, i, k - 1, beta), pn = kry_dir(a, j, i, k + 1, beta);
+      const long long e = pt - lo;
+      const c64 pc = pl[e];
+      const c64 pw = i > 0 ? pl[e - 1] : zero, pe = i + 1 < a.m ? pl[e + 1] : zero;
+      const c64 ps = k > 0 ? pl[e - a.m] : zero, pn = k + 1 < a.m ? pl[e + a.m] : zero;
       const double kw = a.kx[(size_t)k * (a.m + 1) + i], ke = a.kx[(size_t)k * (a.m + 1) + i + 1];
       const double ks = a.ky[(size_t)k * a.m + i], kn = a.ky[(size_t)(k + 1) * a.m + i];
       c64 ap = cscale(csub(pc, pw), kw);

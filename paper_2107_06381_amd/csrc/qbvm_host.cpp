@@ -664,10 +664,17 @@ int op2_solve(qbvm_plan_s* p, double alpha, int variant, const double* g, double
   a.sys = p->kry_sys;
   // z = P^{-1} r: sine transform, division by s_j + kbar mu_k (with the partial sums of
   // r^T z), inverse sine transform (the orthonormal transform is its own inverse)
+  const double hm = (double)H * (double)M;  // complex unknowns of Step (b)
+  auto step = [&](int which, const char* name, double bytes_per) -> int {
+    ProfScope ps(name, p->stream, bytes_per * hm, 0.0, nullptr);
+    HIP_TRY(launch_krylov(a, which, p->stream));
+    return QBVM_OK;
+  };
   auto precond = [&]() -> int {
     int rc = run_dst(p, a.r, a.z, 2LL * H, false);
     if (rc) return rc;
-    HIP_TRY(launch_krylov(a, kKryPrecond, p->stream));
+    rc = step(kKryPrecond, "kry_precond", 32.0);  // z read and written
+    if (rc) return rc;
     return run_dst(p, a.z, a.z, 2LL * H, false);
   };
   a.init = 1;
@@ -681,8 +688,10 @@ int op2_solve(qbvm_plan_s* p, double alpha, int variant, const double* g, double
   std::vector<double> sys((size_t)H * 8);
   int active = H;
   for (int it = 1; it <= p->kry_maxit && active > 0; ++it) {
-    HIP_TRY(launch_krylov(a, kKryApply, p->stream));
-    HIP_TRY(launch_krylov(a, kKryUpdate, p->stream));
+    rc = step(kKryApply, "kry_apply", 64.0);  // z, p in; p, q out
+    if (rc) return rc;
+    rc = step(kKryUpdate, "kry_update", 96.0);  // x, r, p, q in; x, r out
+    if (rc) return rc;
     rc = precond();
     if (rc) return rc;
     HIP_TRY(launch_krylov(a, kKryScalars, p->stream));
@@ -715,7 +724,11 @@ int op2_solve(qbvm_plan_s* p, double alpha, int variant, const double* g, double
   t.fft = p->tfft->dev;
   const long long nwg = (M + 2LL * t.S - 1) / (2LL * t.S);
   const size_t lds = sizeof(c64) * ((size_t)t.S * t.fft.nc + 2 * (size_t)t.S);
-  HIP_TRY(launch_kry_time(t, nwg, lds, p->stream));
+  {
+    ProfScope ps("kry_time", p->stream, 16.0 * hm + 8.0 * (double)lev_count * (double)M,
+                 0.5 * (double)M * fft_flops(p->tfft->dev), nullptr);
+    HIP_TRY(launch_kry_time(t, nwg, lds, p->stream));
+  }
   if (active > 0 || worst > p->kry_tol)
     return set_error(QBVM_ENOCONV, "2D operator: " + std::to_string(active) + " of " + std::to_string(H) +
                                        " shifted systems above tolerance after " + std::to_string(p->kry_iters) +
@@ -854,6 +867,8 @@ int qbvm_plan_set_operator_2d(qbvm_plan_t p, const double* kx, const double* ky,
     return QBVM_OK;
   }
   if (p->d != 2) return set_error(QBVM_EINVAL, "a 2D operator can be set on 2D plans only");
+  if (p->m > kKryMaxM) return set_error(QBVM_EUNSUPPORTED, "2D operator: m above the stencil kernel's LDS tile");
+  if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   if (!ky) return set_error(QBVM_EINVAL, "ky is NULL");
   if (!(tol > 0.0 && tol < 1.0)) return set_error(QBVM_EINVAL, "tol must lie in (0, 1)");
   if (max_iter < 1) return set_error(QBVM_EINVAL, "max_iter must be >= 1");

@@ -10,7 +10,8 @@ __global__ __launch_bounds__(kKryThreads) void k_kry_init(KrylovArgs a) { kry_in
 
 __global__ __launch_bounds__(kKryThreads) void k_kry_apply(KrylovArgs a) {
   __shared__ c64 red[kKryThreads];
-  kry_apply_body(a, blockIdx.x, red);
+  extern __shared__ c64 pl[];
+  kry_apply_body(a, blockIdx.x, red, pl);
 }
 
 __global__ __launch_bounds__(kKryThreads) void k_kry_update(KrylovArgs a) {
@@ -45,8 +46,17 @@ hipError_t launch_krylov(const KrylovArgs& a, int step, hipStream_t s) {
       break;
     default: return hipErrorInvalidValue;
   }
+  size_t lds = 0;
+  if (step == kKryApply) {
+    lds = kry_apply_lds(a.m);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) {
+      const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+  }
   void* args[] = {const_cast<KrylovArgs*>(&a)};
-  return hipLaunchKernel(f, dim3(grid), dim3(kKryThreads), args, 0, s);
+  return hipLaunchKernel(f, dim3(grid), dim3(kKryThreads), args, lds, s);
 }
 
 }  // namespace qbvm

@@ -160,6 +160,12 @@ struct ThomasArgs {
 // (real block, then imaginary block), M = m*m points, x_1 fastest.
 constexpr int kKryThreads = 256;       // lanes per workgroup of the Krylov kernels
 constexpr int kKryPointsPerLane = 4;   // points per lane (workgroup: 1024 points of one system)
+// dynamic LDS of the operator kernel: the workgroup's points and one grid row either side,
+// plus the static reduction buffer
+constexpr size_t kry_apply_lds(int m) {
+  return 16 * ((size_t)kKryPointsPerLane * kKryThreads + 2 * (size_t)m);
+}
+constexpr int kKryMaxM = (int)((160 * 1024 - 16 * kKryThreads) / 16 - kKryPointsPerLane * kKryThreads) / 2;
 struct KrylovArgs {
   int m;
   int H;
