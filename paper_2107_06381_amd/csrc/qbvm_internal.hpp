@@ -32,7 +32,6 @@ struct Batch1dArgs {
 };
 
 // ---- 2D variable-coefficient Step (b) and its Step (c) (qbvm_krylov.hip) ----
-enum KryStep { kKryInit = 0, kKryApply, kKryUpdate, kKryPrecond, kKryScalars };
 hipError_t launch_krylov(const KrylovArgs& a, int step, hipStream_t s);
 hipError_t launch_kry_time(const KryTimeArgs& a, long long nwg, size_t lds, hipStream_t s);
 

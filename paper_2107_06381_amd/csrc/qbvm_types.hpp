@@ -166,6 +166,7 @@ constexpr size_t kry_apply_lds(int m) {
   return 16 * ((size_t)kKryPointsPerLane * kKryThreads + 2 * (size_t)m);
 }
 constexpr int kKryMaxM = (int)((160 * 1024 - 16 * kKryThreads) / 16 - kKryPointsPerLane * kKryThreads) / 2;
+enum KryStep { kKryInit = 0, kKryApply, kKryUpdate, kKryPrecond, kKryScalars };
 struct KrylovArgs {
   int m;
   int H;

@@ -6,6 +6,9 @@
 //       (plane: 0 = separate x_2 / x_1 passes, v + 1 = plane-pass variant v)
 //   kernels_cpu dst   d m batch in.bin out.bin [var_rows var_cols input]
 //   kernels_cpu general d m n L T alpha variant f.bin out.bin [padded var_gen]   (general right-hand side)
+//   kernels_cpu op2d m n L T alpha variant g.bin out.bin kx.bin ky.bin tol max_iter stats.bin
+//       (2D operator -div(kappa grad u): batched preconditioned COCG and Step (c), every level;
+//       stats.bin: iterations, largest relative residual, breakdowns as three doubles)
 //   kernels_cpu solveop m n L T alpha variant in.bin out.bin op.bin level   (1D, tridiagonal operator;
 //       op.bin: lower[m-1] diag[m] upper[m-1]; level -1: every level, else that level only)
 #include "hip_cpu_shim.hpp"
@@ -20,6 +23,7 @@
 
 #include "../../paper_2107_06381_amd/csrc/qbvm_bodies_p2.hpp"
 #include "../../paper_2107_06381_amd/csrc/qbvm_bodies_gt.hpp"
+#include "../../paper_2107_06381_amd/csrc/qbvm_bodies_krylov.hpp"
 #include "../../paper_2107_06381_amd/csrc/qbvm_fft_plan.hpp"
 #include "../../paper_2107_06381_amd/csrc/qbvm_schedule.hpp"
 
@@ -464,6 +468,128 @@ int main(int argc, char** argv) {
     if (t.args.fft.wide) run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time1d_body<true>(t.args, wg, l); });
     else run_grid(t.nwg, 256, t.lds, [&](long long wg, c64* l) { time1d_body<false>(t.args, wg, l); });
     write_file(argv[9], y.data(), ny * sizeof(double));
+    return 0;
+  }
+  if (cmd == "op2d" && argc == 15) {
+    // the host loop of qbvm_host.cpp::op2_solve with the emulated kernels
+    const int m = atoi(argv[2]), n = atoi(argv[3]);
+    const double L = atof(argv[4]), T = atof(argv[5]), alpha = atof(argv[6]);
+    const int variant = atoi(argv[7]);
+    const double tol = atof(argv[12]);
+    const int maxit = atoi(argv[13]);
+    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1));
+    const double h = L / (m + 1);
+    std::vector<double> mu(m);
+    for (int k = 1; k <= m; ++k) {
+      const long double sn = sinl((long double)k * plan::kPiL / (2.0L * (m + 1)));
+      mu[k - 1] = (double)(4.0L / ((long double)h * h) * sn * sn);
+    }
+    sched::Geom g = geom(2, m, n, L, T, tt, st, mu);
+    const long long M = (long long)m * m;
+    const size_t nf = (size_t)m * (m + 1);
+    auto rg = read_file(argv[8]), rkx = read_file(argv[10]), rky = read_file(argv[11]);
+    if (rg.size() != (size_t)M * 8 || rkx.size() != nf * 8 || rky.size() != nf * 8) return 7;
+    std::vector<double> gv(M), kx(nf), ky(nf);
+    std::memcpy(gv.data(), rg.data(), rg.size());
+    std::memcpy(kx.data(), rkx.data(), rkx.size());
+    std::memcpy(ky.data(), rky.data(), rky.size());
+    double lo = INFINITY, hi = 0.0, gn2 = 0.0;
+    for (size_t i = 0; i < nf; ++i) {
+      lo = std::min(lo, std::min(kx[i], ky[i]));
+      hi = std::max(hi, std::max(kx[i], ky[i]));
+    }
+    for (double v : gv) gn2 += v * v;
+    const int H = (g.Nt + 1) / 2;
+    const int nblk = (int)((M + (long long)kKryPointsPerLane * kKryThreads - 1) / ((long long)kKryPointsPerLane * kKryThreads));
+    const size_t V = 2 * (size_t)H * (size_t)M;
+    std::vector<double> work(6 * V, std::nan("")), part(3 * 2 * (size_t)H * nblk, std::nan("")),
+        sys(8 * (size_t)H, std::nan(""));
+    std::vector<c64> tabs(2 * (size_t)g.Nt, c64{std::nan(""), std::nan("")});
+    const TabJob job{tabs.data(), g.Nt, variant, g.tau, alpha, nullptr, 0};
+    tab_job_run(job, 0, 1);
+    KrylovArgs a{};
+    a.m = m;
+    a.H = H;
+    a.nblk = nblk;
+    a.ppt = kKryPointsPerLane;
+    a.M = M;
+    a.ih2 = 1.0 / (h * h);
+    a.kbar = 0.5 * (lo + hi);
+    a.tol2 = tol * tol * gn2;
+    a.kx = kx.data();
+    a.ky = ky.data();
+    a.mu1d = mu.data();
+    a.shift = tabs.data();
+    a.g = gv.data();
+    a.x = work.data();
+    a.r = a.x + V;
+    a.z = a.x + 2 * V;
+    double* pbuf[2] = {a.x + 3 * V, a.x + 4 * V};
+    a.q = a.x + 5 * V;
+    a.part = part.data();
+    a.sys = sys.data();
+    const long long G = (long long)H * nblk;
+    const size_t red = sizeof(c64) * kKryThreads;
+    auto launch = [&](int step) {
+      switch (step) {
+        case kKryInit: run_grid(G, kKryThreads, 0, [&](long long wg, c64*) { kry_init_body(a, wg); }); break;
+        case kKryApply:
+          run_grid(G, kKryThreads, red + kry_apply_lds(m),
+                   [&](long long wg, c64* l) { kry_apply_body(a, wg, l, l + kKryThreads); });
+          break;
+        case kKryUpdate: run_grid(G, kKryThreads, red, [&](long long wg, c64* l) { kry_update_body(a, wg, l); }); break;
+        case kKryPrecond: run_grid(G, kKryThreads, red, [&](long long wg, c64* l) { kry_precond_body(a, wg, l); }); break;
+        default: run_grid(H, kKryThreads, red, [&](long long wg, c64* l) { kry_scalars_body(a, wg, l); }); break;
+      }
+    };
+    auto precond = [&]() {
+      run_dst(g, a.r, a.z, 2LL * H, false);
+      launch(kKryPrecond);
+      run_dst(g, a.z, a.z, 2LL * H, false);
+    };
+    a.init = 1;
+    a.pin = a.z;
+    a.pout = pbuf[0];
+    launch(kKryInit);
+    precond();
+    launch(kKryScalars);
+    a.init = 0;
+    int it = 0, active = H;
+    while (it < maxit && active > 0) {
+      ++it;
+      launch(kKryApply);
+      launch(kKryUpdate);
+      precond();
+      launch(kKryScalars);
+      active = 0;
+      for (int j = 0; j < H; ++j) active += sys[(size_t)j * 8 + 7] == 1.0;
+      a.pin = a.pout;
+      a.pout = a.pout == pbuf[0] ? pbuf[1] : pbuf[0];
+    }
+    double worst = 0.0, brk = 0.0;
+    for (int j = 0; j < H; ++j) {
+      worst = std::max(worst, std::sqrt(sys[(size_t)j * 8 + 6] / gn2));
+      brk += sys[(size_t)j * 8 + 7] == -1.0;
+    }
+    KryTimeArgs t{};
+    t.Nt = g.Nt;
+    t.H = H;
+    t.S = plan::signals_for(g.tfft.nc);
+    t.lev_first = 0;
+    t.lev_count = g.Nt;
+    t.M = M;
+    t.w = a.x;
+    t.gi = tabs.data() + g.Nt;
+    std::vector<double> y((size_t)g.Nt * M, std::nan(""));
+    t.y = y.data();
+    t.fft = g.tfft;
+    const long long nwg = (M + 2LL * t.S - 1) / (2LL * t.S);
+    const size_t lds = sizeof(c64) * ((size_t)t.S * t.fft.nc + 2 * (size_t)t.S);
+    if (t.fft.wide) run_grid(nwg, 256, lds, [&](long long wg, c64* l) { kry_time_body<true>(t, wg, l); });
+    else run_grid(nwg, 256, lds, [&](long long wg, c64* l) { kry_time_body<false>(t, wg, l); });
+    write_file(argv[9], y.data(), y.size() * sizeof(double));
+    const double stats[3] = {(double)it, worst, brk};
+    write_file(argv[14], stats, sizeof(stats));
     return 0;
   }
   if (cmd == "solve" && (argc == 11 || argc == 14 || argc == 15 || argc == 16)) {

@@ -196,6 +196,32 @@ def test_operator_1d_vs_oracle(exe, tmp_path, m, n, alpha, variant, adv, level):
     assert np.linalg.norm(y - yc) <= 1e-10 * np.linalg.norm(yc)
 
 
+@pytest.mark.parametrize("m,n,alpha,variant", [(7, 8, 1e-3, 0), (12, 15, 1e-4, 1), (31, 8, 1e-2, 0)])
+def test_operator_2d_vs_oracle(exe, tmp_path, m, n, alpha, variant):
+    """2D operator -div(kappa grad u): the Krylov kernel bodies (operator, update, sine-basis
+    preconditioner, scalars) and the Step (c) kernel, driven by the same host loop as the
+    library, against SuperLU on the assembled rows (sine lengths 16, 26 generic and 64
+    compile-time; N_t = 9, 16)."""
+    from paper_2107_06381_amd import workloads as W
+    rng = np.random.default_rng(m * 3 + n)
+    kx, ky = W.diffusion_coefficients_2d(m, rng)
+    g = rng.standard_normal((m, m))
+    L, T, tol = 1.0, 0.9, 1e-12
+    fg, fo, fkx, fky, fs = (tmp_path / x for x in ("g.bin", "o.bin", "kx.bin", "ky.bin", "s.bin"))
+    g.tofile(fg)
+    kx.tofile(fkx)
+    ky.tofile(fky)
+    _run(exe, ["op2d", m, n, repr(L), repr(T), repr(alpha), variant, fg, fo, fkx, fky, repr(tol), 200, fs],
+         tmp_path)
+    y = np.fromfile(fo).reshape((n + 1, m, m))
+    it, worst, brk = np.fromfile(fs)
+    A = O.diffusion_matrix_2d(kx, ky, L)
+    yc = O.solve_splu_operator(g, A, n, T, alpha, variant).reshape((n + 1, m, m))
+    assert 1 <= it <= 200 and worst <= tol and brk == 0
+    assert np.linalg.norm(y - yc) <= 1e-9 * np.linalg.norm(yc)
+    assert np.linalg.norm(y[0] - yc[0]) <= 1e-9 * np.linalg.norm(yc[0])
+
+
 def test_library_exports_every_declared_symbol():
     from paper_2107_06381_amd import qbvm
     L = qbvm.load()
