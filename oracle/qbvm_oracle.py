@@ -27,7 +27,7 @@ What is computed, and from which passage:
 * The same rows with another spatial matrix A in place of -Lap_h (Section 3.3: the
   operator enters only Step (b)): a general tridiagonal A in 1D, and in 2D the
   variable-coefficient diffusion -div(kappa grad u) in conservative five-point form
-  (``diffusion_matrix_2d``); solved by ``solve_splu_operator`` (SuperLU) and
+  (``diffusion_matrix_2d``) and its seven-point 3D counterpart (``diffusion_matrix_3d``); solved by ``solve_splu_operator`` (SuperLU) and
   ``closed_form_operator`` (eigenbasis of A), with the matrix-free residual
   ``residual_operator`` for sizes beyond either.
 * Discrepancy-principle quantities and the bisection used to label alpha, the
@@ -336,6 +336,38 @@ def diffusion_matrix_2d(kx, ky, L: float) -> sp.csr_matrix:
                     cols.append(jj * m + ii)
                     vals.append(-kap * ih2)
     return sp.csr_matrix((vals, (rows, cols)), shape=(m * m, m * m))
+
+
+def diffusion_matrix_3d(kx, ky, kz, L: float) -> sp.csr_matrix:
+    """The same conservative form in 3D: node (k, j, i) at x_1 = (i+1) h, x_2 = (j+1) h,
+    x_3 = (k+1) h, flattened x_1 fastest; kx (m, m, m+1) faces between x_1 neighbours,
+    ky (m, m+1, m) between x_2 neighbours, kz (m+1, m, m) between x_3 neighbours:
+        (A u)_{k,j,i} = sum over the six faces of kappa_face (u_{k,j,i} - u_neighbour) / h^2,
+    u = 0 outside the grid.  Written out one node at a time."""
+    kx = np.asarray(kx, float)
+    ky = np.asarray(ky, float)
+    kz = np.asarray(kz, float)
+    m = kx.shape[0]
+    if kx.shape != (m, m, m + 1) or ky.shape != (m, m + 1, m) or kz.shape != (m + 1, m, m):
+        raise ValueError("kx must be (m, m, m+1), ky (m, m+1, m) and kz (m+1, m, m)")
+    ih2 = 1.0 / (L / (m + 1)) ** 2
+    rows, cols, vals = [], [], []
+    for k in range(m):
+        for j in range(m):
+            for i in range(m):
+                p = (k * m + j) * m + i
+                faces = ((k, j, i - 1, kx[k, j, i]), (k, j, i + 1, kx[k, j, i + 1]),
+                         (k, j - 1, i, ky[k, j, i]), (k, j + 1, i, ky[k, j + 1, i]),
+                         (k - 1, j, i, kz[k, j, i]), (k + 1, j, i, kz[k + 1, j, i]))
+                rows.append(p)
+                cols.append(p)
+                vals.append(sum(f[3] for f in faces) * ih2)
+                for (kk, jj, ii, kap) in faces:
+                    if 0 <= kk < m and 0 <= jj < m and 0 <= ii < m:
+                        rows.append(p)
+                        cols.append((kk * m + jj) * m + ii)
+                        vals.append(-kap * ih2)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(m ** 3, m ** 3))
 
 
 def residual_operator(y, g_delta, A, n: int, T: float, alpha: float, variant: int) -> float:

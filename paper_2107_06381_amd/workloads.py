@@ -219,6 +219,39 @@ def diffusion_coefficients_2d(m: int, rng: np.random.Generator, L: float = 1.0, 
     return np.ascontiguousarray(kx), np.ascontiguousarray(ky)
 
 
+def diffusion_coefficients_3d(m: int, rng: np.random.Generator, L: float = 1.0, contrast: float = 4.0):
+    """3D counterpart of diffusion_coefficients_2d: kappa at the faces of the m^3 interior
+    grid, arrays indexed [x_3][x_2][x_1] with the face axis extended by one:
+    kx (m, m, m+1) at ((i + 1/2) h, (j + 1) h, (k + 1) h), ky (m, m+1, m), kz (m+1, m, m).
+    log kappa is a sum of random sin(k_1 pi x_1) sin(k_2 pi x_2) sin(k_3 pi x_3),
+    k_1, k_2, k_3 <= 2, scaled to max/min `contrast` over the faces, geometric mean 1."""
+    h = L / (m + 1)
+    k = np.arange(1, 3)
+    c = rng.standard_normal((2, 2, 2)) / (k[:, None, None] + k[None, :, None] + k[None, None, :])
+
+    def logk(x1, x2, x3):
+        s1 = np.sin(np.multiply.outer(k, np.pi * x1 / L))
+        s2 = np.sin(np.multiply.outer(k, np.pi * x2 / L))
+        s3 = np.sin(np.multiply.outer(k, np.pi * x3 / L))
+        return np.einsum("abc,a...,b...,c...->...", c, s1, s2, s3)
+
+    nodes = (np.arange(m) + 1.0) * h
+    half = (np.arange(m + 1) + 0.5) * h
+    # meshgrid with indexing="ij" over (x_3, x_2, x_1)
+    X3, X2, X1 = np.meshgrid(nodes, nodes, half, indexing="ij")
+    lx = logk(X1, X2, X3)
+    X3, X2, X1 = np.meshgrid(nodes, half, nodes, indexing="ij")
+    ly = logk(X1, X2, X3)
+    X3, X2, X1 = np.meshgrid(half, nodes, nodes, indexing="ij")
+    lz = logk(X1, X2, X3)
+    allv = np.concatenate([lx.ravel(), ly.ravel(), lz.ravel()])
+    span = float(np.ptp(allv))
+    scale = (np.log(contrast) / span) if span > 0 else 0.0
+    mean = float(allv.mean()) * scale
+    return (np.ascontiguousarray(np.exp(lx * scale - mean)), np.ascontiguousarray(np.exp(ly * scale - mean)),
+            np.ascontiguousarray(np.exp(lz * scale - mean)))
+
+
 def config_1d(seed: int = 0, m: int = 127, n: int = 128, alpha: float = 1e-3,
               eps: float = 0.01) -> Instance:
     """1D, (0,1), z0 = sin(pi x) + 0.5 sin(3 pi x), T=1, 1% relative Gaussian noise."""

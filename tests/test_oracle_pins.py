@@ -489,6 +489,67 @@ def test_residual_operator_detects_a_wrong_level():
     assert O.residual_operator(y, g, A, n, 1.0, alpha, O.PQ) > 1e-9
 
 
+def test_diffusion_3d_unit_kappa_is_the_laplacian():
+    m, L = 5, 0.9
+    A = O.diffusion_matrix_3d(np.ones((m, m, m + 1)), np.ones((m, m + 1, m)), np.ones((m + 1, m, m)), L)
+    # equal up to the rounding of 6 (1/h^2) against 6/h^2 on the diagonal
+    assert np.allclose(A.toarray(), -O.laplacian_matrix(3, m, L).toarray(), rtol=1e-15, atol=0.0)
+
+
+def test_diffusion_3d_exact_on_quadratics():
+    """u = x_1^2 + x_2^2 + x_3^2, kappa = a + b x_1 + c x_2 + e x_3 (at face midpoints):
+    -div(kappa grad u) = -(6 kappa + 2 b x_1 + 2 c x_2 + 2 e x_3) at nodes with interior
+    neighbours only."""
+    m, L = 7, 1.0
+    h = L / (m + 1)
+    a, b, c, e = 1.2, 0.5, -0.3, 0.8
+    nodes = (np.arange(m) + 1.0) * h
+    half = (np.arange(m + 1) + 0.5) * h
+
+    def kap(X1, X2, X3):
+        return a + b * X1 + c * X2 + e * X3
+
+    X3, X2, X1 = np.meshgrid(nodes, nodes, half, indexing="ij")
+    kx = kap(X1, X2, X3)
+    X3, X2, X1 = np.meshgrid(nodes, half, nodes, indexing="ij")
+    ky = kap(X1, X2, X3)
+    X3, X2, X1 = np.meshgrid(half, nodes, nodes, indexing="ij")
+    kz = kap(X1, X2, X3)
+    A = O.diffusion_matrix_3d(kx, ky, kz, L)
+    X3, X2, X1 = np.meshgrid(nodes, nodes, nodes, indexing="ij")
+    u = X1 ** 2 + X2 ** 2 + X3 ** 2
+    exact = -(6.0 * kap(X1, X2, X3) + 2.0 * b * X1 + 2.0 * c * X2 + 2.0 * e * X3)
+    got = (A @ u.ravel()).reshape(m, m, m)
+    inner = (slice(1, m - 1),) * 3
+    assert np.allclose(got[inner], exact[inner], rtol=1e-11, atol=1e-9)
+
+
+def test_diffusion_3d_splu_vs_eigenbasis():
+    from paper_2107_06381_amd import workloads as W
+    m, n, alpha = 6, 7, 1e-3
+    rng = np.random.default_rng(12)
+    kx, ky, kz = W.diffusion_coefficients_3d(m, rng)
+    A = O.diffusion_matrix_3d(kx, ky, kz, 1.0)
+    assert np.array_equal(A.toarray(), A.toarray().T)
+    lam = np.linalg.eigvalsh(A.toarray())
+    mu = np.sort(O.stencil_eigenvalues(3, m, 1.0).ravel())
+    allv = np.concatenate([kx.ravel(), ky.ravel(), kz.ravel()])
+    assert lam[0] >= allv.min() * mu[0] * (1 - 1e-12) and lam[-1] <= allv.max() * mu[-1] * (1 + 1e-12)
+    g = rng.standard_normal((m, m, m))
+    ys = O.solve_splu_operator(g, A, n, 0.6, alpha, O.PM)
+    yc = O.closed_form_operator(g, A, n, 0.6, alpha, O.PM)
+    assert np.linalg.norm(ys - yc) <= 1e-9 * np.linalg.norm(ys)
+    assert O.residual_operator(ys, g, A, n, 0.6, alpha, O.PM) < 1e-11
+
+
+def test_diffusion_coefficients_3d_input():
+    from paper_2107_06381_amd import workloads as W
+    kx, ky, kz = W.diffusion_coefficients_3d(9, np.random.default_rng(4), contrast=3.0)
+    assert kx.shape == (9, 9, 10) and ky.shape == (9, 10, 9) and kz.shape == (10, 9, 9)
+    allv = np.concatenate([kx.ravel(), ky.ravel(), kz.ravel()])
+    assert np.all(allv > 0) and abs(allv.max() / allv.min() - 3.0) < 1e-9
+
+
 def test_diffusion_coefficients_input():
     from paper_2107_06381_amd import workloads as W
     kx, ky = W.diffusion_coefficients_2d(20, np.random.default_rng(8), contrast=5.0)
