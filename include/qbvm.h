@@ -216,7 +216,18 @@ int qbvm_plan_set_operator_1d(qbvm_plan_t p, const double* lower, const double* 
  * (the operator kernel keeps a workgroup's 1024 points and a grid row either side in LDS). */
 int qbvm_plan_set_operator_2d(qbvm_plan_t p, const double* kx, const double* ky, double tol, int max_iter);
 
-/* Statistics of the last 2D-operator solve (HOST outputs, each may be NULL): iterations
+/* The same in 3D (d = 3 plans): A = -div(kappa grad u) in conservative seven-point form,
+ *   (A u)_{k,j,i} = sum over the six faces of the cell of kappa_face (u_{k,j,i} - u_neighbour) / h^2,
+ * node (k, j, i) at x_1 = (i+1) h, x_2 = (j+1) h, x_3 = (k+1) h, u = 0 outside the grid.
+ * kx: HOST [m][m][m+1] faces between x_1 neighbours; ky: HOST [m][m+1][m] between x_2
+ * neighbours; kz: HOST [m+1][m][m] between x_3 neighbours; row-major, positive, finite,
+ * copied.  Everything else (method, preconditioner, tolerance, workspace of
+ * 12 ceil(N_t/2) m^3 doubles, errors, the entry points it disables) as for 2D;
+ * QBVM_EINVAL for d != 3. */
+int qbvm_plan_set_operator_3d(qbvm_plan_t p, const double* kx, const double* ky, const double* kz, double tol,
+                              int max_iter);
+
+/* Statistics of the last 2D/3D-operator solve (HOST outputs, each may be NULL): iterations
  * taken, the largest relative residual |r_j|/|f0| over the systems, and the number of
  * systems that stopped on a breakdown (a zero bilinear form) before converging. */
 int qbvm_plan_operator_stats(qbvm_plan_t p, int* iterations, double* max_rel_residual, int* breakdowns);

@@ -1,6 +1,6 @@
-// Step (b) with a variable-coefficient 2D operator (Section 3.3: the diagonalisation in
+// Step (b) with a variable-coefficient 2D/3D operator (Section 3.3: the diagonalisation in
 // time leaves one independent spatial system per shift, whatever the operator).  The
-// systems (s_j I + A) w_j = g, A = -div(kappa grad u) in conservative five-point form
+// systems (s_j I + A) w_j = g, A = -div(kappa grad u) in conservative (2d+1)-point form
 // with kappa at the cell faces, are complex symmetric (A real symmetric, s_j complex),
 // so they are solved by conjugate orthogonal conjugate gradients (CG with the bilinear
 // form u^T v in place of the inner product), preconditioned by the constant-coefficient
@@ -74,9 +74,15 @@ __device__ __forceinline__ void kry_init_body(const KrylovArgs& a, long long wg)
   if (b == 0 && threadIdx.x < kSysStride) a.sys[(size_t)j * kSysStride + threadIdx.x] = threadIdx.x == kSysState ? 1.0 : 0.0;
 }
 
+// p = z + beta p_in at flattened point pt of system j, from global memory
+__device__ __forceinline__ c64 kry_dir_at(const KrylovArgs& a, int j, long long pt, c64 beta) {
+  return cadd(kry_load(a.z, a, j, pt), cmul(beta, kry_load(a.pin, a, j, pt)));
+}
+
 // New direction p = z + beta p_in (stored), q = (s_j I + A) p, partial sums of p^T q
 // (slot block 0).  The workgroup's points [base, base + TP) and one grid row on either
-// side are formed once into LDS (pl, TP + 2m entries), the stencil reads them there.
+// side are formed once into LDS (pl, TP + 2m entries), where the stencil reads its x_1
+// and x_2 neighbours; in 3D the x_3 neighbours (a plane away) come from global memory.
 __device__ __forceinline__ void kry_apply_body(const KrylovArgs& a, long long wg, c64* red, c64* pl) {
   const int j = (int)(wg / a.nblk), b = (int)(wg - (long long)j * a.nblk);
   const double* sy = a.sys + (size_t)j * kSysStride;
@@ -87,25 +93,35 @@ __device__ __forceinline__ void kry_apply_body(const KrylovArgs& a, long long wg
   const long long base = (long long)b * TP;
   const long long lo = base - a.m;  // pl[e] holds point lo + e
   const long long hi = base + TP + a.m < a.M ? base + TP + a.m : a.M;
-  for (long long pt = (lo > 0 ? lo : 0) + threadIdx.x; pt < hi; pt += kKryThreads)
-    pl[pt - lo] = cadd(kry_load(a.z, a, j, pt), cmul(beta, kry_load(a.pin, a, j, pt)));
+  for (long long pt = (lo > 0 ? lo : 0) + threadIdx.x; pt < hi; pt += kKryThreads) pl[pt - lo] = kry_dir_at(a, j, pt, beta);
   __syncthreads();
+  const long long m2 = (long long)a.m * a.m;
   c64 acc = {0.0, 0.0};
   const c64 zero = {0.0, 0.0};
   for (int kk = 0; kk < a.ppt; ++kk) {
     const long long pt = base + (long long)kk * kKryThreads + threadIdx.x;
     if (pt < a.M) {
-      const int k = (int)(pt / a.m), i = (int)(pt - (long long)k * a.m);
+      const long long row = pt / a.m;  // k3 m + k2
+      const int i = (int)(pt - row * a.m);
+      const int k3 = (int)(row / a.m), k = (int)(row - (long long)k3 * a.m);
       const long long e = pt - lo;
       const c64 pc = pl[e];
       const c64 pw = i > 0 ? pl[e - 1] : zero, pe = i + 1 < a.m ? pl[e + 1] : zero;
       const c64 ps = k > 0 ? pl[e - a.m] : zero, pn = k + 1 < a.m ? pl[e + a.m] : zero;
-      const double kw = a.kx[(size_t)k * (a.m + 1) + i], ke = a.kx[(size_t)k * (a.m + 1) + i + 1];
-      const double ks = a.ky[(size_t)k * a.m + i], kn = a.ky[(size_t)(k + 1) * a.m + i];
+      const double kw = a.kx[(size_t)row * (a.m + 1) + i], ke = a.kx[(size_t)row * (a.m + 1) + i + 1];
+      const size_t yb = ((size_t)k3 * (a.m + 1) + k) * a.m + i;
+      const double ks = a.ky[yb], kn = a.ky[yb + a.m];
       c64 ap = cscale(csub(pc, pw), kw);
       ap = cadd(ap, cscale(csub(pc, pe), ke));
       ap = cadd(ap, cscale(csub(pc, ps), ks));
       ap = cadd(ap, cscale(csub(pc, pn), kn));
+      if (a.d == 3) {
+        const c64 pd = k3 > 0 ? kry_dir_at(a, j, pt - m2, beta) : zero;
+        const c64 pu = k3 + 1 < a.m ? kry_dir_at(a, j, pt + m2, beta) : zero;
+        const double kd = a.kz[(size_t)pt], ku = a.kz[(size_t)pt + (size_t)m2];
+        ap = cadd(ap, cscale(csub(pc, pd), kd));
+        ap = cadd(ap, cscale(csub(pc, pu), ku));
+      }
       const c64 qv = cadd(cmul(s, pc), cscale(ap, a.ih2));
       kry_store(a.pout, a, j, pt, pc);
       kry_store(a.q, a, j, pt, qv);
@@ -157,8 +173,10 @@ __device__ __forceinline__ void kry_precond_body(const KrylovArgs& a, long long 
   for (int kk = 0; kk < a.ppt; ++kk) {
     const long long pt = base + (long long)kk * kKryThreads + threadIdx.x;
     if (pt < a.M) {
-      const int k2 = (int)(pt / a.m), k1 = (int)(pt - (long long)k2 * a.m);
-      const double re = s.re + a.kbar * (a.mu1d[k1] + a.mu1d[k2]);
+      const long long row = pt / a.m;
+      const int k1 = (int)(pt - row * a.m), k3 = (int)(row / a.m), k2 = (int)(row - (long long)k3 * a.m);
+      const double mu = a.mu1d[k1] + a.mu1d[k2] + (a.d == 3 ? a.mu1d[k3] : 0.0);
+      const double re = s.re + a.kbar * mu;
       const double inv = 1.0 / (re * re + s.im * s.im);
       const c64 rh = kry_load(a.z, a, j, pt);
       const c64 zh = {(rh.re * re + rh.im * s.im) * inv, (rh.im * re - rh.re * s.im) * inv};

@@ -255,10 +255,11 @@ struct qbvm_plan_s {
   c64* tabs = nullptr;  // per-solve time-transform tables, 3 N_t
   double* op = nullptr;  // 1D spatial operator: [m-1] lower, [m] diagonal, [m-1] upper (3m doubles)
   bool has_op = false;
-  // 2D operator -div(kappa grad u): Step (b) by batched preconditioned COCG
-  bool op2 = false;
-  double* kx = nullptr;  // [m][m+1]
-  double* ky = nullptr;  // [m+1][m]
+  // 2D/3D operator -div(kappa grad u): Step (b) by batched preconditioned COCG
+  bool kop = false;
+  double* kx = nullptr;  // faces between x_1 neighbours, m^(d-1) (m+1)
+  double* ky = nullptr;  // between x_2 neighbours
+  double* kz = nullptr;  // 3D: between x_3 neighbours
   double kbar = 1.0, kry_tol = 1e-12;
   int kry_maxit = 200;
   int kry_H = 0, kry_nblk = 0;
@@ -617,15 +618,15 @@ int enqueue_row(const qbvm_plan_s* p, int count, const double* ghat, int level, 
   return QBVM_OK;
 }
 
-// Full or single-level solve with the 2D operator -div(kappa grad u): Step (a) is the
+// Full or single-level solve with the 2D/3D operator -div(kappa grad u): Step (a) is the
 // broadcast of f0 (rank one), Step (b) the batched preconditioned COCG over the shifts
 // j < H (w_{N_t-1-j} = conj w_j: A, f0 real, d_{N_t-1-j} = conj d_j), Step (c) the
 // inverse time transform per pair of points.  g is f0 up to the factor f0s, which the
 // per-solve gamma table carries.  Synchronous.
-int op2_solve(qbvm_plan_s* p, double alpha, int variant, const double* g, double* y, int lev_first,
+int kop_solve(qbvm_plan_s* p, double alpha, int variant, const double* g, double* y, int lev_first,
               int lev_count) {
   const int H = p->kry_H, Nt = p->Nt;
-  const long long M = (long long)p->m * p->m;
+  const long long M = p->nmodes;
   const size_t V = 2 * (size_t)H * (size_t)M;
   std::vector<double> gh((size_t)M);
   HIP_TRY(hipMemcpyAsync(gh.data(), g, sizeof(double) * (size_t)M, hipMemcpyDeviceToHost, p->stream));
@@ -642,6 +643,7 @@ int op2_solve(qbvm_plan_s* p, double alpha, int variant, const double* g, double
   }
   HIP_TRY(launch_tab_job(TabJob{p->tabs, Nt, variant, p->tau, alpha, nullptr, 0}, p->stream));
   KrylovArgs a{};
+  a.d = p->d;
   a.m = p->m;
   a.H = H;
   a.nblk = p->kry_nblk;
@@ -652,6 +654,7 @@ int op2_solve(qbvm_plan_s* p, double alpha, int variant, const double* g, double
   a.tol2 = p->kry_tol * p->kry_tol * gn2;
   a.kx = p->kx;
   a.ky = p->ky;
+  a.kz = p->kz;
   a.mu1d = p->mu1d;
   a.shift = p->tabs;
   a.g = g;
@@ -730,7 +733,7 @@ int op2_solve(qbvm_plan_s* p, double alpha, int variant, const double* g, double
     HIP_TRY(launch_kry_time(t, nwg, lds, p->stream));
   }
   if (active > 0 || worst > p->kry_tol)
-    return set_error(QBVM_ENOCONV, "2D operator: " + std::to_string(active) + " of " + std::to_string(H) +
+    return set_error(QBVM_ENOCONV, "diffusion operator: " + std::to_string(active) + " of " + std::to_string(H) +
                                        " shifted systems above tolerance after " + std::to_string(p->kry_iters) +
                                        " iterations (" + std::to_string(breakdowns) + " breakdowns)");
   return QBVM_OK;
@@ -754,6 +757,54 @@ int wait_mailbox(qbvm_plan_s* p, double seq) {
   return QBVM_OK;
 }
 
+// kappa at the faces of a d = 2 or 3 plan: each array has m^(d-1) (m+1) entries
+int set_diffusion(qbvm_plan_s* p, int d, const double* kx, const double* ky, const double* kz, double tol,
+                  int max_iter) {
+  if (!kx) {
+    p->kop = false;
+    return QBVM_OK;
+  }
+  if (p->d != d) return set_error(QBVM_EINVAL, "the operator's dimension differs from the plan's");
+  if (!ky || (d == 3 && !kz)) return set_error(QBVM_EINVAL, "ky (and kz in 3D) must not be NULL");
+  if (!(tol > 0.0 && tol < 1.0)) return set_error(QBVM_EINVAL, "tol must lie in (0, 1)");
+  if (max_iter < 1) return set_error(QBVM_EINVAL, "max_iter must be >= 1");
+  if (p->m > kKryMaxM) return set_error(QBVM_EUNSUPPORTED, "diffusion operator: m above the stencil kernel's LDS tile");
+  const int m = p->m;
+  const size_t nf = (size_t)(p->nmodes / m) * (m + 1);
+  double lo = INFINITY, hi = 0.0;
+  for (const double* k : {kx, ky, kz}) {
+    if (!k) continue;
+    for (size_t i = 0; i < nf; ++i) {
+      const double v = k[i];
+      if (!(v > 0.0) || !std::isfinite(v)) return set_error(QBVM_EINVAL, "kappa must be positive and finite");
+      lo = std::min(lo, v);
+      hi = std::max(hi, v);
+    }
+  }
+  const int H = (p->Nt + 1) / 2;
+  const long long M = p->nmodes;
+  const long long TP = (long long)kKryPointsPerLane * kKryThreads;
+  const int nblk = (int)((M + TP - 1) / TP);
+  HIP_TRY(hipStreamSynchronize(p->stream));  // solves in flight may still read the old operator
+  if (!p->kx) {
+    HIP_TRY(dalloc(p, &p->kx, nf));
+    HIP_TRY(dalloc(p, &p->ky, nf));
+    if (d == 3) HIP_TRY(dalloc(p, &p->kz, nf));
+    HIP_TRY(dalloc(p, &p->kry, 12 * (size_t)H * (size_t)M));
+    HIP_TRY(dalloc(p, &p->kry_part, 3 * 2 * (size_t)H * (size_t)nblk));
+    HIP_TRY(dalloc(p, &p->kry_sys, 8 * (size_t)H));
+  }
+  HIP_TRY(hipMemcpy(p->kx, kx, sizeof(double) * nf, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->ky, ky, sizeof(double) * nf, hipMemcpyHostToDevice));
+  if (d == 3) HIP_TRY(hipMemcpy(p->kz, kz, sizeof(double) * nf, hipMemcpyHostToDevice));
+  p->kbar = 0.5 * (lo + hi);
+  p->kry_tol = tol;
+  p->kry_maxit = max_iter;
+  p->kry_H = H;
+  p->kry_nblk = nblk;
+  p->kop = true;
+  return QBVM_OK;
+}
 }  // namespace
 
 // ======================================================================= ABI
@@ -803,8 +854,8 @@ int qbvm_solve(qbvm_plan_t p, double alpha, int variant, const double* g_delta, 
   if (rc) return rc;
   if (output != QBVM_OUT_ALL && output != QBVM_OUT_Y0 && output != QBVM_OUT_YN)
     return set_error(QBVM_EINVAL, "output must be QBVM_OUT_ALL, QBVM_OUT_Y0 or QBVM_OUT_YN");
-  if (p->op2)
-    return op2_solve(p, alpha, variant, g_delta, y, output == QBVM_OUT_YN ? p->n : 0,
+  if (p->kop)
+    return kop_solve(p, alpha, variant, g_delta, y, output == QBVM_OUT_YN ? p->n : 0,
                      output == QBVM_OUT_ALL ? p->Nt : 1);
   if (output == QBVM_OUT_ALL)
     return enqueue_full(p, alpha, nullptr, variant, g_delta, y, p->s2, nullptr, p->stream, p->W);
@@ -862,46 +913,13 @@ int qbvm_plan_set_operator_1d(qbvm_plan_t p, const double* lower, const double* 
 
 int qbvm_plan_set_operator_2d(qbvm_plan_t p, const double* kx, const double* ky, double tol, int max_iter) {
   if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
-  if (!kx) {
-    p->op2 = false;
-    return QBVM_OK;
-  }
-  if (p->d != 2) return set_error(QBVM_EINVAL, "a 2D operator can be set on 2D plans only");
-  if (p->m > kKryMaxM) return set_error(QBVM_EUNSUPPORTED, "2D operator: m above the stencil kernel's LDS tile");
-  if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
-  if (!ky) return set_error(QBVM_EINVAL, "ky is NULL");
-  if (!(tol > 0.0 && tol < 1.0)) return set_error(QBVM_EINVAL, "tol must lie in (0, 1)");
-  if (max_iter < 1) return set_error(QBVM_EINVAL, "max_iter must be >= 1");
-  const int m = p->m;
-  const size_t nf = (size_t)m * (m + 1);
-  double lo = INFINITY, hi = 0.0;
-  for (size_t i = 0; i < nf; ++i) {
-    for (double v : {kx[i], ky[i]}) {
-      if (!(v > 0.0) || !std::isfinite(v)) return set_error(QBVM_EINVAL, "kappa must be positive and finite");
-      lo = std::min(lo, v);
-      hi = std::max(hi, v);
-    }
-  }
-  const int H = (p->Nt + 1) / 2;
-  const long long M = (long long)m * m;
-  const int nblk = (int)((M + (long long)kKryPointsPerLane * kKryThreads - 1) / ((long long)kKryPointsPerLane * kKryThreads));
-  HIP_TRY(hipStreamSynchronize(p->stream));  // solves in flight may still read the old operator
-  if (!p->kx) {
-    HIP_TRY(dalloc(p, &p->kx, nf));
-    HIP_TRY(dalloc(p, &p->ky, nf));
-    HIP_TRY(dalloc(p, &p->kry, 12 * (size_t)H * (size_t)M));
-    HIP_TRY(dalloc(p, &p->kry_part, 3 * 2 * (size_t)H * (size_t)nblk));
-    HIP_TRY(dalloc(p, &p->kry_sys, 8 * (size_t)H));
-  }
-  HIP_TRY(hipMemcpy(p->kx, kx, sizeof(double) * nf, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->ky, ky, sizeof(double) * nf, hipMemcpyHostToDevice));
-  p->kbar = 0.5 * (lo + hi);
-  p->kry_tol = tol;
-  p->kry_maxit = max_iter;
-  p->kry_H = H;
-  p->kry_nblk = nblk;
-  p->op2 = true;
-  return QBVM_OK;
+  return set_diffusion(p, 2, kx, ky, nullptr, tol, max_iter);
+}
+
+int qbvm_plan_set_operator_3d(qbvm_plan_t p, const double* kx, const double* ky, const double* kz, double tol,
+                              int max_iter) {
+  if (!p) return set_error(QBVM_EINVAL, "plan is NULL");
+  return set_diffusion(p, 3, kx, ky, kz, tol, max_iter);
 }
 
 int qbvm_plan_operator_stats(qbvm_plan_t p, int* iterations, double* max_rel_residual, int* breakdowns) {
@@ -914,7 +932,7 @@ int qbvm_plan_operator_stats(qbvm_plan_t p, int* iterations, double* max_rel_res
 
 int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f, double* y) {
   if (!p || !f || !y) return set_error(QBVM_EINVAL, "NULL argument");
-  if (p->has_op || p->op2) return set_error(QBVM_EUNSUPPORTED, "general right-hand side with a spatial operator set");
+  if (p->has_op || p->kop) return set_error(QBVM_EUNSUPPORTED, "general right-hand side with a spatial operator set");
   if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_alpha(alpha, variant);
   if (rc) return rc;
@@ -947,7 +965,7 @@ int qbvm_solve_general(qbvm_plan_t p, double alpha, int variant, const double* f
 
 int qbvm_discrepancy(qbvm_plan_t p, double alpha, int variant, const double* g_delta, double* D_out) {
   if (!p || !g_delta || !D_out) return set_error(QBVM_EINVAL, "NULL argument");
-  if (p->has_op || p->op2) return set_error(QBVM_EUNSUPPORTED, "discrepancy with a spatial operator set");
+  if (p->has_op || p->kop) return set_error(QBVM_EUNSUPPORTED, "discrepancy with a spatial operator set");
   if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_alpha(alpha, variant);
   if (rc) return rc;
@@ -992,7 +1010,7 @@ static int check_opts(const qbvm_alpha_opts* o) {
 int qbvm_choose_alpha(qbvm_plan_t p, int variant, const double* g_delta, double delta, const qbvm_alpha_opts* o,
                       double* alpha_out, qbvm_alpha_info* info) {
   if (!p || !g_delta || !alpha_out) return set_error(QBVM_EINVAL, "NULL argument");
-  if (p->has_op || p->op2) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
+  if (p->has_op || p->kop) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
   if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_opts(o);
   if (rc) return rc;
@@ -1071,7 +1089,7 @@ static int ensure_batch_ws(qbvm_plan_t p, size_t bytes) {
 int qbvm_bisect_batched(qbvm_plan_t p, int variant, int count, const double* g_deltas, const double* deltas,
                         const qbvm_alpha_opts* o, double* alphas_out, int* hits_out) {
   if (!p || !g_deltas || !deltas || !alphas_out) return set_error(QBVM_EINVAL, "NULL argument");
-  if (p->has_op || p->op2) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
+  if (p->has_op || p->kop) return set_error(QBVM_EUNSUPPORTED, "alpha choice with a spatial operator set");
   if (p->no_sine) return set_error(QBVM_EUNSUPPORTED, "sine transform of length 2(m+1) exceeds the FFT core");
   int rc = check_opts(o);
   if (rc) return rc;

@@ -1,4 +1,4 @@
-// Kernels of the 2D variable-coefficient Step (b): batched preconditioned conjugate
+// Kernels of the 2D/3D variable-coefficient Step (b): batched preconditioned conjugate
 // orthogonal conjugate gradients over the shifted systems (its Step (c) kernel runs on the
 // runtime FFT engine and lives with that engine's constant tables in qbvm_kernels.hip).
 #include "qbvm_internal.hpp"
@@ -30,7 +30,8 @@ __global__ __launch_bounds__(kKryThreads) void k_kry_scalars(KrylovArgs a) {
 }
 
 hipError_t launch_krylov(const KrylovArgs& a, int step, hipStream_t s) {
-  if (a.H < 1 || a.nblk < 1 || a.ppt < 1 || a.M != (long long)a.m * a.m ||
+  if (a.H < 1 || a.nblk < 1 || a.ppt < 1 || (a.d != 2 && a.d != 3) || (a.d == 3 && !a.kz) ||
+      a.M != (long long)a.m * a.m * (a.d == 3 ? a.m : 1) ||
       (long long)a.nblk * a.ppt * kKryThreads < a.M)
     return hipErrorInvalidValue;
   const void* f = nullptr;

@@ -152,12 +152,12 @@ struct ThomasArgs {
   const double* op_up;
 };
 
-// 2D Step (b) with the operator A = -div(kappa grad u) (five-point conservative form,
+// 2D/3D Step (b) with the operator A = -div(kappa grad u) ((2d+1)-point conservative form,
 // kappa at the cell faces): the shifted systems (s_j I + A) w_j = g, s_j = d_j/tau, for
 // j < H = ceil(N_t/2) (the others are their conjugates), by batched conjugate orthogonal
 // conjugate gradients preconditioned with the constant-coefficient solve
 // (s_j I + kbar (-Lap_h))^{-1} in the sine basis.  Complex vectors are [2][H][M] doubles
-// (real block, then imaginary block), M = m*m points, x_1 fastest.
+// (real block, then imaginary block), M = m^d points, x_1 fastest.
 constexpr int kKryThreads = 256;       // lanes per workgroup of the Krylov kernels
 constexpr int kKryPointsPerLane = 4;   // points per lane (workgroup: 1024 points of one system)
 // dynamic LDS of the operator kernel: the workgroup's points and one grid row either side,
@@ -168,6 +168,7 @@ constexpr size_t kry_apply_lds(int m) {
 constexpr int kKryMaxM = (int)((160 * 1024 - 16 * kKryThreads) / 16 - kKryPointsPerLane * kKryThreads) / 2;
 enum KryStep { kKryInit = 0, kKryApply, kKryUpdate, kKryPrecond, kKryScalars };
 struct KrylovArgs {
+  int d;          // 2 or 3
   int m;
   int H;
   int nblk;       // workgroups per system
@@ -177,8 +178,9 @@ struct KrylovArgs {
   double kbar;    // preconditioner coefficient
   double tol2;    // converged when |r_j|^2 <= tol2
   int init;       // scalars kernel: first call (no residual partial sums yet)
-  const double* kx;    // [m][m+1] faces between x_1 neighbours
-  const double* ky;    // [m+1][m] faces between x_2 neighbours
+  const double* kx;    // [m^(d-2)][m][m+1] faces between x_1 neighbours
+  const double* ky;    // [m^(d-2)][m+1][m] faces between x_2 neighbours
+  const double* kz;    // 3D: [m+1][m][m] faces between x_3 neighbours
   const double* mu1d;  // eigenvalues of the 1D Dirichlet stencil
   const c64* shift;    // [N_t] d_j/tau (per-solve table)
   const double* g;     // right-hand side, M
@@ -192,7 +194,7 @@ struct KrylovArgs {
   double* sys;         // [H][8] per-system scalars (see qbvm_bodies_krylov.hpp)
 };
 
-// Step (c) for the 2D operator path: y_l = Re(gamma_l^{-1}/N_t sum_j theta^{-jl} w_j) per
+// Step (c) for the 2D/3D operator path: y_l = Re(gamma_l^{-1}/N_t sum_j theta^{-jl} w_j) per
 // point, w_j for j >= H taken as conj(w_{N_t-1-j}); two points share one transform.
 struct KryTimeArgs {
   int Nt;

@@ -33,7 +33,7 @@ EXPORTS = [
     "qbvm_last_error", "qbvm_version", "qbvm_profile_enable", "qbvm_profile_reset",
     "qbvm_profile_count", "qbvm_profile_get", "qbvm_plan_autotune", "qbvm_plan_get_variants",
     "qbvm_plan_set_variants", "qbvm_plan_set_operator_1d", "qbvm_plan_set_plane", "qbvm_plan_get_plane",
-    "qbvm_plan_set_operator_2d", "qbvm_plan_operator_stats",
+    "qbvm_plan_set_operator_2d", "qbvm_plan_set_operator_3d", "qbvm_plan_operator_stats",
 ]
 
 
@@ -108,6 +108,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qbvm_plan_set_variants": (i, [vp, i, i, i, i]),
         "qbvm_plan_set_operator_1d": (i, [vp, vp, vp, vp]),
         "qbvm_plan_set_operator_2d": (i, [vp, vp, vp, d, i]),
+        "qbvm_plan_set_operator_3d": (i, [vp, vp, vp, vp, d, i]),
         "qbvm_plan_operator_stats": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(d), ctypes.POINTER(i)]),
         "qbvm_plan_set_plane": (i, [vp, i]),
         "qbvm_plan_get_plane": (i, [vp, ctypes.POINTER(i)]),
@@ -224,6 +225,20 @@ class Plan:
         if kx.shape != (self.m, self.m + 1) or ky.shape != (self.m + 1, self.m):
             raise ValueError("kx must be (m, m+1) and ky (m+1, m)")
         _check(self.L_.qbvm_plan_set_operator_2d(self._h, kx.ctypes.data, ky.ctypes.data, float(tol),
+                                                 int(max_iter)))
+
+    def set_operator_3d(self, kx=None, ky=None, kz=None, tol: float = 1e-12, max_iter: int = 200):
+        """-div(kappa grad u) in place of -Lap_h (3D), kappa at the cell faces: kx (m, m, m+1),
+        ky (m, m+1, m), kz (m+1, m, m); kx=None restores -Lap_h (qbvm_plan_set_operator_3d)."""
+        import numpy as np
+        if kx is None:
+            _check(self.L_.qbvm_plan_set_operator_3d(self._h, None, None, None, 0.0, 0))
+            return
+        m = self.m
+        arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (kx, ky, kz)]
+        if [a.shape for a in arrs] != [(m, m, m + 1), (m, m + 1, m), (m + 1, m, m)]:
+            raise ValueError("kx, ky, kz must be (m, m, m+1), (m, m+1, m), (m+1, m, m)")
+        _check(self.L_.qbvm_plan_set_operator_3d(self._h, *(a.ctypes.data for a in arrs), float(tol),
                                                  int(max_iter)))
 
     def operator_stats(self) -> dict:

@@ -6,9 +6,10 @@
 //       (plane: 0 = separate x_2 / x_1 passes, v + 1 = plane-pass variant v)
 //   kernels_cpu dst   d m batch in.bin out.bin [var_rows var_cols input]
 //   kernels_cpu general d m n L T alpha variant f.bin out.bin [padded var_gen]   (general right-hand side)
-//   kernels_cpu op2d m n L T alpha variant g.bin out.bin kx.bin ky.bin tol max_iter stats.bin
-//       (2D operator -div(kappa grad u): batched preconditioned COCG and Step (c), every level;
-//       stats.bin: iterations, largest relative residual, breakdowns as three doubles)
+//   kernels_cpu opdiff d m n L T alpha variant g.bin out.bin kx.bin ky.bin kz.bin tol max_iter stats.bin
+//       (2D/3D operator -div(kappa grad u): batched preconditioned COCG and Step (c), every
+//       level; kz.bin unused for d = 2; stats.bin: iterations, largest relative residual,
+//       breakdowns as three doubles)
 //   kernels_cpu solveop m n L T alpha variant in.bin out.bin op.bin level   (1D, tridiagonal operator;
 //       op.bin: lower[m-1] diag[m] upper[m-1]; level -1: every level, else that level only)
 #include "hip_cpu_shim.hpp"
@@ -470,13 +471,14 @@ int main(int argc, char** argv) {
     write_file(argv[9], y.data(), ny * sizeof(double));
     return 0;
   }
-  if (cmd == "op2d" && argc == 15) {
-    // the host loop of qbvm_host.cpp::op2_solve with the emulated kernels
-    const int m = atoi(argv[2]), n = atoi(argv[3]);
-    const double L = atof(argv[4]), T = atof(argv[5]), alpha = atof(argv[6]);
-    const int variant = atoi(argv[7]);
-    const double tol = atof(argv[12]);
-    const int maxit = atoi(argv[13]);
+  if (cmd == "opdiff" && argc == 17) {
+    // the host loop of qbvm_host.cpp::kop_solve with the emulated kernels
+    const int d = atoi(argv[2]), m = atoi(argv[3]), n = atoi(argv[4]);
+    const double L = atof(argv[5]), T = atof(argv[6]), alpha = atof(argv[7]);
+    const int variant = atoi(argv[8]);
+    const double tol = atof(argv[14]);
+    const int maxit = atoi(argv[15]);
+    if (d != 2 && d != 3) return 8;
     Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1));
     const double h = L / (m + 1);
     std::vector<double> mu(m);
@@ -484,20 +486,26 @@ int main(int argc, char** argv) {
       const long double sn = sinl((long double)k * plan::kPiL / (2.0L * (m + 1)));
       mu[k - 1] = (double)(4.0L / ((long double)h * h) * sn * sn);
     }
-    sched::Geom g = geom(2, m, n, L, T, tt, st, mu);
-    const long long M = (long long)m * m;
-    const size_t nf = (size_t)m * (m + 1);
-    auto rg = read_file(argv[8]), rkx = read_file(argv[10]), rky = read_file(argv[11]);
+    sched::Geom g = geom(d, m, n, L, T, tt, st, mu);
+    const long long M = g.nmodes;
+    const size_t nf = (size_t)(M / m) * (m + 1);
+    auto rg = read_file(argv[9]), rkx = read_file(argv[11]), rky = read_file(argv[12]);
     if (rg.size() != (size_t)M * 8 || rkx.size() != nf * 8 || rky.size() != nf * 8) return 7;
-    std::vector<double> gv(M), kx(nf), ky(nf);
+    std::vector<double> gv(M), kx(nf), ky(nf), kz(d == 3 ? nf : 0);
     std::memcpy(gv.data(), rg.data(), rg.size());
     std::memcpy(kx.data(), rkx.data(), rkx.size());
     std::memcpy(ky.data(), rky.data(), rky.size());
-    double lo = INFINITY, hi = 0.0, gn2 = 0.0;
-    for (size_t i = 0; i < nf; ++i) {
-      lo = std::min(lo, std::min(kx[i], ky[i]));
-      hi = std::max(hi, std::max(kx[i], ky[i]));
+    if (d == 3) {
+      auto rkz = read_file(argv[13]);
+      if (rkz.size() != nf * 8) return 7;
+      std::memcpy(kz.data(), rkz.data(), rkz.size());
     }
+    double lo = INFINITY, hi = 0.0, gn2 = 0.0;
+    for (const auto* k : {&kx, &ky, &kz})
+      for (double v : *k) {
+        lo = std::min(lo, v);
+        hi = std::max(hi, v);
+      }
     for (double v : gv) gn2 += v * v;
     const int H = (g.Nt + 1) / 2;
     const int nblk = (int)((M + (long long)kKryPointsPerLane * kKryThreads - 1) / ((long long)kKryPointsPerLane * kKryThreads));
@@ -508,6 +516,7 @@ int main(int argc, char** argv) {
     const TabJob job{tabs.data(), g.Nt, variant, g.tau, alpha, nullptr, 0};
     tab_job_run(job, 0, 1);
     KrylovArgs a{};
+    a.d = d;
     a.m = m;
     a.H = H;
     a.nblk = nblk;
@@ -518,6 +527,7 @@ int main(int argc, char** argv) {
     a.tol2 = tol * tol * gn2;
     a.kx = kx.data();
     a.ky = ky.data();
+    a.kz = d == 3 ? kz.data() : nullptr;
     a.mu1d = mu.data();
     a.shift = tabs.data();
     a.g = gv.data();
@@ -587,9 +597,9 @@ int main(int argc, char** argv) {
     const size_t lds = sizeof(c64) * ((size_t)t.S * t.fft.nc + 2 * (size_t)t.S);
     if (t.fft.wide) run_grid(nwg, 256, lds, [&](long long wg, c64* l) { kry_time_body<true>(t, wg, l); });
     else run_grid(nwg, 256, lds, [&](long long wg, c64* l) { kry_time_body<false>(t, wg, l); });
-    write_file(argv[9], y.data(), y.size() * sizeof(double));
+    write_file(argv[10], y.data(), y.size() * sizeof(double));
     const double stats[3] = {(double)it, worst, brk};
-    write_file(argv[14], stats, sizeof(stats));
+    write_file(argv[16], stats, sizeof(stats));
     return 0;
   }
   if (cmd == "solve" && (argc == 11 || argc == 14 || argc == 15 || argc == 16)) {

@@ -196,27 +196,34 @@ def test_operator_1d_vs_oracle(exe, tmp_path, m, n, alpha, variant, adv, level):
     assert np.linalg.norm(y - yc) <= 1e-10 * np.linalg.norm(yc)
 
 
-@pytest.mark.parametrize("m,n,alpha,variant", [(7, 8, 1e-3, 0), (12, 15, 1e-4, 1), (31, 8, 1e-2, 0)])
-def test_operator_2d_vs_oracle(exe, tmp_path, m, n, alpha, variant):
-    """2D operator -div(kappa grad u): the Krylov kernel bodies (operator, update, sine-basis
-    preconditioner, scalars) and the Step (c) kernel, driven by the same host loop as the
-    library, against SuperLU on the assembled rows (sine lengths 16, 26 generic and 64
-    compile-time; N_t = 9, 16)."""
+@pytest.mark.parametrize("d,m,n,alpha,variant", [(2, 7, 8, 1e-3, 0), (2, 12, 15, 1e-4, 1), (2, 31, 8, 1e-2, 0),
+                                                 (3, 5, 6, 1e-3, 1), (3, 7, 8, 1e-4, 0)])
+def test_operator_diffusion_vs_oracle(exe, tmp_path, d, m, n, alpha, variant):
+    """2D/3D operator -div(kappa grad u): the Krylov kernel bodies (operator, update,
+    sine-basis preconditioner, scalars) and the Step (c) kernel, driven by the same host
+    loop as the library, against SuperLU on the assembled rows (2D sine lengths 16, 26
+    generic and 64 compile-time; N_t = 7, 9, 16)."""
     from paper_2107_06381_amd import workloads as W
-    rng = np.random.default_rng(m * 3 + n)
-    kx, ky = W.diffusion_coefficients_2d(m, rng)
-    g = rng.standard_normal((m, m))
+    rng = np.random.default_rng(d * 100 + m * 3 + n)
+    if d == 2:
+        kx, ky = W.diffusion_coefficients_2d(m, rng)
+        kz = np.zeros(1)
+        A_of = lambda: O.diffusion_matrix_2d(kx, ky, 1.0)  # noqa: E731
+    else:
+        kx, ky, kz = W.diffusion_coefficients_3d(m, rng)
+        A_of = lambda: O.diffusion_matrix_3d(kx, ky, kz, 1.0)  # noqa: E731
+    g = rng.standard_normal((m,) * d)
     L, T, tol = 1.0, 0.9, 1e-12
-    fg, fo, fkx, fky, fs = (tmp_path / x for x in ("g.bin", "o.bin", "kx.bin", "ky.bin", "s.bin"))
+    fg, fo, fkx, fky, fkz, fs = (tmp_path / x for x in ("g.bin", "o.bin", "kx.bin", "ky.bin", "kz.bin", "s.bin"))
     g.tofile(fg)
     kx.tofile(fkx)
     ky.tofile(fky)
-    _run(exe, ["op2d", m, n, repr(L), repr(T), repr(alpha), variant, fg, fo, fkx, fky, repr(tol), 200, fs],
-         tmp_path)
-    y = np.fromfile(fo).reshape((n + 1, m, m))
+    kz.tofile(fkz)
+    _run(exe, ["opdiff", d, m, n, repr(L), repr(T), repr(alpha), variant, fg, fo, fkx, fky, fkz, repr(tol), 200,
+               fs], tmp_path)
+    y = np.fromfile(fo).reshape((n + 1,) + (m,) * d)
     it, worst, brk = np.fromfile(fs)
-    A = O.diffusion_matrix_2d(kx, ky, L)
-    yc = O.solve_splu_operator(g, A, n, T, alpha, variant).reshape((n + 1, m, m))
+    yc = O.solve_splu_operator(g, A_of(), n, T, alpha, variant).reshape((n + 1,) + (m,) * d)
     assert 1 <= it <= 200 and worst <= tol and brk == 0
     assert np.linalg.norm(y - yc) <= 1e-9 * np.linalg.norm(yc)
     assert np.linalg.norm(y[0] - yc[0]) <= 1e-9 * np.linalg.norm(yc[0])

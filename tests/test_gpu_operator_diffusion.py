@@ -1,6 +1,7 @@
-"""GPU parity of the 2D variable-coefficient operator path (Section 3.3: another spatial
-operator changes only Step (b)) against the oracle's SuperLU solve of the assembled
-all-at-once rows with A = -div(kappa grad u), and properties at the full 2D size.
+"""GPU parity of the 2D/3D variable-coefficient operator path (Section 3.3: another
+spatial operator changes only Step (b)) against the oracle's SuperLU solve of the
+assembled all-at-once rows with A = -div(kappa grad u) (or its eigenbasis closed form),
+and properties at the full 2D size and a larger 3D size.
 
 Bar: relative 2-norm 1e-9 on the whole solution and on y^0.  A level l far below y^0
 is also accepted with an absolute error below 1e3 * tol * |omega|^{-l/N_t} * ||y^0||:
@@ -160,11 +161,10 @@ def test_operator2d_refusals_and_restore():
     torch.cuda.synchronize()
     assert torch.equal(again, base)
     p.close()
-    for d in (1, 3):
-        q = qbvm.Plan(d, 7, 8)
-        with pytest.raises(qbvm.QbvmError):
-            q.set_operator_2d(np.ones((7, 8)), np.ones((8, 7)))
-        q.close()
+    q = qbvm.Plan(1, 7, 8)
+    with pytest.raises(qbvm.QbvmError):
+        q.set_operator_2d(np.ones((7, 8)), np.ones((8, 7)))
+    q.close()
 
 
 def test_operator2d_full_size_residual():
@@ -180,3 +180,75 @@ def test_operator2d_full_size_residual():
     assert st["max_rel_residual"] <= KTOL and st["breakdowns"] == 0
     A = O.diffusion_matrix_2d(kx, ky, 1.0)
     assert O.residual_operator(y.reshape(n + 1, -1), g, A, n, T, alpha, 0) < 1e-9
+
+
+def solve_op3(m, n, T, alpha, variant, kx, ky, kz, g, tol=KTOL):
+    p = qbvm.Plan(3, m, n, 1.0, T)
+    p.set_operator_3d(kx, ky, kz, tol, 200)
+    y = p.solve(alpha, variant, to_dev(g))
+    torch.cuda.synchronize()
+    st = p.operator_stats()
+    out = y.cpu().numpy()
+    p.close()
+    return out, st
+
+
+@pytest.mark.parametrize("m,n,alpha,variant", [(7, 8, 1e-3, 0), (9, 16, 1e-5, 1), (6, 5, 1e-2, 0)])
+def test_operator3d_vs_oracle(m, n, alpha, variant):
+    say(f"[case] operator3d m={m} n={n} alpha={alpha} variant={variant}")
+    T = 0.7
+    rng = np.random.default_rng(m * 17 + n)
+    kx, ky, kz = W.diffusion_coefficients_3d(m, rng)
+    g = rng.standard_normal((m, m, m))
+    y, st = solve_op3(m, n, T, alpha, variant, kx, ky, kz, g)
+    A = O.diffusion_matrix_3d(kx, ky, kz, 1.0)
+    solver = O.solve_splu_operator if (n + 1) * m ** 3 <= 30000 else O.closed_form_operator
+    yc = solver(g, A, n, T, alpha, variant).reshape((n + 1, m, m, m))
+    say(f"  stats {st}, rel {rel(y, yc):.3e}")
+    assert st["max_rel_residual"] <= KTOL and st["breakdowns"] == 0
+    assert rel(y, yc) < BAR and rel(y[0], yc[0]) < BAR
+    ok, info = levels_ok(y, yc, n, alpha, variant, T)
+    assert ok, info
+
+
+def test_operator3d_unit_kappa_is_the_sine_solve():
+    m, n, alpha = 15, 16, 1e-4
+    g = np.random.default_rng(6).standard_normal((m, m, m))
+    ones = (np.ones((m, m, m + 1)), np.ones((m, m + 1, m)), np.ones((m + 1, m, m)))
+    y, st = solve_op3(m, n, 1.0, alpha, 0, *ones, g)
+    p = qbvm.Plan(3, m, n, 1.0, 1.0)
+    yd = p.solve(alpha, 0, to_dev(g)).cpu().numpy()
+    p.close()
+    assert st["iterations"] == 1, st
+    assert rel(y, yd) < 1e-11
+
+
+def test_operator3d_residual_larger_grid():
+    """3D m = 31, n = 32: the all-at-once rows with the seven-point operator applied matrix
+    free to the GPU solution."""
+    m, n, alpha, T = 31, 32, 1e-4, 0.5
+    say("[case] operator3d m=31")
+    rng = np.random.default_rng(13)
+    kx, ky, kz = W.diffusion_coefficients_3d(m, rng)
+    g = rng.standard_normal((m, m, m))
+    y, st = solve_op3(m, n, T, alpha, 0, kx, ky, kz, g)
+    say(f"  stats {st}")
+    assert st["max_rel_residual"] <= KTOL and st["breakdowns"] == 0
+    A = O.diffusion_matrix_3d(kx, ky, kz, 1.0)
+    assert O.residual_operator(y.reshape(n + 1, -1), g, A, n, T, alpha, 0) < 1e-9
+
+
+def test_operator3d_refusals():
+    m = 7
+    q = qbvm.Plan(2, m, 8)
+    with pytest.raises(qbvm.QbvmError):
+        q.set_operator_3d(np.ones((m, m, m + 1)), np.ones((m, m + 1, m)), np.ones((m + 1, m, m)))
+    q.close()
+    p = qbvm.Plan(3, m, 8)
+    bad = np.ones((m + 1, m, m))
+    bad[2, 3, 4] = 0.0
+    with pytest.raises(qbvm.QbvmError):
+        p.set_operator_3d(np.ones((m, m, m + 1)), np.ones((m, m + 1, m)), bad)
+    with pytest.raises(qbvm.QbvmError):
+        p.set_operator_2d(np.ones((m, m + 1)), np.ones((m + 1, m)))
+    p.close()
