@@ -7,7 +7,7 @@ interior points per dimension (7-point Laplacian), n=128 backward-Euler steps
 synthetic).  One step = one full solve (every level: 129 levels of 127^3 values,
 2.1 GB), inputs resident in HBM.  Metric: solve throughput in Munknowns/s on the
 n*m^d basis.  Side sections: the 2D workload (m=255, n=256), alpha choice,
-batched solves, general right-hand side, 1D and 2D variable-coefficient operators.
+batched solves, general right-hand side, 1D/2D/3D variable-coefficient operators.
 
 Prints one JSON line.  --gpus above 1 is refused: this build measures one GPU.
 """
@@ -27,10 +27,17 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
+# sources that no recorded counter summary depends on (the operator-path Krylov kernels)
+HASH_EXCLUDE = {"qbvm_krylov.hip", "qbvm_bodies_krylov.hpp"}
+
+
 def source_hash() -> str:
+    """Hash of the kernel and executor sources the committed counter summaries were taken on."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2107_06381_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
+        if f in HASH_EXCLUDE:
+            continue
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -421,22 +428,26 @@ def operator_1d_bench(steps: int = 20):
             "config_1d_m127_n128_us_per_solve": round(us1, 2)}
 
 
-def operator_2d_bench(reps: int = 3):
-    """2D solve with the variable-coefficient operator -div(kappa grad u) (Step (b) by
+def operator_diffusion_bench(d: int = 2, reps: int = 3):
+    """2D or 3D solve with the variable-coefficient operator -div(kappa grad u) (Step (b) by
     batched preconditioned conjugate orthogonal CG over the shifts) on the 2D workload's
-    grid: seconds per solve (synchronous; host clock, best of reps), iterations, the
-    kernel split, and the HBM fraction of the iteration's algorithmic bytes."""
+    grid (m=255, n=256) or the 3D workload's grid (m=127, n=128): seconds per solve
+    (synchronous; host clock, best of reps), iterations, the kernel split, and the HBM
+    fraction of the iteration's algorithmic bytes."""
     import numpy as np
     import torch
     from paper_2107_06381_amd import qbvm, workloads as W
-    m, n, alpha, tol = 255, 256, 1e-4, 1e-12
+    m, n, alpha, tol = (255, 256, 1e-4, 1e-12) if d == 2 else (127, 128, 1e-5, 1e-12)
     rng = np.random.default_rng(19)
-    kx, ky = W.diffusion_coefficients_2d(m, rng)
-    plan = qbvm.Plan(2, m, n, 1.0, 1.0)
+    kap = W.diffusion_coefficients_2d(m, rng) if d == 2 else W.diffusion_coefficients_3d(m, rng)
+    plan = qbvm.Plan(d, m, n, 1.0, 1.0 if d == 2 else 0.5)
     plan.autotune()
-    plan.set_operator_2d(kx, ky, tol, 200)
-    g = torch.from_numpy(rng.standard_normal((m, m))).to("cuda:0")
-    y = torch.empty((n + 1, m, m), dtype=torch.float64, device="cuda:0")
+    if d == 2:
+        plan.set_operator_2d(*kap, tol, 200)
+    else:
+        plan.set_operator_3d(*kap, tol, 200)
+    g = torch.from_numpy(rng.standard_normal((m,) * d)).to("cuda:0")
+    y = torch.empty((n + 1,) + (m,) * d, dtype=torch.float64, device="cuda:0")
     plan.solve(alpha, qbvm.QBVM_PQ, g, y)
     torch.cuda.synchronize()
     best = float("inf")
@@ -458,9 +469,9 @@ def operator_2d_bench(reps: int = 3):
     tot_bytes = sum(r["bytes"] for r in rep.values())
     tot_ms = sum(r["total_ms"] for r in rep.values())
     H = (n + 2) // 2
-    return {"workload": "2D m=255, n=256 (N_t=257), -div(kappa grad u), kappa log-smooth contrast 4, alpha=1e-4, "
-                        "COCG tol 1e-12, every level",
-            "ms_per_solve": round(best * 1e3, 3), "Munknowns_per_s": round(n * m * m / best / 1e6, 1),
+    work = ("2D m=255, n=256 (N_t=257), alpha=1e-4" if d == 2 else "3D m=127, n=128 (N_t=129), T=0.5, alpha=1e-5")
+    return {"workload": f"{work}, -div(kappa grad u), kappa log-smooth contrast 4, COCG tol 1e-12, every level",
+            "ms_per_solve": round(best * 1e3, 3), "Munknowns_per_s": round(n * m ** d / best / 1e6, 1),
             "iterations": st["iterations"], "max_rel_residual": st["max_rel_residual"],
             "shifted_systems": H, "iteration_bytes_per_complex_unknown": 320,
             "kernel_ms_sum": round(tot_ms, 3),
@@ -593,7 +604,7 @@ def main():
     ap.add_argument("--no-alpha", action="store_true", help="skip the learned/bisection alpha-choice section")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched section")
     ap.add_argument("--no-general", action="store_true", help="skip the general right-hand-side section")
-    ap.add_argument("--no-operator", action="store_true", help="skip the 1D and 2D variable-coefficient sections")
+    ap.add_argument("--no-operator", action="store_true", help="skip the 1D, 2D and 3D variable-coefficient sections")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for counter calibration)")
     ap.add_argument("--alpha-train", type=int, default=20000)
@@ -643,7 +654,8 @@ def main():
     batched = None if args.no_batched else batched_bench()
     general = None if args.no_general else general_rhs_bench()
     operator_1d = None if args.no_operator else operator_1d_bench()
-    operator_2d = None if args.no_operator else operator_2d_bench()
+    operator_2d = None if args.no_operator else operator_diffusion_bench(2)
+    operator_3d = None if args.no_operator else operator_diffusion_bench(3, reps=2)
     n, m = 128, 127
     line = {
         "metric": "PinT solve Munknowns/s (n*m^d, FP64)",
@@ -674,6 +686,7 @@ def main():
         "general_rhs": general,
         "operator_1d": operator_1d,
         "operator_2d": operator_2d,
+        "operator_3d": operator_3d,
     }
     print(json.dumps(line), flush=True)
 
