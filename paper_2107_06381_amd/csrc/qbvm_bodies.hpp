@@ -169,6 +169,7 @@ __device__ __forceinline__ void dst_body(const DstArgs& a, long long wg, c64* ld
     i0 = (wg - o * a.tiles_per_outer) * nl;
   }
   for (int e = threadIdx.x; e < S * nc; e += blockDim.x) buf[e] = {0.0, 0.0};
+  const c64* tw = stage_twiddles(a.fft, a.tw_lds, side + 2 * S);
   __syncthreads();
   double* bp = reinterpret_cast<double*>(buf);
   const int tot = nl * m;
@@ -193,7 +194,7 @@ __device__ __forceinline__ void dst_body(const DstArgs& a, long long wg, c64* ld
   }
   __syncthreads();
   if (a.fft.kind == kBluestein) fft_bluestein_prep(buf, S, a.fft);
-  fft_run<WIDE>(buf, S, a.fft, side);
+  fft_run<WIDE>(buf, S, a.fft, side, tw);
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     int q, k;
     long long dst;
@@ -248,6 +249,7 @@ __device__ __forceinline__ void time_body(const TimeArgs& a, long long wg, c64* 
       gh[q] = 0.0;
     }
   }
+  const c64* tw = stage_twiddles(a.fft, a.tw_lds, reinterpret_cast<c64*>(gh + 2 * S));
   __syncthreads();
   // Steps (a)+(b): u_j = g_a/(d_j/tau + mu_a) + i g_b/(d_j/tau + mu_b)
   for (int e = threadIdx.x; e < S * Nt; e += blockDim.x) {
@@ -264,7 +266,7 @@ __device__ __forceinline__ void time_body(const TimeArgs& a, long long wg, c64* 
   }
   __syncthreads();
   if (a.fft.kind == kBluestein) fft_bluestein_prep(buf, S, a.fft);
-  fft_run<WIDE>(buf, S, a.fft, side);
+  fft_run<WIDE>(buf, S, a.fft, side, tw);
   // Step (c): gamma_l^{-1}/N_t * X_l; real part -> mode a, imaginary part -> mode b
   const int tot = S * a.lev_count;
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {

@@ -186,32 +186,33 @@ __device__ __forceinline__ void fft_stage(c64* __restrict__ buf, int S, int nc, 
   __syncthreads();
 }
 
+// tw: the plan's twiddle table, or a copy of it in LDS
 template <bool WIDE>
-__device__ __forceinline__ void fft_core(c64* buf, int S, const FftPlanDev& p) {
+__device__ __forceinline__ void fft_core(c64* buf, int S, const FftPlanDev& p, const c64* __restrict__ tw) {
   for (int i = 0; i < p.nstages; ++i) {
     const int R = p.st[i].radix, ns = p.st[i].ns, tws = p.st[i].twstride;
     switch (R) {
-      case 2: fft_stage<2>(buf, S, p.nc, ns, tws, p.tw); break;
-      case 3: fft_stage<3>(buf, S, p.nc, ns, tws, p.tw); break;
-      case 4: fft_stage<4>(buf, S, p.nc, ns, tws, p.tw); break;
-      case 5: fft_stage<5>(buf, S, p.nc, ns, tws, p.tw); break;
-      case 7: fft_stage<7>(buf, S, p.nc, ns, tws, p.tw); break;
-      case 8: fft_stage<8>(buf, S, p.nc, ns, tws, p.tw); break;
-      case 16: fft_stage<16>(buf, S, p.nc, ns, tws, p.tw); break;
+      case 2: fft_stage<2>(buf, S, p.nc, ns, tws, tw); break;
+      case 3: fft_stage<3>(buf, S, p.nc, ns, tws, tw); break;
+      case 4: fft_stage<4>(buf, S, p.nc, ns, tws, tw); break;
+      case 5: fft_stage<5>(buf, S, p.nc, ns, tws, tw); break;
+      case 7: fft_stage<7>(buf, S, p.nc, ns, tws, tw); break;
+      case 8: fft_stage<8>(buf, S, p.nc, ns, tws, tw); break;
+      case 16: fft_stage<16>(buf, S, p.nc, ns, tws, tw); break;
       default:
         if constexpr (WIDE) {
           switch (R) {
-            case 11: fft_stage<11>(buf, S, p.nc, ns, tws, p.tw); break;
-            case 13: fft_stage<13>(buf, S, p.nc, ns, tws, p.tw); break;
-            case 17: fft_stage<17>(buf, S, p.nc, ns, tws, p.tw); break;
-            case 19: fft_stage<19>(buf, S, p.nc, ns, tws, p.tw); break;
-            case 23: fft_stage<23>(buf, S, p.nc, ns, tws, p.tw); break;
-            case 29: fft_stage<29>(buf, S, p.nc, ns, tws, p.tw); break;
-            case 31: fft_stage<31>(buf, S, p.nc, ns, tws, p.tw); break;
-            case 37: fft_stage<37>(buf, S, p.nc, ns, tws, p.tw); break;
-            case 41: fft_stage<41>(buf, S, p.nc, ns, tws, p.tw); break;
-            case 43: fft_stage<43>(buf, S, p.nc, ns, tws, p.tw); break;
-            case 47: fft_stage<47>(buf, S, p.nc, ns, tws, p.tw); break;
+            case 11: fft_stage<11>(buf, S, p.nc, ns, tws, tw); break;
+            case 13: fft_stage<13>(buf, S, p.nc, ns, tws, tw); break;
+            case 17: fft_stage<17>(buf, S, p.nc, ns, tws, tw); break;
+            case 19: fft_stage<19>(buf, S, p.nc, ns, tws, tw); break;
+            case 23: fft_stage<23>(buf, S, p.nc, ns, tws, tw); break;
+            case 29: fft_stage<29>(buf, S, p.nc, ns, tws, tw); break;
+            case 31: fft_stage<31>(buf, S, p.nc, ns, tws, tw); break;
+            case 37: fft_stage<37>(buf, S, p.nc, ns, tws, tw); break;
+            case 41: fft_stage<41>(buf, S, p.nc, ns, tws, tw); break;
+            case 43: fft_stage<43>(buf, S, p.nc, ns, tws, tw); break;
+            case 47: fft_stage<47>(buf, S, p.nc, ns, tws, tw); break;
             default: break;
           }
         }
@@ -240,8 +241,8 @@ __device__ __forceinline__ void fft_bluestein_prep(c64* buf, int S, const FftPla
 // Run the transform on placed input (Bluestein input already pre-processed).
 // side[0..S) holds Rader's x_0; side[S..2S) receives sum_{j>=1} x_j.
 template <bool WIDE>
-__device__ __forceinline__ void fft_run(c64* buf, int S, const FftPlanDev& p, c64* side) {
-  fft_core<WIDE>(buf, S, p);
+__device__ __forceinline__ void fft_run(c64* buf, int S, const FftPlanDev& p, c64* side, const c64* tw) {
+  fft_core<WIDE>(buf, S, p, tw);
   if (p.kind == kStockham) return;
   const int tot = S * p.nc;
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
@@ -251,7 +252,20 @@ __device__ __forceinline__ void fft_run(c64* buf, int S, const FftPlanDev& p, c6
     buf[e] = cconj(cmul(x, p.kspec[k]));
   }
   __syncthreads();
-  fft_core<WIDE>(buf, S, p);
+  fft_core<WIDE>(buf, S, p, tw);
+}
+
+template <bool WIDE>
+__device__ __forceinline__ void fft_run(c64* buf, int S, const FftPlanDev& p, c64* side) {
+  fft_run<WIDE>(buf, S, p, side, p.tw);
+}
+
+// Copy of the twiddle table into LDS at dst (nc entries) when the kernel's flag asks for it;
+// returns the table the transform reads (the caller synchronises before the transform).
+__device__ __forceinline__ const c64* stage_twiddles(const FftPlanDev& p, int in_lds, c64* dst) {
+  if (!in_lds) return p.tw;
+  for (int i = threadIdx.x; i < p.nc; i += blockDim.x) dst[i] = p.tw[i];
+  return dst;
 }
 
 // Logical output X_k of signal s after fft_run.

@@ -43,6 +43,10 @@ struct Launch {
 };
 
 inline size_t lds_dst(const Geom& g) { return sizeof(c64) * ((size_t)g.S_dst * g.sfft.nc + 2 * g.S_dst); }
+// Runtime-engine kernels copy the twiddle table (nc entries) into LDS when that keeps the
+// workgroup within 80 KB, i.e. two workgroups per CU.
+constexpr size_t kTwLdsBudget = 80 * 1024;
+inline bool tw_fits_lds(size_t lds, int nc) { return lds + sizeof(c64) * (size_t)nc <= kTwLdsBudget; }
 inline size_t lds_time(const Geom& g, int lev_count) {
   const int S = g.S_time;
   return sizeof(c64) * ((size_t)S * g.tfft.nc + 2 * S + g.Nt + lev_count) + sizeof(double) * 4 * S;
@@ -94,6 +98,10 @@ inline std::vector<Launch<DstArgs>> dst_passes(const Geom& g, const double* in, 
     } else {
       a.tiles_per_outer = (inner + 2 * a.S - 1) / (2 * a.S);
       nwg = a.outer * a.tiles_per_outer;
+    }
+    if (!g.sfft.p2 && tw_fits_lds(lds, g.sfft.nc)) {
+      a.tw_lds = 1;
+      lds += sizeof(c64) * (size_t)g.sfft.nc;
     }
     v.push_back({a, nwg, lds});
     inner *= m;
@@ -231,6 +239,10 @@ inline Launch<TimeArgs> time_step(const Geom& g, SolveScalars sc, const double* 
   } else {
     t.fft.p2 = 0;  // generic kernel
     t.fft.gtA = t.fft.gtB = 0;
+    if (tw_fits_lds(lds, g.tfft.nc)) {
+      t.tw_lds = 1;
+      lds += sizeof(c64) * (size_t)g.tfft.nc;
+    }
   }
   const long long nwg = (g.nmodes + 2LL * t.S - 1) / (2LL * t.S);
   return {t, nwg, lds};

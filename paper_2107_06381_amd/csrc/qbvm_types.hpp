@@ -76,6 +76,7 @@ struct TimeArgs {
   long long pitch;   // > 0: y rows of m modes padded to this pitch (tiles never straddle rows)
   int tiles_per_row;
   long long ntiles;  // tiles of the launch (set at launch; persistent kernels stride over them)
+  int tw_lds;        // runtime engine: twiddles copied into LDS after the per-signal tables
   const c64* tabs;   // optional: [N_t] d_j/tau then [N_t] f0s/N_t gamma_l^{-1} for this solve
   const double* fgen; // general right-hand side in the sine basis, levels ystride apart (general solve)
   FftPlanDev fft;
@@ -113,6 +114,7 @@ struct DstArgs {
   long long kstride, ostride;
   int colmod, colvalid;
   TabJob tab;  // optional side work (power-of-two kernels)
+  int tw_lds;  // runtime engine: twiddles copied into LDS after the side slots
   FftPlanDev fft;
 };
 
