@@ -151,7 +151,8 @@ int qbvm_plan_get_variants(qbvm_plan_t p, int* var_rows, int* var_cols, int* var
 /* Select kernel variants by hand (an addition, for tests and tuning outside the
  * autotuner): -1 keeps the current one.  A variant must exist for the plan's
  * transform lengths (sine variants 0..7 for a power-of-two sine length, time
- * variants 0..5 for a power-of-two or Rader length and 0..1 for Good-Thomas,
+ * variants 0..5 for a power-of-two or Rader length and 0..3 for Good-Thomas (2 and 3
+ * with Rader's algorithm for the prime rows),
  * general variants 0..5 where the padded general pipeline runs), else QBVM_EINVAL and
  * nothing changes.  Shapes that use the generic kernels accept only -1. */
 int qbvm_plan_set_variants(qbvm_plan_t p, int var_rows, int var_cols, int var_time, int var_general);

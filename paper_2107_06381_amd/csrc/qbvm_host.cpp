@@ -1315,7 +1315,7 @@ extern "C" int qbvm_plan_autotune(qbvm_plan_t p, double* ms_out) {
   if ((Nt2 && p2sz::time_valid(Nt2, 0)) || gt) {
     double best = 1e30;
     int bestv = -1;
-    for (int V = 0; V < (gt ? 2 : p2sz::kTimeVariants2); ++V) {
+    for (int V = 0; V < (gt ? p2sz::kGtVariants : p2sz::kTimeVariants2); ++V) {
       if (!gt && !p2sz::time_valid(Nt2, V)) continue;
       sched::Geom G = geom(p);
       G.var_time = V;
@@ -1414,7 +1414,7 @@ extern "C" int qbvm_plan_set_variants(qbvm_plan_t p, int var_rows, int var_cols,
   const bool gt = p->tfft->dev.gtA != 0;
   auto dst_ok = [&](int V) { return V == -1 || (Ns && p->d >= 2 && p2sz::dst_valid(Ns, V)); };
   const bool time_ok = var_time == -1 || (p->d >= 2 && ((Nt2 && p2sz::time_valid(Nt2, var_time)) ||
-                                                        (gt && (var_time == 0 || var_time == 1))));
+                                                        (gt && var_time >= 0 && var_time < p2sz::kGtVariants)));
   const bool gen_ok = var_general == -1 ||
                       (p->W && sched::use_padded_general(geom(p)) && p2sz::time_general_valid(Nt2, var_general));
   if (!dst_ok(var_rows) || !dst_ok(var_cols) || !time_ok || !gen_ok)

@@ -78,13 +78,23 @@ __global__ __launch_bounds__(p2sz::time_T(V)) void k_time_p2(TimeArgs a) {
 template <int A, int B, int V, bool PAIR>
 __global__ __launch_bounds__(p2sz::gt_T(A, V), 2) void k_time_gt(TimeArgs a) {
   extern __shared__ c64 lds[];
-  time_gt_body<A, B, p2sz::gt_S(V), p2sz::gt_KC(V), PAIR>(a, blockIdx.x, lds);
+  time_gt_body<A, B, p2sz::gt_S(V), p2sz::gt_KC(V), PAIR, p2sz::gt_rader(V)>(a, blockIdx.x, lds);
+}
+
+template <int V>
+static const void* time_gt_fn_v(bool pair) {
+  return pair ? (const void*)&k_time_gt<3, 43, V, true> : (const void*)&k_time_gt<3, 43, V, false>;
 }
 
 static const void* time_gt_fn(int A, int B, int V, bool pair) {
   if (A == 3 && B == 43) {
-    if (pair) return V == 0 ? (const void*)&k_time_gt<3, 43, 0, true> : (const void*)&k_time_gt<3, 43, 1, true>;
-    return V == 0 ? (const void*)&k_time_gt<3, 43, 0, false> : (const void*)&k_time_gt<3, 43, 1, false>;
+    switch (V) {
+      case 0: return time_gt_fn_v<0>(pair);
+      case 1: return time_gt_fn_v<1>(pair);
+      case 2: return time_gt_fn_v<2>(pair);
+      case 3: return time_gt_fn_v<3>(pair);
+      default: return nullptr;
+    }
   }
   return nullptr;
 }

@@ -102,8 +102,12 @@ constexpr bool gt_supported(int A, int B) {
     if (p[0] == A && p[1] == B) return true;
   return false;
 }
+// Good-Thomas variants: 0, 1 direct 43-point rows (output chunks of 7 or 5 pairs); 2, 3 the
+// same with Rader rows
+constexpr int kGtVariants = 4;
 constexpr int gt_S(int) { return 64; }
-constexpr int gt_KC(int V) { return V == 0 ? 7 : 5; }
+constexpr int gt_KC(int V) { return V % 2 == 0 ? 7 : 5; }
+constexpr bool gt_rader(int V) { return V >= 2; }
 constexpr int gt_T(int A, int V) { return A * gt_S(V); }
 constexpr size_t gt_lds(int A, int B, int V) {
   return sizeof(c64) * ((size_t)(2 * gt_KC(V) + 1) * A * gt_S(V) + 2 * (size_t)A * B);

@@ -223,7 +223,7 @@ inline Launch<TimeArgs> time_step(const Geom& g, SolveScalars sc, const double* 
   t.tiles_per_row = 0;
   size_t lds = lds_time(g, lev_count);
   if (g.tfft.gtA && lev_first == 0 && lev_count == g.Nt) {
-    const int V = (g.var_time == 0 || g.var_time == 1) ? g.var_time : 0;
+    const int V = (g.var_time >= 0 && g.var_time < p2sz::kGtVariants) ? g.var_time : 0;
     t.var = V;
     t.S = p2sz::gt_S(V);
     t.threads = p2sz::gt_T(g.tfft.gtA, V);

@@ -243,13 +243,19 @@ static void run_time_fast(const Launch<TimeArgs>& t) {
     auto run = [&](auto v, auto pair) {
       constexpr int V = decltype(v)::value;
       run_grid(t.nwg, A.threads, t.lds, [&](long long wg, c64* l) {
-        time_gt_body<3, 43, p2sz::gt_S(V), p2sz::gt_KC(V), decltype(pair)::value>(A, wg, l);
+        time_gt_body<3, 43, p2sz::gt_S(V), p2sz::gt_KC(V), decltype(pair)::value, p2sz::gt_rader(V)>(A, wg, l);
       });
     };
-    if (A.var == 0 && A.pitch > 0) run(std::integral_constant<int, 0>{}, std::true_type{});
-    else if (A.var == 0) run(std::integral_constant<int, 0>{}, std::false_type{});
-    else if (A.pitch > 0) run(std::integral_constant<int, 1>{}, std::true_type{});
-    else run(std::integral_constant<int, 1>{}, std::false_type{});
+    auto runv = [&](auto v) {
+      if (A.pitch > 0) run(v, std::true_type{});
+      else run(v, std::false_type{});
+    };
+    switch (A.var) {
+      case 0: runv(std::integral_constant<int, 0>{}); break;
+      case 1: runv(std::integral_constant<int, 1>{}); break;
+      case 2: runv(std::integral_constant<int, 2>{}); break;
+      default: runv(std::integral_constant<int, 3>{}); break;
+    }
     return;
   }
   if (!A.fft.p2) exit(15);

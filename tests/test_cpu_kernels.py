@@ -100,7 +100,9 @@ SOLVE_KV = [(0, 4, 0, 1), (4, 1, 1, 1), (1, 3, 2, 0), (3, 0, 3, 0), (6, 5, 3, 1)
 _QUICK_SKIP = {(3, 15, 127, 1e-3, 1), (3, 31, 63, 1e-3, 0), (3, 31, 128, 1e-3, 1), (2, 255, 6, 1e-3, 0),
                (2, 63, 255, 1e-5, 1)}
 SOLVE_PARAMS = ([(c, kv) for c in SOLVE_CASES for kv in SOLVE_KV] if FULL else
-                [(c, SOLVE_KV[i % len(SOLVE_KV)]) for i, c in enumerate(c for c in SOLVE_CASES if c not in _QUICK_SKIP)])
+                [(c, SOLVE_KV[i % len(SOLVE_KV)]) for i, c in enumerate(c for c in SOLVE_CASES if c not in _QUICK_SKIP)]
+                # Good-Thomas with Rader rows (time variants 2, 3), padded and in place
+                + [((2, 63, 128, 1e-4, 0), (0, 4, 2, 1)), ((3, 7, 128, 1e-3, 0), (1, 3, 3, 0))])
 
 
 @pytest.mark.parametrize("case,kv", SOLVE_PARAMS,

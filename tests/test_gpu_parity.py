@@ -260,6 +260,32 @@ def test_general_rhs_rank_one_and_in_place(m, n):
     assert rel(fd.cpu().numpy(), y1.cpu().numpy()) < 1e-11
 
 
+@pytest.mark.parametrize("d,m", [(3, 31), (2, 127)])
+def test_good_thomas_variants(d, m):
+    """N_t = 129 = 3 * 43: the Good-Thomas time kernel's four variants (direct 43-point rows
+    or Rader's algorithm on the 42-point prime-factor DFT, two output chunkings), selected by
+    hand, against the closed form, every level."""
+    n, alpha = 128, 1e-4
+    say(f"[case] good-thomas variants d={d} m={m}")
+    g = np.random.default_rng(31).standard_normal((m,) * d)
+    yc = O.closed_form(g, d, m, n, 1.0, 0.5, alpha, O.PQ)
+    p = qbvm.Plan(d, m, n, 1.0, 0.5)
+    gd = to_dev(g)
+    ys = []
+    for V in range(4):
+        p.set_variants(time=V)
+        y = p.solve(alpha, qbvm.QBVM_PQ, gd).cpu().numpy()
+        ys.append(y)
+        assert rel(y, yc) < TOL, (V, rel(y, yc))
+        w = omega_abs(alpha, 0, 0.5 / n)
+        ok, r = level_ok(y[-1], yc[-1], yc[0], n, n + 1, w)
+        assert ok, (V, r)
+    assert rel(ys[2], ys[0]) < 1e-12 and rel(ys[3], ys[1]) < 1e-12
+    with pytest.raises(qbvm.QbvmError):
+        p.set_variants(time=4)
+    p.close()
+
+
 @pytest.mark.parametrize("d,m,n", [(2, 255, 256), (3, 63, 63)])
 def test_every_kernel_variant(d, m, n):
     """Every sine-pass, time and general-time kernel variant, selected by hand, against
