@@ -56,6 +56,14 @@ __device__ __forceinline__ double recip_nr(double x) {
   return fma(r, e, r);
 }
 
+// 1/x and 1/y for positive x, y (their product within the FP64 range) from one reciprocal:
+// r = 1/(x y) refined by two Newton steps, then 1/x = y r and 1/y = x r.
+__device__ __forceinline__ void recip2_nr(double x, double y, double& rx, double& ry) {
+  const double r = recip_nr(x * y);
+  rx = y * r;
+  ry = x * r;
+}
+
 // entries j = gid, gid + gstride, ... of a TabJob (Sections 3.1-3.3: omega from alpha,
 // then the shifts d_j and the inverse scaling gamma_l^{-1})
 __device__ __forceinline__ void tab_job_run(const TabJob& t, long long gid, long long gstride) {
@@ -335,7 +343,8 @@ __device__ __forceinline__ void time_general_body(const TimeArgs& a, long long w
     const c64 zbm = {0.5 * (zj.im - zr.im), -0.5 * (zj.re - zr.re)};  // (z - conj z')/(2i)
     const c64 z = dt[j];
     const double xa = z.re + mus[2 * s], xb = z.re + mus[2 * s + 1];
-    const double qa = recip_nr(xa * xa + z.im * z.im), qb = recip_nr(xb * xb + z.im * z.im);
+    double qa, qb;
+    recip2_nr(xa * xa + z.im * z.im, xb * xb + z.im * z.im, qa, qb);
     // w_a = za / (xa + i z.im), w_b = zbm / (xb + i z.im)
     const c64 wa = {(za.re * xa + za.im * z.im) * qa, (za.im * xa - za.re * z.im) * qa};
     const c64 wb = {(zbm.re * xb + zbm.im * z.im) * qb, (zbm.im * xb - zbm.re * z.im) * qb};

@@ -255,8 +255,9 @@ __device__ __forceinline__ void time_gt_body(const TimeArgs& a, long long wg, c6
     n = n >= N ? n - N : n;
     const c64 z = dt[n];
     const double xa = z.re + mua, xb = z.re + mub;
-    const double ia = ga * recip_nr(xa * xa + z.im * z.im);
-    const double ib = gb * recip_nr(xb * xb + z.im * z.im);
+    double qa, qb;
+    recip2_nr(xa * xa + z.im * z.im, xb * xb + z.im * z.im, qa, qb);
+    const double ia = ga * qa, ib = gb * qb;
     v[b] = {ia * xa + ib * z.im, ib * xb - ia * z.im};
   }
   // length-B DFT over b: Rader's algorithm in registers, or the symmetric form

@@ -476,8 +476,9 @@ __device__ __forceinline__ void time_p2_body(const TimeArgs& a, long long first,
     auto input = [&](int j, int) -> c64 {
       const c64 z = sh.dt[j];
       const double xa = z.re + mua, xb = z.re + mub;
-      const double ia = ga * recip_nr(xa * xa + z.im * z.im);
-      const double ib = gb * recip_nr(xb * xb + z.im * z.im);
+      double qa, qb;
+      recip2_nr(xa * xa + z.im * z.im, xb * xb + z.im * z.im, qa, qb);
+      const double ia = ga * qa, ib = gb * qb;
       return {ia * xa + ib * z.im, ib * xb - ia * z.im};
     };
     auto emit = [&](int l, c64 X, int) { tile.store(a, l, cmul(sh.gi[l], X)); };
@@ -567,7 +568,8 @@ __device__ __forceinline__ void time_general_p2_body(const TimeArgs& a, long lon
     const c64 zb = {0.5 * (zj.im - zr.im), -0.5 * (zj.re - zr.re)};
     const c64 z = sh.dt[j];
     const double xa = z.re + mua, xb = z.re + mub;
-    const double qa = recip_nr(xa * xa + z.im * z.im), qb = recip_nr(xb * xb + z.im * z.im);
+    double qa, qb;
+    recip2_nr(xa * xa + z.im * z.im, xb * xb + z.im * z.im, qa, qb);
     const c64 wa = {(za.re * xa + za.im * z.im) * qa, (za.im * xa - za.re * z.im) * qa};
     const c64 wb = {(zb.re * xb + zb.im * z.im) * qb, (zb.im * xb - zb.re * z.im) * qb};
     return {wa.re - wb.im, wa.im + wb.re};
