@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqbvm.so")
-SOURCES = ["qbvm_kernels.hip", "qbvm_plane.hip", "qbvm_krylov.hip", "qbvm_host.cpp"]
+SOURCES = ["qbvm_kernels.hip", "qbvm_plane.hip", "qbvm_krylov.hip", "qbvm_blue.hip", "qbvm_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

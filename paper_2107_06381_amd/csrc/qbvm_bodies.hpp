@@ -180,50 +180,77 @@ __device__ __forceinline__ void dst_body(const DstArgs& a, long long wg, c64* ld
   const c64* tw = stage_twiddles(a.fft, a.tw_lds, side + 2 * S);
   __syncthreads();
   double* bp = reinterpret_cast<double*>(buf);
-  const int tot = nl * m;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    int q, k;
-    double x = 0.0;
-    if (contig) {
-      q = e / m;
-      k = e - q * m;
-      const long long line = i0 + q;
-      if (line < a.outer) x = a.in[line * a.in_pitch + k];
-    } else {
-      k = e / nl;
-      q = e - k * nl;
-      const long long i = i0 + q;
-      if (dst_col_ok(a, i)) x = a.in[o * a.ostride + k * a.kstride + i];
+  const int tot = nl * m, T = blockDim.x;
+  // element e: contiguous lines (q, k) = (e / m, e mod m); columns (k, q) = (e / nl, e mod nl)
+  LaneWalk w(contig ? m : nl);
+  for (int e0 = threadIdx.x; e0 < tot; e0 += kBatch * T) {
+    double xv[kBatch];
+    int qv[kBatch], p1v[kBatch], p2v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      // indices past the data are clamped to the last valid element, so every load of
+      // the batch is unconditional; the value is then replaced by 0
+      const int q = contig ? w.j : w.s, k = min(contig ? w.s : w.j, m - 1);
+      const bool live = e0 + u * T < tot;
+      double x;
+      if (contig) {
+        const long long line = i0 + q;
+        x = a.in[min(line, a.outer - 1) * a.in_pitch + k];
+        if (!(live && line < a.outer)) x = 0.0;
+      } else {
+        const long long i = i0 + q;
+        x = a.in[o * a.ostride + k * a.kstride + min(i, a.inner - 1)];
+        if (!(live && dst_col_ok(a, i))) x = 0.0;
+      }
+      qv[u] = q;
+      p1v[u] = fft_in_pos(a.fft, k + 1);
+      p2v[u] = fft_in_pos(a.fft, N - 1 - k);
+      xv[u] = x;
+      w.next();
     }
-    const int s = q >> 1, comp = q & 1;
-    const int p1 = fft_in_pos(a.fft, k + 1), p2 = fft_in_pos(a.fft, N - 1 - k);
-    bp[2 * ((size_t)p1 * S + s) + comp] = x;
-    bp[2 * ((size_t)p2 * S + s) + comp] = -x;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (e0 + u * T < tot) {
+        const int s = qv[u] >> 1, comp = qv[u] & 1;
+        bp[2 * ((size_t)p1v[u] * S + s) + comp] = xv[u];
+        bp[2 * ((size_t)p2v[u] * S + s) + comp] = -xv[u];
+      }
+    }
   }
   __syncthreads();
   if (a.fft.kind == kBluestein) fft_bluestein_prep(buf, S, a.fft);
   fft_run<WIDE>(buf, S, a.fft, side, tw);
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    int q, k;
-    long long dst;
-    bool ok;
-    if (contig) {
-      q = e / m;
-      k = e - q * m;
-      const long long line = i0 + q;
-      ok = line < a.outer;
-      dst = line * a.out_pitch + k;
-    } else {
-      k = e / nl;
-      q = e - k * nl;
-      const long long i = i0 + q;
-      ok = dst_col_ok(a, i);
-      dst = o * a.ostride + k * a.kstride + i;
+  LaneWalk wo(contig ? m : nl);
+  for (int e0 = threadIdx.x; e0 < tot; e0 += kBatch * T) {
+    FftOutAt at[kBatch];
+    int qv[kBatch], kv[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      qv[u] = contig ? wo.j : wo.s;
+      kv[u] = contig ? wo.s : wo.j;
+      at[u] = fft_out_at(a.fft, min(kv[u], m - 1) + 1);
+      wo.next();
     }
-    const int s = q >> 1, comp = q & 1;
-    const c64 V = fft_out(buf, S, a.fft, s, k + 1, side);
-    const double val = comp == 0 ? -V.im : V.re;
-    if (ok) a.out[dst] = val * a.scale;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (e0 + u * T >= tot) continue;
+      const int q = qv[u], k = kv[u];
+      long long dst;
+      bool ok;
+      if (contig) {
+        const long long line = i0 + q;
+        ok = line < a.outer;
+        dst = line * a.out_pitch + k;
+      } else {
+        const long long i = i0 + q;
+        ok = dst_col_ok(a, i);
+        dst = o * a.ostride + k * a.kstride + i;
+      }
+      const int s = q >> 1, comp = q & 1;
+      const c64 V = fft_out(buf, S, a.fft, s, at[u], side);
+      const double val = comp == 0 ? -V.im : V.re;
+      if (ok) a.out[dst] = val * a.scale;
+    }
   }
 }
 
@@ -260,31 +287,57 @@ __device__ __forceinline__ void time_body(const TimeArgs& a, long long wg, c64* 
   const c64* tw = stage_twiddles(a.fft, a.tw_lds, reinterpret_cast<c64*>(gh + 2 * S));
   __syncthreads();
   // Steps (a)+(b): u_j = g_a/(d_j/tau + mu_a) + i g_b/(d_j/tau + mu_b)
-  for (int e = threadIdx.x; e < S * Nt; e += blockDim.x) {
-    const int j = e / S, s = e - j * S;
-    const c64 z = dt[j];
-    const double xa = z.re + mus[2 * s], xb = z.re + mus[2 * s + 1];
-    const double ia = gh[2 * s] / (xa * xa + z.im * z.im);
-    const double ib = gh[2 * s + 1] / (xb * xb + z.im * z.im);
-    // A = ia (xa - i z.im), B = ib (xb - i z.im); u = A + i B
-    const c64 u = {ia * xa + ib * z.im, ib * xb - ia * z.im};
-    const int pos = fft_in_pos(a.fft, j);
-    if (pos < 0) side[s] = u;
-    else buf[(size_t)pos * S + s] = u;
+  const int T = blockDim.x;
+  LaneWalk w(S);
+  for (int e0 = threadIdx.x; e0 < S * Nt; e0 += kBatch * T) {
+    int pv[kBatch], jv[kBatch], sv[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      jv[u] = w.j;
+      sv[u] = w.s;
+      pv[u] = fft_in_pos(a.fft, min(w.j, Nt - 1));
+      w.next();
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (e0 + u * T >= S * Nt) continue;
+      const int j = jv[u], s = sv[u];
+      const c64 z = dt[j];
+      const double xa = z.re + mus[2 * s], xb = z.re + mus[2 * s + 1];
+      const double ia = gh[2 * s] / (xa * xa + z.im * z.im);
+      const double ib = gh[2 * s + 1] / (xb * xb + z.im * z.im);
+      // A = ia (xa - i z.im), B = ib (xb - i z.im); u = A + i B
+      const c64 uu = {ia * xa + ib * z.im, ib * xb - ia * z.im};
+      if (pv[u] < 0) side[s] = uu;
+      else buf[(size_t)pv[u] * S + s] = uu;
+    }
   }
   __syncthreads();
   if (a.fft.kind == kBluestein) fft_bluestein_prep(buf, S, a.fft);
   fft_run<WIDE>(buf, S, a.fft, side, tw);
   // Step (c): gamma_l^{-1}/N_t * X_l; real part -> mode a, imaginary part -> mode b
   const int tot = S * a.lev_count;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int li = e / S, s = e - li * S;
-    const c64 X = fft_out(buf, S, a.fft, s, a.lev_first + li, side);
-    const c64 v = cmul(gi[li], X);
-    const long long ka = k0 + 2 * s;
-    double* yl = a.y + (long long)(a.lev_dst0 + li) * a.ystride;
-    if (ka < a.nmodes) yl[ka] = v.re;
-    if (ka + 1 < a.nmodes) yl[ka + 1] = v.im;
+  LaneWalk wo(S);
+  for (int e0 = threadIdx.x; e0 < tot; e0 += kBatch * T) {
+    FftOutAt at[kBatch];
+    int lv[kBatch], sv[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      lv[u] = wo.j;
+      sv[u] = wo.s;
+      at[u] = fft_out_at(a.fft, a.lev_first + min(wo.j, a.lev_count - 1));
+      wo.next();
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (e0 + u * T >= tot) continue;
+      const int li = lv[u], s = sv[u];
+      const c64 v = cmul(gi[li], fft_out(buf, S, a.fft, s, at[u], side));
+      const long long ka = k0 + 2 * s;
+      double* yl = a.y + (long long)(a.lev_dst0 + li) * a.ystride;
+      if (ka < a.nmodes) yl[ka] = v.re;
+      if (ka + 1 < a.nmodes) yl[ka + 1] = v.im;
+    }
   }
 }
 

@@ -31,6 +31,32 @@ __device__ __forceinline__ c64 cconj(c64 a) { return {a.re, -a.im}; }
 __device__ __forceinline__ c64 cscale(c64 a, double s) { return {a.re * s, a.im * s}; }
 __device__ __forceinline__ c64 mul_negi(c64 a) { return {a.im, -a.re}; }  // a * (-i)
 
+// Element loops of the workgroup (e = threadIdx.x + i * blockDim.x) run in batches of
+// kBatch: a batch issues all of its global loads before it uses any of them, so it
+// waits for memory once instead of once per element.
+constexpr int kBatch = 8;
+
+// (j, s) = (e / S, e mod S) for e = threadIdx.x + i * blockDim.x, i = 0, 1, ...: one
+// division at the start, then an add with carry per step.
+struct LaneWalk {
+  int j, s, dj, ds, S;
+  __device__ __forceinline__ explicit LaneWalk(int S_) : S(S_) {
+    const int T = (int)blockDim.x, t = (int)threadIdx.x;
+    j = t / S;
+    s = t - j * S;
+    dj = T / S;
+    ds = T - dj * S;
+  }
+  __device__ __forceinline__ void next() {
+    s += ds;
+    j += dj;
+    if (s >= S) {
+      s -= S;
+      ++j;
+    }
+  }
+};
+
 // ---------------------------------------------------------------- butterflies
 __device__ __forceinline__ void bfly4(c64& x0, c64& x1, c64& x2, c64& x3) {
   const c64 t0 = cadd(x0, x2), t1 = csub(x0, x2);
@@ -148,37 +174,39 @@ template <int R>
 __device__ __forceinline__ void fft_stage(c64* __restrict__ buf, int S, int nc, int ns, int twstride,
                                           const c64* __restrict__ tw) {
   constexpr int MB = (kElemsPerThread + R - 1) / R;
-  const int T = blockDim.x;
   const int q = nc / R;
-  const int nbf = S * q;
+  // butterfly b = threadIdx.x + i T: signal s = b mod S, index j = b / S (valid for j < q),
+  // k = j mod ns; all three advance without a division per butterfly
+  LaneWalk w(S);
+  const int dk = w.dj % ns;
+  int k = w.j % ns;
   c64 v[MB][R];
-  int jj[MB], ss[MB];
+  int jj[MB], ss[MB], kk[MB];
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
-    const int b = threadIdx.x + i * T;
-    jj[i] = 0;
-    ss[i] = 0;
-    if (b < nbf) {
-      const int s = b % S, j = b / S;
-      jj[i] = j;
-      ss[i] = s;
+    jj[i] = w.j;
+    ss[i] = w.s;
+    kk[i] = k;
+    if (w.j < q) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * q) * S + s];
+      for (int r = 0; r < R; ++r) v[i][r] = buf[(w.j + r * q) * S + w.s];
     }
+    const int j_old = w.j;
+    w.next();
+    k += dk + (w.j - j_old - w.dj);  // + carry
+    if (k >= ns) k -= ns;
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
-    const int b = threadIdx.x + i * T;
-    if (b < nbf) {
-      const int j = jj[i], s = ss[i];
-      const int k = j % ns;
-      if (k != 0) {
+    if (jj[i] < q) {
+      const int j = jj[i], s = ss[i], kr = kk[i];
+      if (kr != 0) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[k * r * twstride]);
+        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[kr * r * twstride]);
       }
       Bfly<R>::run(v[i]);
-      const int base = (j - k) * R + k;
+      const int base = (j - kr) * R + kr;
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[(base + r * ns) * S + s] = v[i][r];
     }
@@ -229,11 +257,22 @@ __device__ __forceinline__ int fft_in_pos(const FftPlanDev& p, int j) {
 
 // Bluestein pre-processing after raw placement: x_j * conj(w_j) for j < n, 0 beyond.
 __device__ __forceinline__ void fft_bluestein_prep(c64* buf, int S, const FftPlanDev& p) {
-  const int tot = S * p.nc;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int j = e / S;
-    if (j < p.n) buf[e] = cmul(buf[e], cconj(p.chirp[j]));
-    else buf[e] = {0.0, 0.0};
+  const int tot = S * p.nc, T = blockDim.x;
+  LaneWalk w(S);
+  for (int e0 = threadIdx.x; e0 < tot; e0 += kBatch * T) {
+    c64 cw[kBatch];
+    int jv[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      jv[u] = w.j;
+      cw[u] = p.chirp[min(w.j, p.n - 1)];  // clamped: the loads need no branch
+      w.next();
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * T;
+      if (e < tot) buf[e] = jv[u] < p.n ? cmul(buf[e], cconj(cw[u])) : c64{0.0, 0.0};
+    }
   }
   __syncthreads();
 }
@@ -244,12 +283,24 @@ template <bool WIDE>
 __device__ __forceinline__ void fft_run(c64* buf, int S, const FftPlanDev& p, c64* side, const c64* tw) {
   fft_core<WIDE>(buf, S, p, tw);
   if (p.kind == kStockham) return;
-  const int tot = S * p.nc;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int k = e / S;
-    const c64 x = buf[e];
-    if (p.kind == kRader && k == 0) side[S + e] = x;  // e == s when k == 0
-    buf[e] = cconj(cmul(x, p.kspec[k]));
+  const int tot = S * p.nc, T = blockDim.x;
+  LaneWalk w(S);
+  for (int e0 = threadIdx.x; e0 < tot; e0 += kBatch * T) {
+    c64 ks[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      ks[u] = p.kspec[min(w.j, p.nc - 1)];
+      w.next();
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * T;
+      if (e < tot) {
+        const c64 x = buf[e];
+        if (p.kind == kRader && e < S) side[S + e] = x;  // position 0: e == s
+        buf[e] = cconj(cmul(x, ks[u]));
+      }
+    }
   }
   __syncthreads();
   fft_core<WIDE>(buf, S, p, tw);
@@ -264,20 +315,47 @@ __device__ __forceinline__ void fft_run(c64* buf, int S, const FftPlanDev& p, c6
 // returns the table the transform reads (the caller synchronises before the transform).
 __device__ __forceinline__ const c64* stage_twiddles(const FftPlanDev& p, int in_lds, c64* dst) {
   if (!in_lds) return p.tw;
-  for (int i = threadIdx.x; i < p.nc; i += blockDim.x) dst[i] = p.tw[i];
+  const int T = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < p.nc; i0 += kBatch * T) {
+    c64 v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) v[u] = p.tw[min(i0 + u * T, p.nc - 1)];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (i0 + u * T < p.nc) dst[i0 + u * T] = v[u];
+  }
   return dst;
+}
+
+// What the read of logical output k needs from the plan's global tables (Rader's
+// output position, Bluestein's chirp), fetched ahead of the LDS read by batched loops.
+struct FftOutAt {
+  int pos;  // core position; -1: Rader's X_0
+  c64 w;    // Bluestein: conj(chirp_k)
+};
+__device__ __forceinline__ FftOutAt fft_out_at(const FftPlanDev& p, int k) {
+  FftOutAt o{k, {1.0, 0.0}};
+  if (p.kind == kRader) o.pos = k == 0 ? -1 : p.rout[k];
+  else if (p.kind == kBluestein) o.w = cconj(p.chirp[k]);
+  return o;
+}
+
+// Logical output of signal s at o after fft_run.
+__device__ __forceinline__ c64 fft_out(const c64* buf, int S, const FftPlanDev& p, int s, const FftOutAt& o,
+                                       const c64* side) {
+  if (p.kind == kStockham) return buf[o.pos * S + s];
+  if (p.kind == kRader) {
+    const c64 x0 = side[s];
+    if (o.pos < 0) return cadd(x0, side[S + s]);
+    return cadd(x0, cconj(buf[o.pos * S + s]));
+  }
+  return cmul(o.w, cconj(buf[o.pos * S + s]));
 }
 
 // Logical output X_k of signal s after fft_run.
 __device__ __forceinline__ c64 fft_out(const c64* buf, int S, const FftPlanDev& p, int s, int k,
                                        const c64* side) {
-  if (p.kind == kStockham) return buf[k * S + s];
-  if (p.kind == kRader) {
-    const c64 x0 = side[s];
-    if (k == 0) return cadd(x0, side[S + s]);
-    return cadd(x0, cconj(buf[p.rout[k] * S + s]));
-  }
-  return cmul(cconj(p.chirp[k]), cconj(buf[k * S + s]));
+  return fft_out(buf, S, p, s, fft_out_at(p, k), side);
 }
 
 }  // namespace qbvm

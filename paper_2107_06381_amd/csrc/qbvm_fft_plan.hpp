@@ -137,15 +137,22 @@ inline void fill_stages(FftPlanDev& d, int nc) {
 }
 
 // Tables of a forward DFT of logical length n; returns false (with a message) if
-// the core transform would exceed what one workgroup handles.
-inline bool build_tables(int n, HostFft& t, std::string& err) {
+// the core transform would exceed what one workgroup handles.  pow2_blue: a length
+// that takes Bluestein's path gets a power-of-two core (up to 4096), for the
+// compile-time Bluestein kernels, instead of the shortest 7-smooth one.  nout: only
+// outputs 0..nout-1 are wanted (a sine transform needs the first half); Bluestein's
+// cyclic convolution then needs a core of n + nout - 1 points, not 2n - 1.
+inline bool build_tables(int n, HostFft& t, std::string& err, bool pow2_blue = false, int nout = 0) {
   FftPlanDev& d = t.dev;
   d.n = n;
+  if (nout <= 0 || nout > n) nout = n;
+  d.nout = nout;
   // Prefer cores whose radices are all <= 7 (the narrow kernels keep a butterfly in
   // registers without spilling): Stockham, Rader on n - 1, else Bluestein if its core
   // fits; only lengths beyond that use the wide kernels (odd radices up to 47).
   int nc;
-  int blue = 2 * n - 1;
+  const int need = n + nout - 1;  // Bluestein's convolution length
+  int blue = need;
   while (!smooth(blue, kMaxOddRadixNarrow)) ++blue;
   if (smooth(n, kMaxOddRadixNarrow)) {
     d.kind = kStockham;
@@ -156,6 +163,11 @@ inline bool build_tables(int n, HostFft& t, std::string& err) {
   } else if (blue <= kMaxCore) {
     d.kind = kBluestein;
     nc = blue;
+    if (pow2_blue) {
+      int P = 64;
+      while (P < need) P *= 2;
+      if (P <= kMaxCore) nc = P;
+    }
   } else if (smooth(n, kMaxOddRadixWide)) {
     d.kind = kStockham;
     nc = n;
@@ -208,18 +220,22 @@ inline bool build_tables(int n, HostFft& t, std::string& err) {
     }
     t.kspec = dft_over_len(bb);
   } else if (d.kind == kBluestein) {
+    // kernel b_t = w_t at the offsets t = k - j of the wanted outputs k < nout and the
+    // inputs j < n: t in [0, nout) at positions t, t in [1, n) at nc - t (w_t = w_{-t});
+    // nc >= n + nout - 1 keeps the two ranges apart
     t.chirp.resize(n);
     std::vector<std::complex<long double>> bb(nc, 0);
     for (long long k = 0; k < n; ++k) {
       const long long e2 = (k * k) % (2LL * n);
       const std::complex<long double> w = unit_root(e2, 2LL * n, +1);  // exp(i pi k^2/n)
       t.chirp[k] = {(double)w.real(), (double)w.imag()};
-      bb[k] = w;
+      if (k < nout) bb[k] = w;
       if (k > 0) bb[nc - k] = w;
     }
     t.kspec = dft_over_len(bb);
   }
   d.p2 = (d.kind != kBluestein && is_p2_core(nc)) ? nc : 0;
+  d.bp2 = (d.kind == kBluestein && is_p2_core(nc) && nc >= need) ? nc : 0;
   d.gtA = d.gtB = 0;
   for (const auto& pr : p2sz::kGtPairs)
     if (pr[0] * pr[1] == n) {

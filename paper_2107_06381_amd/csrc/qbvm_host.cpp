@@ -64,10 +64,10 @@ hipError_t upload(const std::vector<T>& v, const T** dst, std::vector<void*>& al
 }
 
 // Build the device tables of a forward DFT of logical length n.
-int build_fft(int n, FftTables& t) {
+int build_fft(int n, FftTables& t, bool sine) {
   plan::HostFft h;
   std::string err;
-  if (!plan::build_tables(n, h, err)) return set_error(QBVM_EUNSUPPORTED, err);
+  if (!plan::build_tables(n, h, err, sine, sine ? n / 2 : 0)) return set_error(QBVM_EUNSUPPORTED, err);
   t.dev = h.dev;
   FftPlanDev& d = t.dev;
   HIP_TRY(upload(h.tw, &d.tw, t.allocs));
@@ -81,12 +81,15 @@ int build_fft(int n, FftTables& t) {
 }
 
 std::mutex g_mu;
-std::map<std::pair<int, int>, std::unique_ptr<FftTables>> g_fft_cache;  // (device, n)
+std::map<std::tuple<int, int, bool>, std::unique_ptr<FftTables>> g_fft_cache;  // (device, n, sine)
 // tuned variants: (device, role 0 rows / 1 cols / 2 time, N) -> variant
 std::map<std::tuple<int, int, int>, int> g_tuned;
 std::map<int, bool> g_roots_ready;
 
-int get_fft(int device, int n, const FftTables** out) {
+// sine: tables of a sine transform's length-n DFT (n = 2(m+1)), of which only outputs
+// 0..n/2-1 are used; a Bluestein length gets a power-of-two core for the compile-time
+// Bluestein sine passes
+int get_fft(int device, int n, const FftTables** out, bool sine = false) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_roots_ready[device]) {
     const std::vector<c64> roots = plan::radix_roots();
@@ -94,11 +97,11 @@ int get_fft(int device, int n, const FftTables** out) {
     HIP_TRY(hipGetLastError());
     g_roots_ready[device] = true;
   }
-  auto key = std::make_pair(device, n);
+  auto key = std::make_tuple(device, n, sine);
   auto it = g_fft_cache.find(key);
   if (it == g_fft_cache.end()) {
     auto t = std::make_unique<FftTables>();
-    const int rc = build_fft(n, *t);
+    const int rc = build_fft(n, *t, sine);
     if (rc != QBVM_OK) {
       for (void* p : t->allocs) (void)hipFree(p);
       return rc;
@@ -383,7 +386,7 @@ int create_plan(qbvm_plan_s** out, const qbvm_grid* grid, hipStream_t stream) {
   for (int i = 0; i < p->d; ++i) p->nmodes *= p->m;
   rc = get_fft(p->device, p->Nt, &p->tfft);
   if (rc) return rc;
-  rc = get_fft(p->device, 2 * (p->m + 1), &p->sfft);
+  rc = get_fft(p->device, 2 * (p->m + 1), &p->sfft, true);
   if (rc == QBVM_EUNSUPPORTED && p->d == 1) {
     // the 1D solve never needs the sine transform (Step (b) is tridiagonal); only the
     // calls that work in the sine basis are refused on this plan

@@ -35,6 +35,9 @@ struct Batch1dArgs {
 hipError_t launch_krylov(const KrylovArgs& a, int step, hipStream_t s);
 hipError_t launch_kry_time(const KryTimeArgs& a, long long nwg, size_t lds, hipStream_t s);
 
+// ---- Bluestein sine passes on a power-of-two core (qbvm_blue.hip) ----------
+const void* dst_blue_fn(int P);  // kernel of core length P (64 .. 4096), else null
+
 // ---- launch wrappers (defined in qbvm_kernels.hip) ------------------------
 void upload_radix_roots(const c64* roots, int count);  // constant-memory roots per device
 hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, hipStream_t s,

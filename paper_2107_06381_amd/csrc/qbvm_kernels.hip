@@ -794,6 +794,9 @@ hipError_t launch_dst(const DstArgs& a, long long nwg, int threads, size_t lds, 
     if (!f) return hipErrorInvalidValue;
     allow_big_lds(f);
     nwg = persistent_grid(f, threads, lds, nwg);
+  } else if (a.fft.bp2) {
+    f = dst_blue_fn(a.fft.bp2);
+    if (!f || threads != p2sz::blue_T(a.fft.bp2) || a.S != p2sz::blue_S(a.fft.bp2)) return hipErrorInvalidValue;
   }
   return enqueue1(f, dim3((unsigned)nwg), dim3(threads), lds, s, a, nc);
 }

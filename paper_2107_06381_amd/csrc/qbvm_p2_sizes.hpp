@@ -138,5 +138,19 @@ constexpr bool plane_valid(int N, int V) {
   return N == 256 && V >= 0 && V < kPlaneVariants && plane_lds(N, V) <= 160 * 1024;
 }
 
+// Bluestein sine pass on a power-of-two core of P points (64 .. 4096, P >= 3N/2 - 1 for the
+// sine length N): E = 16 values per lane, 128 lanes (256 for P = 4096), S = T E / P
+// signals (2S lines) per workgroup.  LDS: the exchange buffer ([signal][position],
+// XOR-mapped), then for P <= 1024 the twiddle table; the staged input and output lines
+// (2S m doubles, m < P/3) reuse the exchange buffer.
+constexpr int kBlueE = 16;
+constexpr int blue_T(int P) { return P >= 4096 ? 256 : 128; }
+constexpr int blue_S(int P) { return blue_T(P) * kBlueE / P; }
+constexpr int blue_tw_mode(int P) { return P <= 1024 ? 1 : 0; }
+constexpr size_t blue_lds(int P) {
+  return sizeof(c64) * ((size_t)P * blue_S(P) + (blue_tw_mode(P) == 1 ? (size_t)P : 0));
+}
+constexpr bool blue_valid(int P) { return P >= 64 && P <= 4096 && (P & (P - 1)) == 0; }
+
 }  // namespace p2sz
 }  // namespace qbvm

@@ -90,6 +90,10 @@ inline std::vector<Launch<DstArgs>> dst_passes(const Geom& g, const double* in, 
       a.S = p2sz::dst_S(N, V);
       a.threads = p2sz::dst_T(N, V);
       lds = p2sz::dst_lds(N, V, inner > 1);
+    } else if (g.sfft.bp2) {  // Bluestein on the compile-time engine
+      a.S = p2sz::blue_S(g.sfft.bp2);
+      a.threads = p2sz::blue_T(g.sfft.bp2);
+      lds = p2sz::blue_lds(g.sfft.bp2);
     }
     long long nwg;
     if (inner == 1) {
@@ -99,7 +103,7 @@ inline std::vector<Launch<DstArgs>> dst_passes(const Geom& g, const double* in, 
       a.tiles_per_outer = (inner + 2 * a.S - 1) / (2 * a.S);
       nwg = a.outer * a.tiles_per_outer;
     }
-    if (!g.sfft.p2 && tw_fits_lds(lds, g.sfft.nc)) {
+    if (!g.sfft.p2 && !g.sfft.bp2 && tw_fits_lds(lds, g.sfft.nc)) {
       a.tw_lds = 1;
       lds += sizeof(c64) * (size_t)g.sfft.nc;
     }

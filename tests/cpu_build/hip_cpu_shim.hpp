@@ -30,6 +30,9 @@ inline void sincospi(double x, double* s, double* c) {
   *c = (double)cosl(a);
 }
 inline double exp10(double x) { return std::pow(10.0, x); }
+// HIP's integer min of device code
+inline int min(int a, int b) { return b < a ? b : a; }
+inline long long min(long long a, long long b) { return b < a ? b : a; }
 // the hardware reciprocal estimate, exact here (the bodies refine it by Newton steps)
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))
 // every lane of the emulated wave holds the same value where the bodies use this

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../paper_2107_06381_amd/csrc/qbvm_bodies_p2.hpp"
+#include "../../paper_2107_06381_amd/csrc/qbvm_bodies_blue.hpp"
 #include "../../paper_2107_06381_amd/csrc/qbvm_bodies_gt.hpp"
 #include "../../paper_2107_06381_amd/csrc/qbvm_bodies_krylov.hpp"
 #include "../../paper_2107_06381_amd/csrc/qbvm_fft_plan.hpp"
@@ -61,10 +62,11 @@ struct Tables {
   FftPlanDev dev;
 };
 
-static Tables make_tables(int n) {
+// sine: the tables of a sine transform (outputs 0..n/2-1, power-of-two Bluestein core)
+static Tables make_tables(int n, bool sine = false) {
   Tables t;
   std::string err;
-  if (!plan::build_tables(n, t.h, err)) {
+  if (!plan::build_tables(n, t.h, err, sine, sine ? n / 2 : 0)) {
     fprintf(stderr, "plan failed: %s\n", err.c_str());
     exit(3);
   }
@@ -295,8 +297,19 @@ static void general_p2_n(const Launch<TimeArgs>& t) {
   }
 }
 
+template <int P>
+static void dst_blue_n(const Launch<DstArgs>& Lz) {
+  const DstArgs& A = Lz.args;
+  if (A.threads != p2sz::blue_T(P) || A.S != p2sz::blue_S(P) || Lz.lds != p2sz::blue_lds(P)) exit(21);
+  run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_blue_body<P>(A, wg, l); });
+}
+
 static void run_dst_generic(const Launch<DstArgs>& Lz) {
   const DstArgs& A = Lz.args;
+  if (A.fft.bp2) {
+    P2_SWITCH(A.fft.bp2, dst_blue_n, Lz)
+    return;
+  }
   if (A.fft.wide) run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_body<true>(A, wg, l); });
   else run_grid(Lz.nwg, A.threads, Lz.lds, [&](long long wg, c64* l) { dst_body<false>(A, wg, l); });
 }
@@ -313,6 +326,8 @@ static void run_dst(const sched::Geom& g, const double* in, double* out, long lo
     const int T = A.threads;
     if (A.fft.p2) {
       P2_SWITCH(A.fft.p2, dst_p2_n, Lz)
+    } else if (A.fft.bp2) {
+      P2_SWITCH(A.fft.bp2, dst_blue_n, Lz)
     } else if (A.fft.wide) {
       run_grid(Lz.nwg, T, Lz.lds, [&](long long wg, c64* l) { dst_body<true>(A, wg, l); });
     } else {
@@ -343,7 +358,7 @@ int main(int argc, char** argv) {
   if (cmd == "dst" && (argc == 7 || argc == 10)) {
     const int d = atoi(argv[2]), m = atoi(argv[3]);
     const long long batch = atoll(argv[4]);
-    Tables tt = make_tables(2), st = make_tables(2 * (m + 1));
+    Tables tt = make_tables(2), st = make_tables(2 * (m + 1), true);
     std::vector<double> mu(m, 0.0);
     sched::Geom g = geom(d, m, 1, 1.0, 1.0, tt, st, mu);
     bool input = batch == 1;
@@ -370,7 +385,7 @@ int main(int argc, char** argv) {
     const int variant = atoi(argv[8]);
     const bool want_pad = argc == 13 && atoi(argv[11]) != 0;
     const int var_gen = argc == 13 ? atoi(argv[12]) : 0;
-    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1));
+    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1), true);
     const double h = L / (m + 1);
     std::vector<double> mu(m);
     for (int k = 1; k <= m; ++k) {
@@ -431,7 +446,7 @@ int main(int argc, char** argv) {
     const int m = atoi(argv[2]), n = atoi(argv[3]);
     const double L = atof(argv[4]), T = atof(argv[5]), alpha = atof(argv[6]);
     const int variant = atoi(argv[7]), level = atoi(argv[11]);
-    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1));
+    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1), true);
     const double h = L / (m + 1);
     std::vector<double> mu(m, 0.0);
     sched::Geom g = geom(1, m, n, L, T, tt, st, mu);
@@ -485,7 +500,7 @@ int main(int argc, char** argv) {
     const double tol = atof(argv[14]);
     const int maxit = atoi(argv[15]);
     if (d != 2 && d != 3) return 8;
-    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1));
+    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1), true);
     const double h = L / (m + 1);
     std::vector<double> mu(m);
     for (int k = 1; k <= m; ++k) {
@@ -612,7 +627,7 @@ int main(int argc, char** argv) {
     const int d = atoi(argv[2]), m = atoi(argv[3]), n = atoi(argv[4]);
     const double L = atof(argv[5]), T = atof(argv[6]), alpha = atof(argv[7]);
     const int variant = atoi(argv[8]);
-    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1));
+    Tables tt = make_tables(n + 1), st = make_tables(2 * (m + 1), true);
     const double h = L / (m + 1);
     std::vector<double> mu(m);
     for (int k = 1; k <= m; ++k) {

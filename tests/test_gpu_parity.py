@@ -368,11 +368,12 @@ def test_operator_1d_vs_oracle(m, n, alpha, variant, adv):
 
 
 def test_1d_plan_without_sine_transform():
-    """1D m = 1251: the sine length 2(m+1) = 2504 = 8 * 313 needs a Bluestein core above
-    4096 points.  The plan still solves (tridiagonal path, every output mode); the calls
-    that work in the sine basis are refused."""
+    """1D m = 1400: the sine length 2(m+1) = 2802 = 2 * 3 * 467 needs a Bluestein core of
+    2802 + 1401 - 1 = 4202 > 4096 points even for the first half of its outputs.  The plan
+    still solves (tridiagonal path, every output mode); the calls that work in the sine
+    basis are refused."""
     say("[case] 1d without sine transform")
-    m, n, alpha = 1251, 106, 1e-4
+    m, n, alpha = 1400, 106, 1e-4
     g = np.random.default_rng(12).standard_normal(m)
     p = qbvm.Plan(1, m, n, 1.0, 0.8)
     gd = to_dev(g)
@@ -386,6 +387,22 @@ def test_1d_plan_without_sine_transform():
         with pytest.raises(qbvm.QbvmError) as ei:
             call()
         assert ei.value.code == -5
+    p.close()
+
+
+@pytest.mark.parametrize("d,m,n", [(2, 10, 7), (2, 22, 9), (3, 22, 5), (2, 52, 11), (2, 178, 20),
+                                   (2, 400, 3), (2, 1251, 2)])
+def test_bluestein_sine_cores(d, m, n):
+    """Sine lengths 2(m+1) with a prime factor above 7 take the Bluestein sine passes on the
+    power-of-two engine; these grids use the cores 64, 128 (2D and 3D), 256, 1024, 2048 and
+    4096 (P >= 3(m+1) - 1), every level compared with the closed form."""
+    say(f"[case] bluestein sine d={d} m={m} n={n}")
+    alpha = 1e-4
+    g = np.random.default_rng(m + d).standard_normal((m,) * d)
+    p = qbvm.Plan(d, m, n, 1.0, 1.0)
+    y = p.solve(alpha, 0, to_dev(g))
+    torch.cuda.synchronize()
+    assert rel(y.cpu().numpy(), O.closed_form(g, d, m, n, 1.0, 1.0, alpha, O.PQ)) < TOL
     p.close()
 
 
