@@ -95,7 +95,7 @@ inline bool dst_pairs_aligned(const DstArgs& a) {
 
 // Good-Thomas time kernels (N_t = A * B, gcd 1, B an odd prime): S = 64 signals per
 // workgroup (A waves); the B-point outputs are exchanged in chunks of KC symmetric
-// pairs, variant 0: KC = 7, variant 1: KC = 11.
+// pairs (KC = 7 for the even variants, 5 for the odd ones).
 constexpr int kGtPairs[][2] = {{3, 43}};
 constexpr bool gt_supported(int A, int B) {
   for (const auto& p : kGtPairs)
@@ -139,12 +139,12 @@ constexpr bool plane_valid(int N, int V) {
 }
 
 // Bluestein sine pass on a power-of-two core of P points (64 .. 4096, P >= 3N/2 - 1 for the
-// sine length N): E = 16 values per lane, 128 lanes (256 for P = 4096), S = T E / P
+// sine length N): E = 16 values per lane, 128 lanes (256 from P = 1024), S = T E / P
 // signals (2S lines) per workgroup.  LDS: the exchange buffer ([signal][position],
 // XOR-mapped), then for P <= 1024 the twiddle table; the staged input and output lines
 // (2S m doubles, m < P/3) reuse the exchange buffer.
 constexpr int kBlueE = 16;
-constexpr int blue_T(int P) { return P >= 4096 ? 256 : 128; }
+constexpr int blue_T(int P) { return P >= 1024 ? 256 : 128; }
 constexpr int blue_S(int P) { return blue_T(P) * kBlueE / P; }
 constexpr int blue_tw_mode(int P) { return P <= 1024 ? 1 : 0; }
 constexpr size_t blue_lds(int P) {
