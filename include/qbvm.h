@@ -58,12 +58,11 @@ extern "C" {
 #define QBVM_OUT_Y0  1 /* the reconstruction y^0 only: m^d doubles (Section 5) */
 #define QBVM_OUT_YN  2 /* the final level y^N only: m^d doubles              */
 
-/* Size limits of this build.  Within them, a transform length whose FFT core (Rader
- * on n-1, or Bluestein on a 7-smooth length >= 2n-1, for lengths with a prime factor
- * above 47) would exceed 4096 points is refused with QBVM_EUNSUPPORTED: the time length
- * n+1 at plan creation; the sine length 2(m+1) at plan creation for d >= 2, and in 1D by
- * the calls that work in the sine basis (qbvm_solve_general, qbvm_discrepancy,
- * qbvm_choose_alpha, qbvm_bisect_batched, qbvm_features) while qbvm_solve still works. */
+/* Size limits of this build.  Within them, a time length n+1 whose FFT core (Rader on n,
+ * or Bluestein on a 7-smooth length >= 2(n+1)-1, for lengths with a prime factor above 47)
+ * would exceed 4096 points is refused with QBVM_EUNSUPPORTED at plan creation.  Every
+ * sine length 2(m+1) within the limits has a transform (its Bluestein form needs a
+ * power-of-two core >= 2m+1 only). */
 #define QBVM_MAX_NT      4096  /* n + 1, d = 1 */
 #define QBVM_MAX_NT_MD   2048  /* n + 1, d = 2, 3 (one time signal and its tables fit in LDS) */
 #define QBVM_MAX_M_1D    2047  /* the sine transform of g (length 2(m+1)) serves 1D too */

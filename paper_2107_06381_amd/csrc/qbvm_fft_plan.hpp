@@ -137,22 +137,27 @@ inline void fill_stages(FftPlanDev& d, int nc) {
 }
 
 // Tables of a forward DFT of logical length n; returns false (with a message) if
-// the core transform would exceed what one workgroup handles.  pow2_blue: a length
-// that takes Bluestein's path gets a power-of-two core (up to 4096), for the
-// compile-time Bluestein kernels, instead of the shortest 7-smooth one.  nout: only
-// outputs 0..nout-1 are wanted (a sine transform needs the first half); Bluestein's
-// cyclic convolution then needs a core of n + nout - 1 points, not 2n - 1.
-inline bool build_tables(int n, HostFft& t, std::string& err, bool pow2_blue = false, int nout = 0) {
+// the core transform would exceed what one workgroup handles.  sine: the DFT of a sine
+// transform's odd extension (n = 2(m+1), input x_{n-j} = -x_j with x_0 = x_{n/2} = 0, only
+// outputs 1..n/2-1 used).  A sine length that takes Bluestein's path gets the symmetric
+// form run by the compile-time sine kernel (`bp2`): with h = n/2 and w_t = exp(i pi t^2/n),
+// the chirp-weighted input a_j = x_j conj(w_j) obeys a_{j+h} = -a_{h-j}, so the inputs
+// j >= h are the negated mirror image of the first half and their transform is the first
+// half's at -k times exp(-2 pi i k h/P).  The convolution then runs over inputs j < h and
+// outputs k < h only, on a power-of-two core P >= n - 1 (64..4096), with two kernel
+// spectra: kspec[k] for the first half and kspec[P + k] (the phase and the sign folded
+// in) for the mirrored one.  No other kernel reads these tables.
+inline bool build_tables(int n, HostFft& t, std::string& err, bool sine = false) {
   FftPlanDev& d = t.dev;
   d.n = n;
-  if (nout <= 0 || nout > n) nout = n;
-  d.nout = nout;
+  const bool sym = sine && n % 2 == 0;
+  int symP = 64;
+  while (symP < n - 1) symP *= 2;
   // Prefer cores whose radices are all <= 7 (the narrow kernels keep a butterfly in
   // registers without spilling): Stockham, Rader on n - 1, else Bluestein if its core
   // fits; only lengths beyond that use the wide kernels (odd radices up to 47).
   int nc;
-  const int need = n + nout - 1;  // Bluestein's convolution length
-  int blue = need;
+  int blue = 2 * n - 1;
   while (!smooth(blue, kMaxOddRadixNarrow)) ++blue;
   if (smooth(n, kMaxOddRadixNarrow)) {
     d.kind = kStockham;
@@ -160,14 +165,12 @@ inline bool build_tables(int n, HostFft& t, std::string& err, bool pow2_blue = f
   } else if (is_prime(n) && smooth(n - 1, kMaxOddRadixNarrow)) {
     d.kind = kRader;
     nc = n - 1;
+  } else if (sym && symP <= kMaxCore) {
+    d.kind = kBluestein;
+    nc = symP;
   } else if (blue <= kMaxCore) {
     d.kind = kBluestein;
     nc = blue;
-    if (pow2_blue) {
-      int P = 64;
-      while (P < need) P *= 2;
-      if (P <= kMaxCore) nc = P;
-    }
   } else if (smooth(n, kMaxOddRadixWide)) {
     d.kind = kStockham;
     nc = n;
@@ -220,22 +223,43 @@ inline bool build_tables(int n, HostFft& t, std::string& err, bool pow2_blue = f
     }
     t.kspec = dft_over_len(bb);
   } else if (d.kind == kBluestein) {
-    // kernel b_t = w_t at the offsets t = k - j of the wanted outputs k < nout and the
-    // inputs j < n: t in [0, nout) at positions t, t in [1, n) at nc - t (w_t = w_{-t});
-    // nc >= n + nout - 1 keeps the two ranges apart
     t.chirp.resize(n);
-    std::vector<std::complex<long double>> bb(nc, 0);
+    std::vector<std::complex<long double>> w(n);  // w_t = w_{-t}, t < n
     for (long long k = 0; k < n; ++k) {
       const long long e2 = (k * k) % (2LL * n);
-      const std::complex<long double> w = unit_root(e2, 2LL * n, +1);  // exp(i pi k^2/n)
-      t.chirp[k] = {(double)w.real(), (double)w.imag()};
-      if (k < nout) bb[k] = w;
-      if (k > 0) bb[nc - k] = w;
+      w[k] = unit_root(e2, 2LL * n, +1);  // exp(i pi k^2/n)
+      t.chirp[k] = {(double)w[k].real(), (double)w[k].imag()};
     }
-    t.kspec = dft_over_len(bb);
+    auto wt = [&](long long x) { return w[x < 0 ? -x : x]; };
+    if (sym && nc == symP) {
+      // offsets s = k - j in [-(h-1), h-1] of outputs k < h and inputs j < h; the first
+      // half's kernel is w_s, the mirrored half's w_{s-h}
+      const long long h = n / 2, P = nc;
+      std::vector<std::complex<long double>> blo(P, 0), bhi(P, 0);
+      for (long long x = -(h - 1); x <= h - 1; ++x) {
+        blo[(x + P) % P] = wt(x);
+        bhi[(x + P) % P] = wt(x - h);
+      }
+      const std::vector<c64> Blo = dft_over_len(blo), Bhi = dft_over_len(bhi);
+      t.kspec.resize(2 * P);
+      for (long long k = 0; k < P; ++k) {
+        t.kspec[k] = Blo[k];
+        const std::complex<long double> ph = -unit_root(k * h, P, -1);
+        const std::complex<long double> v = ph * std::complex<long double>(Bhi[k].re, Bhi[k].im);
+        t.kspec[P + k] = {(double)v.real(), (double)v.imag()};
+      }
+    } else {
+      // kernel b_t = w_t at offsets t in (-n, n): t >= 0 at position t, t < 0 at nc + t
+      std::vector<std::complex<long double>> bb(nc, 0);
+      for (long long k = 0; k < n; ++k) {
+        bb[k] = w[k];
+        if (k > 0) bb[nc - k] = w[k];
+      }
+      t.kspec = dft_over_len(bb);
+    }
   }
   d.p2 = (d.kind != kBluestein && is_p2_core(nc)) ? nc : 0;
-  d.bp2 = (d.kind == kBluestein && is_p2_core(nc) && nc >= need) ? nc : 0;
+  d.bp2 = (d.kind == kBluestein && sym && nc == symP) ? nc : 0;
   d.gtA = d.gtB = 0;
   for (const auto& pr : p2sz::kGtPairs)
     if (pr[0] * pr[1] == n) {

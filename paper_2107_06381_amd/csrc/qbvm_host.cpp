@@ -67,7 +67,7 @@ hipError_t upload(const std::vector<T>& v, const T** dst, std::vector<void*>& al
 int build_fft(int n, FftTables& t, bool sine) {
   plan::HostFft h;
   std::string err;
-  if (!plan::build_tables(n, h, err, sine, sine ? n / 2 : 0)) return set_error(QBVM_EUNSUPPORTED, err);
+  if (!plan::build_tables(n, h, err, sine)) return set_error(QBVM_EUNSUPPORTED, err);
   t.dev = h.dev;
   FftPlanDev& d = t.dev;
   HIP_TRY(upload(h.tw, &d.tw, t.allocs));
@@ -86,9 +86,8 @@ std::map<std::tuple<int, int, bool>, std::unique_ptr<FftTables>> g_fft_cache;  /
 std::map<std::tuple<int, int, int>, int> g_tuned;
 std::map<int, bool> g_roots_ready;
 
-// sine: tables of a sine transform's length-n DFT (n = 2(m+1)), of which only outputs
-// 0..n/2-1 are used; a Bluestein length gets a power-of-two core for the compile-time
-// Bluestein sine passes
+// sine: tables of a sine transform's length-n DFT (n = 2(m+1)); a Bluestein length gets
+// the symmetric form of the compile-time Bluestein sine passes
 int get_fft(int device, int n, const FftTables** out, bool sine = false) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_roots_ready[device]) {

@@ -44,8 +44,8 @@ struct FftPlanDev {
   const int* ginvt;  // Rader: ginvt[p] = g^{-p} mod n, p < n-1
   int p2;            // core length if it has a compile-time power-of-two kernel (64..4096), else 0
   int gtA, gtB;      // n = gtA * gtB handled by the compile-time Good-Thomas time kernel (else 0)
-  int bp2;           // Bluestein whose core nc is a power of two with a compile-time kernel (else 0)
-  int nout;          // outputs 0..nout-1 are computed (n, or a sine transform's first half)
+  int bp2;           // sine tables in the symmetric Bluestein form of the compile-time sine
+                     // kernel: its power-of-two core (kspec holds 2 bp2 values), else 0
 };
 
 // Per-solve scalars derived from (alpha, variant, tau).

@@ -63,9 +63,11 @@ DST_VARIANTS = [(0, 1, 0), (1, 0, 1), (3, 4, 0), (4, 3, 1), (5, 6, 0), (6, 5, 0)
 DST_QUICK = [((1, 9, 3), (0, 1, 0)), ((2, 13, 2), (1, 0, 1)), ((3, 6, 2), (3, 4, 0)), ((2, 31, 3), (5, 6, 0)),
              ((2, 127, 2), (6, 5, 0)), ((2, 255, 1), (3, 4, 0)), ((2, 511, 1), (4, 3, 1)), ((2, 1023, 1), (1, 0, 1)),
              ((1, 2047, 5), (0, 1, 0)), ((2, 100, 1), (1, 0, 0)), ((3, 63, 1), (7, 7, 1)),
-             # Bluestein sine passes on power-of-two cores 64, 128 (3D), 1024, 2048 and 4096
-             ((1, 10, 3), (0, 1, 0)), ((3, 22, 1), (0, 1, 0)), ((2, 178, 1), (0, 1, 0)),
-             ((1, 400, 3), (0, 1, 0)), ((1, 1251, 2), (0, 1, 0))]
+             # Bluestein sine passes (symmetric form) on power-of-two cores 64 (1D, 3D), 128,
+             # 512, 1024, 2048 and 4096
+             ((1, 10, 3), (0, 1, 0)), ((3, 22, 1), (0, 1, 0)), ((1, 52, 2), (0, 1, 0)),
+             ((2, 178, 1), (0, 1, 0)), ((1, 400, 3), (0, 1, 0)), ((1, 600, 2), (0, 1, 0)),
+             ((1, 1251, 2), (0, 1, 0))]
 DST_PARAMS = [(c, v) for c in DST_CASES for v in DST_VARIANTS] if FULL else DST_QUICK
 
 

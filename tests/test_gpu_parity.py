@@ -367,13 +367,14 @@ def test_operator_1d_vs_oracle(m, n, alpha, variant, adv):
     p.close()
 
 
-def test_1d_plan_without_sine_transform():
-    """1D m = 1400: the sine length 2(m+1) = 2802 = 2 * 3 * 467 needs a Bluestein core of
-    2802 + 1401 - 1 = 4202 > 4096 points even for the first half of its outputs.  The plan
-    still solves (tridiagonal path, every output mode); the calls that work in the sine
-    basis are refused."""
-    say("[case] 1d without sine transform")
-    m, n, alpha = 1400, 106, 1e-4
+@pytest.mark.parametrize("m", [1251, 1400])
+def test_1d_long_bluestein_sine_lengths(m):
+    """1D m = 1251 (2(m+1) = 8 * 313) and 1400 (2 * 3 * 467): sine lengths whose plain
+    Bluestein core (2N - 1 points and more) exceeds 4096; the symmetric form of the sine
+    kernel needs P >= N - 1, here 4096.  The solve (tridiagonal path, every output mode) and
+    the discrepancy, which works in the sine basis, match the oracle."""
+    say(f"[case] 1d long bluestein sine m={m}")
+    n, alpha = 106, 1e-4
     g = np.random.default_rng(12).standard_normal(m)
     p = qbvm.Plan(1, m, n, 1.0, 0.8)
     gd = to_dev(g)
@@ -382,20 +383,18 @@ def test_1d_plan_without_sine_transform():
     torch.cuda.synchronize()
     yc = O.closed_form(g, 1, m, n, 1.0, 0.8, alpha, O.PQ)
     assert rel(y.cpu().numpy(), yc) < TOL and rel(yn.cpu().numpy(), yc[-1]) < TOL
-    for call in (lambda: p.discrepancy(alpha, 0, gd),
-                 lambda: p.solve_general(alpha, 0, to_dev(np.zeros((n + 1, m))))):
-        with pytest.raises(qbvm.QbvmError) as ei:
-            call()
-        assert ei.value.code == -5
+    D = p.discrepancy(alpha, 0, gd)
+    Do = O.discrepancy(alpha, g, 1, m, n, 1.0, 0.8)
+    assert abs(D / Do - 1.0) < 1e-10
     p.close()
 
 
-@pytest.mark.parametrize("d,m,n", [(2, 10, 7), (2, 22, 9), (3, 22, 5), (2, 52, 11), (2, 178, 20),
-                                   (2, 400, 3), (2, 1251, 2)])
+@pytest.mark.parametrize("d,m,n", [(2, 10, 7), (2, 22, 9), (3, 22, 5), (2, 52, 11), (2, 100, 6),
+                                   (2, 178, 20), (2, 400, 3), (2, 600, 2), (2, 1251, 2)])
 def test_bluestein_sine_cores(d, m, n):
-    """Sine lengths 2(m+1) with a prime factor above 7 take the Bluestein sine passes on the
-    power-of-two engine; these grids use the cores 64, 128 (2D and 3D), 256, 1024, 2048 and
-    4096 (P >= 3(m+1) - 1), every level compared with the closed form."""
+    """Sine lengths N = 2(m+1) with a prime factor above 7 take the Bluestein sine passes on
+    the power-of-two engine (symmetric form, P >= N - 1); these grids use every core from
+    64 (2D and 3D) to 4096, every level compared with the closed form."""
     say(f"[case] bluestein sine d={d} m={m} n={n}")
     alpha = 1e-4
     g = np.random.default_rng(m + d).standard_normal((m,) * d)
