@@ -139,12 +139,12 @@ constexpr bool plane_valid(int N, int V) {
 }
 
 // Bluestein sine pass on a power-of-two core of P points (64 .. 4096, P >= N - 1 for the
-// sine length N, symmetric form): E = 16 values per lane, 128 lanes (256 from P = 1024), S = T E / P
+// sine length N, symmetric form): E = 8 values per lane, 256 lanes (512 from P = 1024), S = T E / P
 // signals (2S lines) per workgroup.  LDS: the exchange buffer ([signal][position],
 // XOR-mapped), then for P <= 1024 the twiddle table; the staged input and output lines
 // (2S m doubles, m < P/2) reuse the exchange buffer.
-constexpr int kBlueE = 16;
-constexpr int blue_T(int P) { return P >= 1024 ? 256 : 128; }
+constexpr int kBlueE = 8;
+constexpr int blue_T(int P) { return P >= 1024 ? 512 : 256; }
 constexpr int blue_S(int P) { return blue_T(P) * kBlueE / P; }
 constexpr int blue_tw_mode(int P) { return P <= 1024 ? 1 : 0; }
 constexpr size_t blue_lds(int P) {
