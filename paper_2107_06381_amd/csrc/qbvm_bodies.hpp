@@ -3,6 +3,8 @@
 // gfx950 kernels and, with a thin shim, by the CPU build used in the tests.
 #pragma once
 
+#include <type_traits>
+
 #include "qbvm_fft_dev.hpp"
 
 namespace qbvm {
@@ -286,34 +288,45 @@ __device__ __forceinline__ void time_body(const TimeArgs& a, long long wg, c64* 
   }
   const c64* tw = stage_twiddles(a.fft, a.tw_lds, reinterpret_cast<c64*>(gh + 2 * S));
   __syncthreads();
-  // Steps (a)+(b): u_j = g_a/(d_j/tau + mu_a) + i g_b/(d_j/tau + mu_b)
+  // Steps (a)+(b): u_j = g_a/(d_j/tau + mu_a) + i g_b/(d_j/tau + mu_b); for a Bluestein
+  // length the chirp weight conj(w_j) is applied here and the core beyond N_t is zeroed
+  // (the engine's separate pre-processing pass is not needed)
   const int T = blockDim.x;
   LaneWalk w(S);
-  for (int e0 = threadIdx.x; e0 < S * Nt; e0 += kBatch * T) {
-    int pv[kBatch], jv[kBatch], sv[kBatch];
+  auto place = [&](auto blue_tag) {
+    constexpr bool BLUE = decltype(blue_tag)::value;
+    for (int e0 = threadIdx.x; e0 < S * Nt; e0 += kBatch * T) {
+      int pv[kBatch], jv[kBatch], sv[kBatch];
+      c64 cw[kBatch];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      jv[u] = w.j;
-      sv[u] = w.s;
-      pv[u] = fft_in_pos(a.fft, min(w.j, Nt - 1));
-      w.next();
-    }
+      for (int u = 0; u < kBatch; ++u) {
+        jv[u] = w.j;
+        sv[u] = w.s;
+        pv[u] = fft_in_pos(a.fft, min(w.j, Nt - 1));
+        if constexpr (BLUE) cw[u] = cconj(a.fft.chirp[min(w.j, Nt - 1)]);
+        w.next();
+      }
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      if (e0 + u * T >= S * Nt) continue;
-      const int j = jv[u], s = sv[u];
-      const c64 z = dt[j];
-      const double xa = z.re + mus[2 * s], xb = z.re + mus[2 * s + 1];
-      const double ia = gh[2 * s] / (xa * xa + z.im * z.im);
-      const double ib = gh[2 * s + 1] / (xb * xb + z.im * z.im);
-      // A = ia (xa - i z.im), B = ib (xb - i z.im); u = A + i B
-      const c64 uu = {ia * xa + ib * z.im, ib * xb - ia * z.im};
-      if (pv[u] < 0) side[s] = uu;
-      else buf[(size_t)pv[u] * S + s] = uu;
+      for (int u = 0; u < kBatch; ++u) {
+        if (e0 + u * T >= S * Nt) continue;
+        const int j = jv[u], s = sv[u];
+        const c64 z = dt[j];
+        const double xa = z.re + mus[2 * s], xb = z.re + mus[2 * s + 1];
+        const double ia = gh[2 * s] / (xa * xa + z.im * z.im);
+        const double ib = gh[2 * s + 1] / (xb * xb + z.im * z.im);
+        // A = ia (xa - i z.im), B = ib (xb - i z.im); u = A + i B
+        c64 uu = {ia * xa + ib * z.im, ib * xb - ia * z.im};
+        if constexpr (BLUE) uu = cmul(uu, cw[u]);
+        if (pv[u] < 0) side[s] = uu;
+        else buf[(size_t)pv[u] * S + s] = uu;
+      }
     }
-  }
+    if constexpr (BLUE)
+      for (int e = threadIdx.x; e < S * (nc - Nt); e += T) buf[(size_t)S * Nt + e] = {0.0, 0.0};
+  };
+  if (a.fft.kind == kBluestein) place(std::true_type{});
+  else place(std::false_type{});
   __syncthreads();
-  if (a.fft.kind == kBluestein) fft_bluestein_prep(buf, S, a.fft);
   fft_run<WIDE>(buf, S, a.fft, side, tw);
   // Step (c): gamma_l^{-1}/N_t * X_l; real part -> mode a, imaginary part -> mode b
   const int tot = S * a.lev_count;

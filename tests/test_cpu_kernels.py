@@ -91,6 +91,8 @@ SOLVE_CASES = [
     (1, 7, 6, 1e-2, 0), (1, 127, 128, 1e-3, 0), (1, 33, 40, 1e-6, 1), (1, 64, 63, 1e-6, 0),
     (2, 5, 4, 1e-3, 0), (2, 15, 16, 1e-4, 1), (2, 20, 11, 1e-2, 0), (2, 31, 100, 1e-8, 0),
     (3, 4, 5, 1e-3, 0), (3, 9, 8, 1e-5, 1), (2, 1, 1, 0.5, 0), (1, 1, 3, 0.1, 1),
+    # Bluestein time lengths on the runtime engine: N_t = 23 (2D), 47 (3D)
+    (2, 12, 22, 1e-3, 0), (3, 6, 46, 1e-4, 1),
     # power-of-two time kernels: N_t = 64, 128, 256 (Stockham) and 257 (Rader on 256)
     (2, 63, 63, 1e-4, 0), (3, 15, 127, 1e-3, 1), (2, 20, 255, 1e-6, 0), (2, 33, 256, 1e-4, 0),
     (2, 255, 6, 1e-3, 0),
