@@ -62,11 +62,11 @@ struct Tables {
   FftPlanDev dev;
 };
 
-// sine: the tables of a sine transform (outputs 0..n/2-1, power-of-two Bluestein core)
+// sine: the tables of a sine transform (symmetric Bluestein form for the compile-time kernel)
 static Tables make_tables(int n, bool sine = false) {
   Tables t;
   std::string err;
-  if (!plan::build_tables(n, t.h, err, sine, sine ? n / 2 : 0)) {
+  if (!plan::build_tables(n, t.h, err, sine)) {
     fprintf(stderr, "plan failed: %s\n", err.c_str());
     exit(3);
   }
