@@ -169,8 +169,20 @@ inline bool build_tables(int n, HostFft& t, std::string& err, bool sine = false)
     d.kind = kBluestein;
     nc = symP;
   } else if (blue <= kMaxCore) {
+    // Bluestein core: the 7-smooth length >= 2n - 1 with the fewest element-stages
+    // (length x number of Stockham stages), since the engine's cost per stage is mostly
+    // one LDS round trip per element: 640 = 16.8.5 (3 stages) beats 625 = 5^4 (4)
     d.kind = kBluestein;
     nc = blue;
+    long long best = (long long)blue * (long long)radices(blue).size();
+    for (int c = blue + 1; c < 2 * blue && c <= kMaxCore; ++c) {
+      if (!smooth(c, kMaxOddRadixNarrow)) continue;
+      const long long cost = (long long)c * (long long)radices(c).size();
+      if (cost < best) {
+        best = cost;
+        nc = c;
+      }
+    }
   } else if (smooth(n, kMaxOddRadixWide)) {
     d.kind = kStockham;
     nc = n;
