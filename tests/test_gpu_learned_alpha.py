@@ -3,7 +3,7 @@ forward/backward/Adam kernels, the discrepancy window with bisection as fallback
 and what the trained network gains over the method without it.
 
 Parity of the network kernels themselves against the FP64 reference is in
-test_gpu_parity.py; here the trained predictor is judged by the discrepancy
+test_gpu_parity.py; here the trained predictor is evaluated by the discrepancy
 principle it imitates (labels: alpha_DP from the batched bisection).  The
 quality figures have no published counterpart ("parity unpinned").
 """
